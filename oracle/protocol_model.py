@@ -1,0 +1,193 @@
+"""Explicit-state model of the queue-pair protocol (TEST INFRASTRUCTURE).
+
+Two small models are explored exhaustively (every interleaving of atomic steps) for
+tiny queue depths and thread counts:
+
+* ``agile``: submitters never touch completion queues.  A submitting wave reserves its
+  tickets with one atomic, writes each command into its slot once the slot's previous
+  lap is EMPTY, marks it UPDATED, and rings the doorbell by scanning UPDATED slots in
+  order and marking them ISSUED (Sec. 3.3.1, Alg. 2).  An emulated controller fetches
+  issued commands, may complete them in any order, and posts phase-tagged completion
+  entries when the completion queue has room.  A separate completion service checks a
+  window of entries against the expected phase, frees each command's slot for the next
+  lap, and advances the completion head when the window is full (Sec. 3.2, Alg. 1).
+* ``naive``: the design of Fig. 1 (Sec. 2.3.1): a submitter holds each slot it filled
+  until it has itself consumed the matching completion, and it spins for a free slot
+  before it ever looks at the completion queue.
+
+``explore`` returns the number of reachable states and the first deadlocked state found
+(a state where some thread has not finished and no step is enabled).  The agile model
+must have none; the naive model must reach one (the Fig. 1 scenario) once the threads
+together want more slots than the queue holds.
+
+``agile_ring_last`` is ``agile`` with one change: a wave rings the doorbell only after
+all of its commands are written.  The search shows that this variant deadlocks when a
+wave's later command needs the slot of one of its own earlier commands, which is why
+the submission loop rings while it still waits for slots.
+"""
+from __future__ import annotations
+
+from collections import deque
+
+EMPTY, UPDATED, ISSUED = 0, 1, 2
+
+
+def _agile_init(depth, window, reqs):
+    slots = tuple((s, EMPTY) for s in range(depth))
+    cq = tuple((0, -1) for _ in range(depth))  # (phase bit in memory, cid)
+    threads = tuple((0, -1, 0) for _ in reqs)  # (pc, base ticket, written mask)
+    # ticket, db, head, inflight(frozenset of slot), cq_tail, cq_head, offset, mask, done
+    return (0, 0, 0, frozenset(), 0, 0, 0, 0, frozenset(), slots, cq, threads)
+
+
+def _agile_succ(state, depth, window, reqs, ring_early=True):
+    (ticket, db, head, infl, cq_tail, cq_head, off, mask, done, slots, cq, threads) = state
+    out = []
+    for t, (pc, base, wr) in enumerate(threads):
+        n = reqs[t]
+        if pc == 0:  # one atomic reservation for the whole wave
+            th = list(threads)
+            th[t] = (1, ticket, 0)
+            out.append((ticket + n, db, head, infl, cq_tail, cq_head, off, mask, done, slots, cq,
+                        tuple(th)))
+        elif pc == 1:
+            for i in range(n):
+                if wr >> i & 1:
+                    continue
+                T = base + i
+                s = T % depth
+                if slots[s] == (T, EMPTY):
+                    sl = list(slots)
+                    sl[s] = (T, UPDATED)
+                    nwr = wr | (1 << i)
+                    th = list(threads)
+                    th[t] = (2 if nwr == (1 << n) - 1 else 1, base, nwr)
+                    out.append((ticket, db, head, infl, cq_tail, cq_head, off, mask, done,
+                                tuple(sl), cq, tuple(th)))
+        if pc == 2 or (pc == 1 and ring_early):
+            # a wave rings for what it has written while it still waits for slots of
+            # its own later commands (ringing only after all writes can deadlock)
+            p = db
+            sl = list(slots)
+            while sl[p % depth] == (p, UPDATED):
+                sl[p % depth] = (p, ISSUED)
+                p += 1
+            if p != db:
+                out.append((ticket, p, head, infl, cq_tail, cq_head, off, mask, done,
+                            tuple(sl), cq, threads))
+        if pc == 2:
+            if db >= base + n:
+                th = list(threads)
+                th[t] = (3, base, wr)
+                out.append((ticket, db, head, infl, cq_tail, cq_head, off, mask, done, slots,
+                            cq, tuple(th)))
+        elif pc == 3:
+            if all((base + i) in done for i in range(n)):
+                th = list(threads)
+                th[t] = (4, base, wr)
+                out.append((ticket, db, head, infl, cq_tail, cq_head, off, mask, done, slots,
+                            cq, tuple(th)))
+    # controller: fetch
+    if head < db:
+        out.append((ticket, db, head + 1, infl | {head % depth}, cq_tail, cq_head, off, mask,
+                    done, slots, cq, threads))
+    # controller: complete any fetched command (out of order) when the CQ has room
+    if cq_tail - cq_head < depth:
+        for s in infl:
+            c = list(cq)
+            phase = ((cq_tail // depth) & 1) ^ 1
+            c[cq_tail % depth] = (phase, s)
+            out.append((ticket, db, head, infl - {s}, cq_tail + 1, cq_head, off, mask, done,
+                        slots, tuple(c), threads))
+    # completion service lanes
+    for i in range(window):
+        if mask >> i & 1:
+            continue
+        pos = off + i
+        exp = ((pos // depth) & 1) ^ 1
+        ph, cid = cq[pos % depth]
+        if ph == exp:
+            T, st = slots[cid]
+            assert st == ISSUED, "completion for a slot that was not issued"
+            assert T not in done, "command completed twice"
+            sl = list(slots)
+            sl[cid] = (T + depth, EMPTY)
+            out.append((ticket, db, head, infl, cq_tail, cq_head, off, mask | (1 << i),
+                        done | {T}, tuple(sl), cq, threads))
+    if mask == (1 << window) - 1:
+        out.append((ticket, db, head, infl, cq_tail, off + window, off + window, 0, done, slots,
+                    cq, threads))
+    return out
+
+
+def _agile_finished(state):
+    return all(pc == 4 for pc, _, _ in state[-1])
+
+
+def _naive_init(depth, reqs):
+    slots = tuple(-1 for _ in range(depth))  # owner thread or -1
+    threads = tuple((0, 0, frozenset()) for _ in reqs)  # (pc, issued count, held slots)
+    return (0, frozenset(), frozenset(), slots, threads)  # db-less: (dummy, inflight, posted)
+
+
+def _naive_succ(state, depth, reqs):
+    (_, infl, posted, slots, threads) = state
+    out = []
+    for t, (pc, k, held) in enumerate(threads):
+        n = reqs[t]
+        if pc == 0:  # need a free SQE for request k (spins while the SQ is full)
+            for s in range(depth):
+                if slots[s] == -1:
+                    sl = list(slots)
+                    sl[s] = t
+                    th = list(threads)
+                    th[t] = (1 if k + 1 == n else 0, k + 1, held | {s})
+                    out.append((0, infl | {s}, posted, tuple(sl), tuple(th)))
+                    break
+        elif pc == 1:  # consume own completions, releasing the held SQEs
+            for s in held:
+                if s in posted:
+                    sl = list(slots)
+                    sl[s] = -1
+                    nh = held - {s}
+                    th = list(threads)
+                    th[t] = (2 if not nh else 1, k, nh)
+                    out.append((0, infl, posted - {s}, tuple(sl), tuple(th)))
+    for s in infl:
+        out.append((0, infl - {s}, posted | {s}, slots, threads))
+    return out
+
+
+def _naive_finished(state):
+    return all(pc == 2 for pc, _, _ in state[-1])
+
+
+def explore(model: str, depth: int, reqs, window: int = None, limit: int = 2_000_000):
+    """Breadth-first search of all interleavings.  Returns (states, deadlock or None)."""
+    if model in ("agile", "agile_ring_last"):
+        window = window or depth
+        assert depth % window == 0
+        start = _agile_init(depth, window, reqs)
+        early = model == "agile"
+        succ = lambda s: _agile_succ(s, depth, window, reqs, early)  # noqa: E731
+        fin = _agile_finished
+    elif model == "naive":
+        start = _naive_init(depth, reqs)
+        succ = lambda s: _naive_succ(s, depth, reqs)  # noqa: E731
+        fin = _naive_finished
+    else:
+        raise ValueError(model)
+    seen = {start}
+    q = deque([start])
+    while q:
+        s = q.popleft()
+        nxt = succ(s)
+        if not nxt and not fin(s):
+            return len(seen), s
+        for n in nxt:
+            if n not in seen:
+                seen.add(n)
+                if len(seen) > limit:
+                    raise RuntimeError("state limit exceeded")
+                q.append(n)
+    return len(seen), None
