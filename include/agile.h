@@ -1,0 +1,235 @@
+/*
+ * agile.h - C ABI of an MI355X (gfx950) library for GPU-initiated asynchronous block
+ * reads through NVMe-style submission/completion queue pairs into a set-associative
+ * HBM software cache (AGILE, arXiv 2504.19365).
+ *
+ * Model.  A store is a byte image of 4 KiB blocks in host-pinned memory.  It sits
+ * behind an emulated NVMe controller that runs as GPU service wavefronts: they fetch
+ * commands from submission queues (SQ) after their doorbell moves, hold each command
+ * for a configurable latency and an IOPS cap, copy the block across PCIe into its HBM
+ * cache line (or back, for write-back) and post a phase-tagged completion entry (CQE)
+ * (Sec. 2.1).  Completion-service wavefronts consume CQEs and free SQ slots, so user
+ * waves never process completions (Sec. 3.2, Alg. 1).  User waves coalesce duplicate
+ * requests within a wavefront, probe the cache, and submit misses with one atomic per
+ * wavefront, serialising the doorbell as in Sec. 3.3.1 / Alg. 2.  Cache lines follow
+ * the INVALID / BUSY / READY / MODIFIED states of Sec. 3.4 with clock replacement.
+ *
+ * Every kernel this library launches carries its own service wavefronts as its first
+ * workgroups, so the queues make progress during every launch without relying on two
+ * kernels running side by side.  Calls on one context must not overlap in time (the
+ * library is not thread-safe per context; use one stream per context).
+ *
+ * Conventions.  Every function returns agile_status (0 = AGILE_OK, < 0 error).
+ * "Device pointer" means memory the GPU can dereference (hipMalloc or torch CUDA
+ * tensors); "stream" is a hipStream_t passed as void* (NULL = default stream).
+ * Calls that launch work are stream-ordered and return at once; errors raised on the
+ * device latch into a sticky error word that the next blocking call (agile_wait,
+ * agile_flush, agile_sync, agile_close_store) returns.  After a sticky error the
+ * context accepts only agile_get_stats, agile_last_error and agile_shutdown.
+ */
+#ifndef AGILE_H
+#define AGILE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum agile_status {
+  AGILE_OK = 0,
+  AGILE_EINVAL = -1,    /* bad argument or configuration; nothing was launched */
+  AGILE_ENOMEM = -2,    /* device or pinned host allocation failed */
+  AGILE_EHIP = -3,      /* a HIP runtime call failed */
+  AGILE_ETIMEDOUT = -4, /* a device wait exceeded timeout_ns (watchdog) */
+  AGILE_EAGAIN = -5,    /* a ticket found no evictable way in its set; retry later */
+  AGILE_EIO = -6,       /* a command completed with an error status */
+  AGILE_EPROTO = -7,    /* queue-protocol violation detected on the device */
+  AGILE_ESTATE = -8     /* call not allowed in the current state */
+} agile_status;
+
+typedef struct agile_ctx_s* agile_ctx;
+typedef struct agile_store_s* agile_store;
+
+/* A ticket names one pinned cache line: bits 0-31 line index, 32-39 generation,
+ * 40-47 status (0 = ok, 1 = EAGAIN, 2 = not issued), 48-63 byte offset of the block
+ * within the line divided by 4096.  Tickets live in device memory. */
+typedef uint64_t agile_ticket;
+
+/* agile_config.flags */
+#define AGILE_F_SERIALIZED 0x1u /* workloads run one request at a time on one lane */
+#define AGILE_F_NO_PRIO 0x2u    /* do not raise the service wavefronts' issue priority */
+
+typedef struct agile_config {
+  uint32_t struct_size;  /* sizeof(agile_config) */
+  int32_t device;        /* HIP device ordinal */
+  uint64_t cache_bytes;  /* HBM software-cache capacity; multiple of line_bytes */
+  uint32_t line_bytes;   /* 4096 << k; a line holds line_bytes/4096 consecutive blocks */
+  uint32_t assoc;        /* ways per set; (cache_bytes / line_bytes) % assoc == 0 */
+  uint32_t num_qp;       /* queue pairs, 1..1024 */
+  uint32_t qp_depth;     /* entries per SQ and per CQ: power of two in [64, 65536] */
+  uint32_t ctrl_waves;   /* emulated-controller wavefronts (0 = num_qp) */
+  uint32_t cq_waves;     /* completion-service wavefronts (0 = ceil(num_qp / 8)) */
+  uint32_t max_user_waves; /* cap on user wavefronts per launch (0 = fill the GPU) */
+  uint64_t latency_ns;   /* emulated per-command latency, fetch to completion */
+  uint64_t iops_cap;     /* emulated commands per second over the store (0 = none) */
+  uint64_t timeout_ns;   /* device watchdog for every wait (0 = 10 s) */
+  uint32_t flags;        /* AGILE_F_* */
+  uint32_t reserved;
+} agile_config;
+
+/* Fills a configuration with defaults (1 MiB cache of 4 KiB lines, 8-way, 1 QP of 64
+ * entries, no latency, no cap).  Always succeeds. */
+void agile_config_default(agile_config* cfg);
+
+/* Roughly AGILE_HOST + initializeAgile + startAgile of Listing 1 (Sec. 3.5): selects the
+ * device and allocates the cache lines, per-line metadata, clock hands, SQ/CQ rings,
+ * slot states, counters and the error word in HBM.  Validates cfg first and returns
+ * AGILE_EINVAL without touching the GPU when it is inconsistent.  Owns everything it
+ * allocates; release with agile_shutdown. */
+agile_status agile_init(const agile_config* cfg, agile_ctx* out);
+
+/* Roughly stopAgile: waits for the device to go idle and frees the context.
+ * Open stores are closed without a flush. */
+agile_status agile_shutdown(agile_ctx ctx);
+
+/* Pinned, device-mapped host memory for store images (hipHostMalloc).  The caller owns
+ * it and frees it with agile_host_free after closing any store on it. */
+agile_status agile_host_alloc(uint64_t bytes, void** out);
+agile_status agile_host_free(void* p);
+
+/* Roughly addNvmeDev + initNvme (Sec. 3.5): opens a store over `host_image`, which must
+ * be pinned host memory the device can map (agile_host_alloc or torch pin_memory) and
+ * stay valid until agile_close_store.  bytes must be a multiple of block_bytes, which
+ * must be 4096.  One store per context at a time (AGILE_ESTATE otherwise). */
+agile_status agile_open_store(agile_ctx ctx, void* host_image, uint64_t bytes,
+                              uint32_t block_bytes, uint32_t flags, agile_store* out);
+
+/* Roughly closeNvme: blocks until idle, invalidates the cache (dirty lines are NOT
+ * written back; call agile_flush first) and detaches the store.  Returns the sticky
+ * error, if any. */
+agile_status agile_close_store(agile_ctx ctx, agile_store store);
+
+/* prefetch() of Sec. 3.1 / Listing 1: for each of the n block ids in d_blocks (device
+ * uint64), coalesces duplicates within a wavefront, looks up the cache and, on a miss,
+ * claims a line and submits a READ.  Writes one ticket per block to d_tickets (device).
+ * Each successful ticket pins its line until agile_release; a ticket whose set has no
+ * evictable way carries status EAGAIN and pins nothing.  Stream-ordered; the reads
+ * complete during the launch (its service wavefronts drain every command). */
+agile_status agile_async_read(agile_ctx ctx, agile_store store, const uint64_t* d_blocks,
+                              uint32_t n, agile_ticket* d_tickets, void* stream);
+
+/* The barrier wait of Sec. 3.2 (Fig. 3) / AgileBufPtr::wait of Listing 1: waits until the
+ * line of every ticket is READY and writes the device address of each ticket's 4 KiB
+ * block to d_ptrs[i] (device; NULL for EAGAIN tickets).  Blocks the host until the
+ * stream is idle.  Returns the sticky error if any, else AGILE_EAGAIN if any ticket
+ * carried EAGAIN, else AGILE_OK. */
+agile_status agile_wait(agile_ctx ctx, const agile_ticket* d_tickets, uint32_t n, void** d_ptrs,
+                        void* stream);
+
+/* Unpins the lines of n tickets (EAGAIN tickets are skipped).  Stream-ordered. */
+agile_status agile_release(agile_ctx ctx, const agile_ticket* d_tickets, uint32_t n,
+                           void* stream);
+
+/* Writes every MODIFIED (dirty) line back to the store exactly once and leaves it clean
+ * (Sec. 3.4 case d).  Requires that no line is pinned.  Blocks until done and returns
+ * the sticky error, if any. */
+agile_status agile_flush(agile_ctx ctx, agile_store store, void* stream);
+
+/* Drops every clean, unpinned line (cold cache).  Dirty lines make it fail with
+ * AGILE_ESTATE (flush first).  Blocks until done. */
+agile_status agile_invalidate(agile_ctx ctx, agile_store store, void* stream);
+
+/* Blocks until the stream is idle and returns the sticky device error, if any. */
+agile_status agile_sync(agile_ctx ctx, void* stream);
+
+/* Counters; see agile_stats.  reset != 0 zeroes them after reading (blocking). */
+typedef struct agile_stats {
+  uint64_t requests;   /* lookups presented to the cache (a lookup whose prefetched
+                          chunk was dropped after an EAGAIN is presented again) */
+  uint64_t hits;       /* lookups served by a line resident or in flight at probe time */
+  uint64_t misses;     /* lookups whose wavefront issued the READ that filled the line */
+  uint64_t read_cmds;  /* READ commands submitted */
+  uint64_t write_cmds; /* WRITE commands submitted */
+  uint64_t wb_evict;   /* write-backs of dirty victims */
+  uint64_t wb_flush;   /* write-backs issued by agile_flush */
+  uint64_t eagain;     /* acquisitions that found no evictable way */
+  uint64_t sq_spins;   /* submit-loop iterations that made no progress */
+  uint64_t ctrl_cmds;  /* commands executed by the emulated controller */
+  uint64_t cq_entries; /* completion entries consumed by the completion service */
+  uint64_t submitted;  /* commands submitted (monotonic, not reset) */
+  uint64_t completed;  /* commands completed (monotonic, not reset) */
+  uint64_t consumed;   /* workload rows read out of the cache and used */
+} agile_stats;
+agile_status agile_get_stats(agile_ctx ctx, agile_stats* out, int reset);
+
+/* Static description of a status code; never NULL. */
+const char* agile_status_string(agile_status s);
+/* Text of the last error recorded on ctx (host or device side); never NULL. */
+const char* agile_last_error(agile_ctx ctx);
+
+/* Information for benches and tests (all host values). */
+typedef struct agile_info {
+  uint32_t num_lines, num_sets, assoc, line_bytes;
+  uint32_t num_qp, qp_depth, ctrl_waves, cq_waves;
+  uint32_t cu_count, max_user_waves; /* user wavefronts one launch may run */
+  uint64_t wallclock_hz;             /* rate of s_memrealtime */
+  uint64_t cache_base;               /* device address of line 0 */
+} agile_info;
+agile_status agile_get_info(agile_ctx ctx, agile_info* out);
+
+/* ---------------------------------------------------------------- workloads --------
+ * Tables: `num_tables` fp32 tables of `rows` x `dim`, concatenated row-major in the
+ * store image starting at byte `base_offset`.  Row bytes (dim*4) must divide 4096. */
+typedef struct agile_tables {
+  uint64_t rows;
+  uint32_t dim;
+  uint32_t num_tables;
+  uint64_t base_offset;
+} agile_tables;
+
+#define AGILE_MODE_SYNC 0u  /* issue, wait, compute, release per chunk (the plain method) */
+#define AGILE_MODE_ASYNC 1u /* reads for the next chunk are issued before this chunk is
+                               computed, overlapping I/O with compute (Sec. 4.2) */
+
+/* Gathers n rows: d_out[i*dim + d] = table[d_idx[i] / rows][d_idx[i] % rows][d], where
+ * d_idx holds global row numbers (int64, device).  Stream-ordered. */
+agile_status agile_gather(agile_ctx ctx, agile_store store, const agile_tables* tb,
+                          const int64_t* d_idx, uint64_t n, uint32_t mode, float* d_out,
+                          void* stream);
+
+/* Embedding-bag forward: B samples x T = num_tables bags in sample-major order; bag
+ * g = b*T + t covers lookups [d_off[g], d_off[g+1]) of table t (d_idx: row numbers within
+ * the table).  d_out[g*dim + d] = sum, in lookup order, of f_K(row value), where f_K is
+ * K iterations of v = fmaf(v, 0.999f, 0.001f) (a compute loop that sets the
+ * computation-to-communication ratio, Sec. 4.2); fp32 accumulator from +0.0f.
+ * mode is AGILE_MODE_SYNC or AGILE_MODE_ASYNC; both give bit-identical output. */
+agile_status agile_embbag_forward(agile_ctx ctx, agile_store store, const agile_tables* tb,
+                                  const int64_t* d_idx, const int64_t* d_off, uint64_t B,
+                                  uint32_t K, uint32_t mode, float* d_out, void* stream);
+
+/* ---------------------------------------------------------------- diagnostics ------
+ * For tests and tools; not part of the I/O path. */
+
+/* Runs n requests one at a time on one lane (issue, wait, release): request i asks for
+ * line id d_lines[i] (uint64) and, when d_writes (uint8, may be NULL) is non-zero, marks
+ * the line MODIFIED.  Writes d_hit[i] (1 when no READ was needed) and d_way[i] (the way
+ * that served it).  With nothing else running, the sequence of hits, ways and dirty
+ * write-backs equals that of a sequential clock cache (Sec. 3.4, Sec. 4.4).  Blocks. */
+agile_status agile_debug_trace(agile_ctx ctx, agile_store store, const uint64_t* d_lines,
+                               const uint8_t* d_writes, uint64_t n, uint8_t* d_hit,
+                               int32_t* d_way, void* stream);
+
+/* Raw device counters in their internal order (for diagnostics): out[i] for i < n. */
+agile_status agile_debug_counters(agile_ctx ctx, uint64_t* out, uint32_t n);
+
+/* Decodes every line's metadata into device arrays: tag (int64, -1 when INVALID), state
+ * (uint8: 0 INVALID, 1 FETCHING, 2 READY, 3 DIRTY, 4 WRITEBACK) and pin count (uint32).
+ * Blocks. */
+agile_status agile_debug_dump(agile_ctx ctx, int64_t* d_tags, uint8_t* d_states,
+                              uint32_t* d_rc, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* AGILE_H */

@@ -24,6 +24,11 @@ together want more slots than the queue holds.
 all of its commands are written.  The search shows that this variant deadlocks when a
 wave's later command needs the slot of one of its own earlier commands, which is why
 the submission loop rings while it still waits for slots.
+
+``agile_batch_post`` is ``agile`` with a controller that posts all of its executed
+commands at once or none of them.  It deadlocks: the completion queue's room frees only
+when the polling window is full, and the window may need some of the very entries the
+controller holds back.  The controller therefore posts as many as fit.
 """
 from __future__ import annotations
 
@@ -40,7 +45,7 @@ def _agile_init(depth, window, reqs):
     return (0, 0, 0, frozenset(), 0, 0, 0, 0, frozenset(), slots, cq, threads)
 
 
-def _agile_succ(state, depth, window, reqs, ring_early=True):
+def _agile_succ(state, depth, window, reqs, ring_early=True, batch_post=False):
     (ticket, db, head, infl, cq_tail, cq_head, off, mask, done, slots, cq, threads) = state
     out = []
     for t, (pc, base, wr) in enumerate(threads):
@@ -92,7 +97,17 @@ def _agile_succ(state, depth, window, reqs, ring_early=True):
         out.append((ticket, db, head + 1, infl | {head % depth}, cq_tail, cq_head, off, mask,
                     done, slots, cq, threads))
     # controller: complete any fetched command (out of order) when the CQ has room
-    if cq_tail - cq_head < depth:
+    if batch_post and infl:
+        # all-or-nothing: every fetched command is posted at once, or none
+        if cq_tail - cq_head + len(infl) <= depth:
+            c = list(cq)
+            t = cq_tail
+            for s in sorted(infl):
+                c[t % depth] = (((t // depth) & 1) ^ 1, s)
+                t += 1
+            out.append((ticket, db, head, frozenset(), t, cq_head, off, mask, done, slots,
+                        tuple(c), threads))
+    elif cq_tail - cq_head < depth:
         for s in infl:
             c = list(cq)
             phase = ((cq_tail // depth) & 1) ^ 1
@@ -164,12 +179,13 @@ def _naive_finished(state):
 
 def explore(model: str, depth: int, reqs, window: int = None, limit: int = 2_000_000):
     """Breadth-first search of all interleavings.  Returns (states, deadlock or None)."""
-    if model in ("agile", "agile_ring_last"):
+    if model in ("agile", "agile_ring_last", "agile_batch_post"):
         window = window or depth
         assert depth % window == 0
         start = _agile_init(depth, window, reqs)
-        early = model == "agile"
-        succ = lambda s: _agile_succ(s, depth, window, reqs, early)  # noqa: E731
+        early = model != "agile_ring_last"
+        batch = model == "agile_batch_post"
+        succ = lambda s: _agile_succ(s, depth, window, reqs, early, batch)  # noqa: E731
         fin = _agile_finished
     elif model == "naive":
         start = _naive_init(depth, reqs)

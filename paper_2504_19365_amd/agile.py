@@ -1,0 +1,303 @@
+"""Python binding of libagile.so (include/agile.h): argument marshalling only.
+
+Every step of the path runs in the library's HIP kernels; this module only converts
+torch tensors / numpy arrays into pointers and checks status codes.  It raises loudly
+when the native library is missing: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libagile.so")
+
+OK, EINVAL, ENOMEM, EHIP, ETIMEDOUT, EAGAIN, EIO, EPROTO, ESTATE = 0, -1, -2, -3, -4, -5, -6, -7, -8
+F_SERIALIZED, F_NO_PRIO = 0x1, 0x2
+MODE_SYNC, MODE_ASYNC = 0, 1
+
+
+class AgileError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{msg} (status {status})")
+        self.status = status
+
+
+class Config(C.Structure):
+    _fields_ = [("struct_size", C.c_uint32), ("device", C.c_int32), ("cache_bytes", C.c_uint64),
+                ("line_bytes", C.c_uint32), ("assoc", C.c_uint32), ("num_qp", C.c_uint32),
+                ("qp_depth", C.c_uint32), ("ctrl_waves", C.c_uint32), ("cq_waves", C.c_uint32),
+                ("max_user_waves", C.c_uint32), ("latency_ns", C.c_uint64),
+                ("iops_cap", C.c_uint64), ("timeout_ns", C.c_uint64), ("flags", C.c_uint32),
+                ("reserved", C.c_uint32)]
+
+
+class Stats(C.Structure):
+    _fields_ = [(n, C.c_uint64) for n in (
+        "requests", "hits", "misses", "read_cmds", "write_cmds", "wb_evict", "wb_flush",
+        "eagain", "sq_spins", "ctrl_cmds", "cq_entries", "submitted", "completed",
+        "consumed")]
+
+    def as_dict(self):
+        return {n: int(getattr(self, n)) for n, _ in self._fields_}
+
+
+class Info(C.Structure):
+    _fields_ = [("num_lines", C.c_uint32), ("num_sets", C.c_uint32), ("assoc", C.c_uint32),
+                ("line_bytes", C.c_uint32), ("num_qp", C.c_uint32), ("qp_depth", C.c_uint32),
+                ("ctrl_waves", C.c_uint32), ("cq_waves", C.c_uint32), ("cu_count", C.c_uint32),
+                ("max_user_waves", C.c_uint32), ("wallclock_hz", C.c_uint64),
+                ("cache_base", C.c_uint64)]
+
+    def as_dict(self):
+        return {n: int(getattr(self, n)) for n, _ in self._fields_}
+
+
+class Tables(C.Structure):
+    _fields_ = [("rows", C.c_uint64), ("dim", C.c_uint32), ("num_tables", C.c_uint32),
+                ("base_offset", C.c_uint64)]
+
+
+_lib = None
+
+
+def lib():
+    """Loads libagile.so; raises if it is not built (no CPU fallback exists)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built: run __graft_entry__.build()")
+        # torch ships its own HIP runtime under the same soname; loading torch first makes
+        # this library bind to that one instance instead of a second runtime
+        import torch  # noqa: F401
+        L = C.CDLL(LIB_PATH)
+        vp, u32, u64, i32, st = C.c_void_p, C.c_uint32, C.c_uint64, C.c_int32, C.c_int
+        sig = {
+            "agile_config_default": (None, [C.POINTER(Config)]),
+            "agile_init": (st, [C.POINTER(Config), C.POINTER(vp)]),
+            "agile_shutdown": (st, [vp]),
+            "agile_host_alloc": (st, [u64, C.POINTER(vp)]),
+            "agile_host_free": (st, [vp]),
+            "agile_open_store": (st, [vp, vp, u64, u32, u32, C.POINTER(vp)]),
+            "agile_close_store": (st, [vp, vp]),
+            "agile_async_read": (st, [vp, vp, vp, u32, vp, vp]),
+            "agile_wait": (st, [vp, vp, u32, vp, vp]),
+            "agile_release": (st, [vp, vp, u32, vp]),
+            "agile_flush": (st, [vp, vp, vp]),
+            "agile_invalidate": (st, [vp, vp, vp]),
+            "agile_sync": (st, [vp, vp]),
+            "agile_get_stats": (st, [vp, C.POINTER(Stats), C.c_int]),
+            "agile_status_string": (C.c_char_p, [st]),
+            "agile_last_error": (C.c_char_p, [vp]),
+            "agile_get_info": (st, [vp, C.POINTER(Info)]),
+            "agile_gather": (st, [vp, vp, C.POINTER(Tables), vp, u64, u32, vp, vp]),
+            "agile_embbag_forward": (st, [vp, vp, C.POINTER(Tables), vp, vp, u64, u32, u32, vp,
+                                          vp]),
+            "agile_debug_trace": (st, [vp, vp, vp, vp, u64, vp, vp, vp]),
+            "agile_debug_dump": (st, [vp, vp, vp, vp, vp]),
+            "agile_debug_counters": (st, [vp, vp, u32]),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def status_string(s: int) -> str:
+    return lib().agile_status_string(s).decode()
+
+
+def _ptr(x) -> int:
+    """Device or host address of a torch tensor, numpy array or int."""
+    if x is None:
+        return 0
+    if isinstance(x, int):
+        return x
+    if isinstance(x, np.ndarray):
+        return x.ctypes.data
+    return x.data_ptr()
+
+
+def _stream(stream) -> int:
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def default_config(**kw) -> Config:
+    cfg = Config()
+    lib().agile_config_default(C.byref(cfg))
+    for k, v in kw.items():
+        if not hasattr(cfg, k):
+            raise TypeError(f"unknown config field {k}")
+        setattr(cfg, k, v)
+    return cfg
+
+
+class PinnedBuffer:
+    """Pinned, device-mapped host memory (agile_host_alloc) with a numpy view."""
+
+    def __init__(self, nbytes: int):
+        p = C.c_void_p()
+        s = lib().agile_host_alloc(nbytes, C.byref(p))
+        if s != OK:
+            raise AgileError(s, f"agile_host_alloc({nbytes})")
+        self.ptr = p.value
+        self.nbytes = nbytes
+        self.array = np.ctypeslib.as_array((C.c_uint8 * nbytes).from_address(self.ptr))
+
+    def free(self):
+        if self.ptr:
+            lib().agile_host_free(self.ptr)
+            self.ptr = 0
+            self.array = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+class Store:
+    def __init__(self, ctx: "Context", handle: int, image: PinnedBuffer | None, nbytes: int):
+        self.ctx, self.handle, self.image, self.nbytes = ctx, handle, image, nbytes
+
+
+class Context:
+    def __init__(self, cfg: Config | None = None, **kw):
+        cfg = cfg if cfg is not None else default_config(**kw)
+        self.cfg = cfg
+        h = C.c_void_p()
+        s = lib().agile_init(C.byref(cfg), C.byref(h))
+        if s != OK:
+            raise AgileError(s, "agile_init")
+        self.h = h.value
+        self.store = None
+
+    # ---- helpers
+    def _check(self, s: int, what: str):
+        if s != OK:
+            msg = f"{what}: {lib().agile_last_error(self.h).decode()}"
+            if s in (ETIMEDOUT, EPROTO, EIO):
+                try:
+                    msg += f" counters={self.debug_counters()}"
+                except Exception:
+                    pass
+            raise AgileError(s, msg)
+
+    def last_error(self) -> str:
+        return lib().agile_last_error(self.h).decode()
+
+    # ---- lifecycle
+    def open_store(self, image: PinnedBuffer | int, nbytes: int | None = None) -> Store:
+        ptr = image.ptr if isinstance(image, PinnedBuffer) else int(image)
+        nbytes = nbytes if nbytes is not None else image.nbytes
+        h = C.c_void_p()
+        self._check(lib().agile_open_store(self.h, ptr, nbytes, 4096, 0, C.byref(h)),
+                    "agile_open_store")
+        self.store = Store(self, h.value, image if isinstance(image, PinnedBuffer) else None,
+                           nbytes)
+        return self.store
+
+    def close_store(self, store: Store | None = None) -> int:
+        store = store or self.store
+        s = lib().agile_close_store(self.h, store.handle)
+        self.store = None
+        return s
+
+    def shutdown(self):
+        if self.h:
+            lib().agile_shutdown(self.h)
+            self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.shutdown()
+
+    # ---- ticket API
+    def async_read(self, blocks, tickets, stream=None, store=None):
+        store = store or self.store
+        self._check(lib().agile_async_read(self.h, store.handle, _ptr(blocks), blocks.numel(),
+                                           _ptr(tickets), _stream(stream)), "agile_async_read")
+
+    def wait(self, tickets, ptrs, stream=None) -> int:
+        s = lib().agile_wait(self.h, _ptr(tickets), tickets.numel(), _ptr(ptrs), _stream(stream))
+        if s not in (OK, EAGAIN):
+            self._check(s, "agile_wait")
+        return s
+
+    def release(self, tickets, stream=None):
+        self._check(lib().agile_release(self.h, _ptr(tickets), tickets.numel(), _stream(stream)),
+                    "agile_release")
+
+    def flush(self, stream=None, store=None):
+        store = store or self.store
+        self._check(lib().agile_flush(self.h, store.handle, _stream(stream)), "agile_flush")
+
+    def invalidate(self, stream=None, store=None):
+        store = store or self.store
+        self._check(lib().agile_invalidate(self.h, store.handle, _stream(stream)),
+                    "agile_invalidate")
+
+    def sync(self, stream=None):
+        self._check(lib().agile_sync(self.h, _stream(stream)), "agile_sync")
+
+    def stats(self, reset: bool = False) -> dict:
+        st = Stats()
+        self._check(lib().agile_get_stats(self.h, C.byref(st), 1 if reset else 0),
+                    "agile_get_stats")
+        return st.as_dict()
+
+    def info(self) -> dict:
+        inf = Info()
+        self._check(lib().agile_get_info(self.h, C.byref(inf)), "agile_get_info")
+        return inf.as_dict()
+
+    # ---- workloads
+    @staticmethod
+    def tables(rows: int, dim: int, num_tables: int = 1, base_offset: int = 0) -> Tables:
+        return Tables(rows, dim, num_tables, base_offset)
+
+    def gather(self, tb: Tables, idx, out, mode: int = MODE_SYNC, stream=None, store=None):
+        store = store or self.store
+        self._check(lib().agile_gather(self.h, store.handle, C.byref(tb), _ptr(idx), idx.numel(),
+                                       mode, _ptr(out), _stream(stream)), "agile_gather")
+
+    def embbag_forward(self, tb: Tables, idx, off, B: int, K: int, out, mode: int = MODE_SYNC,
+                       stream=None, store=None):
+        store = store or self.store
+        self._check(lib().agile_embbag_forward(self.h, store.handle, C.byref(tb), _ptr(idx),
+                                               _ptr(off), B, K, mode, _ptr(out), _stream(stream)),
+                    "agile_embbag_forward")
+
+    # ---- diagnostics
+    def debug_trace(self, lines, writes, hit, way, stream=None, store=None):
+        store = store or self.store
+        self._check(lib().agile_debug_trace(self.h, store.handle, _ptr(lines), _ptr(writes),
+                                            lines.numel(), _ptr(hit), _ptr(way), _stream(stream)),
+                    "agile_debug_trace")
+
+    COUNTER_NAMES = ("submitted", "completed", "user_done", "work", "requests", "hits",
+                     "misses", "reads", "writes", "wb_evict", "wb_flush", "eagain", "sq_spins",
+                     "ctrl_cmds", "cq_entries", "aux0", "aux1", "svc_start", "ctrl_fetch",
+                     "ctrl_loops", "cq_loops")
+
+    def debug_counters(self) -> dict:
+        n = len(self.COUNTER_NAMES)
+        out = (C.c_uint64 * n)()
+        lib().agile_debug_counters(self.h, C.cast(out, C.c_void_p), n)
+        return dict(zip(self.COUNTER_NAMES, [int(x) for x in out]))
+
+    def debug_dump(self, tags, states, rc, stream=None):
+        self._check(lib().agile_debug_dump(self.h, _ptr(tags), _ptr(states), _ptr(rc),
+                                           _stream(stream)), "agile_debug_dump")

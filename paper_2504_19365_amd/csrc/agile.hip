@@ -1,0 +1,1117 @@
+// agile.hip - kernels and host implementation of the C ABI in include/agile.h.
+//
+// Every launch that can submit commands carries its own service wavefronts: workgroups
+// [0, service_blocks) run the emulated controller and the completion service, the rest
+// run user wavefronts.  Workgroups are dispatched in index order, and the user grid is
+// sized to the resident capacity, so the service is always resident while users wait.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "agile.h"
+#include "agile_dev.hpp"
+
+using namespace ag;
+
+// =============================================================================== kernels
+namespace {
+
+constexpr uint32_t TK_OK = 0, TK_EAGAIN = 1;
+
+struct embbag_args {
+  const int64_t* idx;
+  const int64_t* off;   // NULL in gather mode (bag g = lookups [64g, 64g+64))
+  float* out;
+  uint64_t nbags;
+  uint64_t n;           // lookups (gather mode)
+  uint64_t rows;        // rows per table
+  uint64_t base_off;    // byte offset of table 0 in the store
+  uint64_t table_bytes;
+  uint32_t T, dim, row_bytes, K;
+  uint32_t mode, gather, active_waves, _a1;
+};
+
+__device__ __forceinline__ float fK(float v, uint32_t K) {
+  for (uint32_t k = 0; k < K; ++k) v = __builtin_fmaf(v, 0.999f, 0.001f);
+  return v;
+}
+
+// Descriptor of one chunk: bag g, lookups [j, j + n), last chunk of its bag?
+struct desc_t {
+  int64_t g;
+  int64_t j, end;
+  uint32_t n;
+  bool valid, last;
+};
+
+__device__ __forceinline__ int64_t grab(const dev_ctx& c, const launch_t& li) {
+  uint64_t v = 0;
+  if (lane() == 0) v = add_rlx(counter(c, C_WORK), 1ull);
+  v = rdlane64(v, 0);
+  return (int64_t)(v - li.work_base);
+}
+
+template <int VPL>
+__device__ __forceinline__ void write_bag(const embbag_args& a, int64_t g, const float (&acc)[VPL]) {
+  const uint32_t d0 = lane() * VPL;
+  float* o = a.out + (uint64_t)g * a.dim + d0;
+#pragma unroll
+  for (int v = 0; v < VPL; ++v)
+    if (d0 + v < a.dim) o[v] = acc[v];
+}
+
+// Next chunk after `d` (or the first one when !d.valid): continues the bag or grabs the
+// next non-empty bag; empty bags get their zero output on the way.
+template <int VPL>
+__device__ desc_t next_desc(const dev_ctx& c, const launch_t& li, const embbag_args& a,
+                            const desc_t& d) {
+  desc_t r;
+  if (d.valid && !d.last) {
+    r.g = d.g;
+    r.j = d.j + d.n;
+    r.end = d.end;
+  } else {
+    for (;;) {
+      const int64_t g = grab(c, li);
+      if (g >= (int64_t)a.nbags) {
+        r.valid = false;
+        return r;
+      }
+      int64_t j0, j1;
+      if (a.gather) {
+        j0 = g * 64;
+        j1 = ((int64_t)a.n < j0 + 64) ? (int64_t)a.n : j0 + 64;
+      } else {
+        j0 = a.off[g];
+        j1 = a.off[g + 1];
+      }
+      if (j1 > j0) {
+        r.g = g;
+        r.j = j0;
+        r.end = j1;
+        break;
+      }
+      if (!a.gather) {
+        float z[VPL];
+#pragma unroll
+        for (int v = 0; v < VPL; ++v) z[v] = 0.0f;
+        write_bag<VPL>(a, g, z);
+      }
+    }
+  }
+  const int64_t left = r.end - r.j;
+  r.n = (uint32_t)(left < 64 ? left : 64);
+  r.last = r.j + r.n == r.end;
+  r.valid = true;
+  return r;
+}
+
+__device__ __forceinline__ void make_chunk(const dev_ctx& c, const embbag_args& a, const desc_t& d,
+                                           chunk_t& ch) {
+  ch.act = d.valid && lane() < d.n;
+  ch.st = A_NONE;
+  if (ch.act) {
+    const int64_t row = a.idx[d.j + lane()];
+    uint64_t byte;
+    if (a.gather) {
+      byte = a.base_off + (uint64_t)row * a.row_bytes;
+    } else {
+      const uint32_t t = (uint32_t)(d.g % a.T);
+      byte = a.base_off + (uint64_t)t * a.table_bytes + (uint64_t)row * a.row_bytes;
+    }
+    ch.line_id = (uint32_t)(byte >> c.line_shift);
+    ch.off = (uint32_t)(byte & ((1ull << c.line_shift) - 1));
+  }
+}
+
+// Consumes rows of the chunk in order until the first row whose lane is not pinned.
+// Returns the number consumed.  Four rows' loads are in flight before their compute.
+template <int VPL>
+__device__ uint32_t consume(const dev_ctx& c, const embbag_args& a, const desc_t& d,
+                            const chunk_t& ch, float (&acc)[VPL]) {
+  const uint64_t okm = ballot(ch.act && (ch.st == A_HIT || ch.st == A_JOIN || ch.st == A_MISS));
+  const uint32_t nok = (~okm == 0ull) ? 64u : ffs64(~okm);
+  const uint32_t n = nok < d.n ? nok : d.n;
+  const uint32_t d0 = lane() * VPL;
+  const bool mine = d0 < a.dim;
+  uint32_t j = 0;
+  for (; j < n; j += 4) {
+    float v[4][VPL];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      if (j + u < n) {
+        const uint32_t idx = rdlane(ch.idx, j + u);
+        const uint32_t off = rdlane(ch.off, j + u);
+        const float* p = reinterpret_cast<const float*>(line_ptr(c, idx) + off) + d0;
+        if (mine) {
+          if constexpr (VPL == 4) {
+            const float4 t = *reinterpret_cast<const float4*>(p);
+            v[u][0] = t.x; v[u][1] = t.y; v[u][2] = t.z; v[u][3] = t.w;
+          } else if constexpr (VPL == 2) {
+            const float2 t = *reinterpret_cast<const float2*>(p);
+            v[u][0] = t.x; v[u][1] = t.y;
+          } else {
+            v[u][0] = p[0];
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      if (j + u < n && mine) {
+        if (a.gather) {
+          float* o = a.out + (uint64_t)(d.j + j + u) * a.dim + d0;
+#pragma unroll
+          for (int e = 0; e < VPL; ++e) o[e] = v[u][e];
+        } else {
+#pragma unroll
+          for (int e = 0; e < VPL; ++e) acc[e] = acc[e] + fK(v[u][e], a.K);
+        }
+      }
+    }
+  }
+  return n;
+}
+
+// One user wavefront of the embedding-bag / gather workload.
+template <int VPL>
+__device__ void embbag_wave(const dev_ctx& c, const launch_t& li, const embbag_args& a, uint32_t uw) {
+  const uint32_t q = uw % c.num_qp;
+  const bool async = a.mode == AGILE_MODE_ASYNC;
+  float acc[VPL];
+#pragma unroll
+  for (int v = 0; v < VPL; ++v) acc[v] = 0.0f;
+  desc_t none;
+  none.valid = false;
+  desc_t dc = next_desc<VPL>(c, li, a, none);
+  if (!dc.valid) return;
+  chunk_t cc, cn;
+  make_chunk(c, a, dc, cc);
+  if (!chunk_issue(c, cc, q, true)) return;
+  while (dc.valid) {
+    desc_t dn;
+    bool n_issued = false;
+    if (async) {
+      dn = next_desc<VPL>(c, li, a, dc);
+      if (dn.valid) {
+        make_chunk(c, a, dn, cn);
+        if (!chunk_issue(c, cn, q, true)) return;
+        n_issued = true;
+      }
+    }
+    // consume the current chunk in order up to its first row without a line
+    if (!chunk_wait(c, cc)) return;
+    const uint32_t k = consume<VPL>(c, a, dc, cc, acc);
+    chunk_release(c, cc, false);
+    if (lane() == 0) count(c, C_AUX1, k);
+    if (k < dc.n) {
+      // EAGAIN: drop every pin this wave holds (including the prefetched chunk), then
+      // drain the rest of the chunk one row at a time, acquiring each row while holding
+      // nothing, so that no wave ever waits for a line while it pins others (Sec. 2.3.2).
+      if (n_issued) {
+        if (!chunk_wait(c, cn)) return;
+        chunk_release(c, cn, false);
+        n_issued = false;
+      }
+      dc.j += k;
+      dc.n -= k;
+      while (dc.n > 0) {
+        desc_t one = dc;
+        one.n = 1;
+        spin_t sp;
+        for (;;) {
+          make_chunk(c, a, one, cc);
+          if (!chunk_issue(c, cc, q, true)) return;
+          if (rdlane(cc.st, 0) != A_EAGAIN) break;
+          if (!sp.step(c, 0xF0000000ull | (uint32_t)dc.g)) return;
+        }
+        if (!chunk_wait(c, cc)) return;
+        consume<VPL>(c, a, one, cc, acc);
+        chunk_release(c, cc, false);
+        if (lane() == 0) count(c, C_AUX1, 1);
+        dc.j += 1;
+        dc.n -= 1;
+      }
+    }
+    if (dc.last && !a.gather) {
+      write_bag<VPL>(a, dc.g, acc);
+#pragma unroll
+      for (int v = 0; v < VPL; ++v) acc[v] = 0.0f;
+    }
+    if (!async) dn = next_desc<VPL>(c, li, a, dc);
+    dc = dn;
+    if (!dc.valid) break;
+    if (n_issued) {
+      cc = cn;
+    } else {
+      make_chunk(c, a, dc, cc);
+      if (!chunk_issue(c, cc, q, true)) return;
+    }
+  }
+}
+
+// Serialized mode: lane 0 of a single wave handles one lookup at a time in program order
+// (issue, wait, compute, release), so the cache sees exactly the request sequence.
+template <int VPL>
+__device__ void embbag_serial(const dev_ctx& c, const launch_t& li, const embbag_args& a) {
+  float acc[VPL];
+  const uint64_t nb = a.nbags;
+  for (uint64_t g = 0; g < nb; ++g) {
+    int64_t j0 = a.gather ? (int64_t)g * 64 : a.off[g];
+    int64_t j1 = a.gather ? (((int64_t)a.n < j0 + 64) ? (int64_t)a.n : j0 + 64) : a.off[g + 1];
+#pragma unroll
+    for (int v = 0; v < VPL; ++v) acc[v] = 0.0f;
+    for (int64_t j = j0; j < j1; ++j) {
+      desc_t d;
+      d.g = (int64_t)g;
+      d.j = j;
+      d.end = j + 1;
+      d.n = 1;
+      d.valid = true;
+      d.last = true;
+      chunk_t ch;
+      spin_t sp;
+      for (;;) {
+        make_chunk(c, a, d, ch);
+        if (!chunk_issue(c, ch, 0, true)) return;
+        if (!chunk_wait(c, ch)) return;
+        const uint32_t k = consume<VPL>(c, a, d, ch, acc);
+        chunk_release(c, ch, false);
+        if (k == 1) {
+          if (lane() == 0) count(c, C_AUX1, 1);
+          break;
+        }
+        if (!sp.step(c, 0xF1000000ull)) return;
+      }
+    }
+    if (!a.gather) write_bag<VPL>(a, (int64_t)g, acc);
+  }
+}
+
+template <int VPL>
+__global__ __launch_bounds__(WG) void k_embbag(dev_ctx c, launch_t li, embbag_args a) {
+  if (blockIdx.x < li.service_blocks) {
+    run_service(c, li);
+    return;
+  }
+  const uint32_t uw = (blockIdx.x - li.service_blocks) * WPB + threadIdx.x / 64;
+  if (c.flags & AGILE_F_SERIALIZED) {
+    if (uw == 0) embbag_serial<VPL>(c, li, a);
+  } else if (uw < a.active_waves) {
+    embbag_wave<VPL>(c, li, a, uw);
+  }
+  user_wave_done(c);
+}
+
+// ---- host-level ticket API kernels
+__global__ __launch_bounds__(WG) void k_async_read(dev_ctx c, launch_t li, const uint64_t* blocks,
+                                                   uint32_t n, agile_ticket* tickets) {
+  if (blockIdx.x < li.service_blocks) {
+    run_service(c, li);
+    return;
+  }
+  const uint32_t uw = (blockIdx.x - li.service_blocks) * WPB + threadIdx.x / 64;
+  const uint32_t q = uw % c.num_qp;
+  for (uint64_t base = (uint64_t)uw * 64; base < n; base += (uint64_t)li.user_waves * 64) {
+    chunk_t ch;
+    const uint64_t i = base + lane();
+    ch.act = i < n;
+    uint64_t blk = 0;
+    if (ch.act) {
+      blk = blocks[i];
+      if (blk >= c.store_blocks) {
+        raise_error(c, E_STATE, blk);
+        ch.act = false;
+      }
+      ch.line_id = (uint32_t)(blk / c.blocks_per_line);
+      ch.off = (uint32_t)((blk % c.blocks_per_line) << 12);
+    }
+    if (!chunk_issue(c, ch, q, true, true)) break;
+    if (ch.act) {
+      const bool ok = ch.st == A_HIT || ch.st == A_JOIN || ch.st == A_MISS;
+      tickets[i] = (uint64_t)ch.idx | ((uint64_t)(ch.gen & 0xFF) << 32) |
+                   ((uint64_t)(ok ? TK_OK : TK_EAGAIN) << 40) | ((uint64_t)(ch.off >> 12) << 48);
+    }
+  }
+  user_wave_done(c);
+}
+
+__global__ __launch_bounds__(WG) void k_wait(dev_ctx c, launch_t li, const agile_ticket* tickets,
+                                             uint32_t n, void** ptrs) {
+  const uint32_t uw = blockIdx.x * WPB + threadIdx.x / 64;
+  const uint64_t i = (uint64_t)uw * 64 + lane();
+  bool waiting = false;
+  uint32_t idx = 0, gen = 0, st = TK_EAGAIN, boff = 0;
+  if (i < n) {
+    const uint64_t t = tickets[i];
+    idx = (uint32_t)t;
+    gen = (uint32_t)(t >> 32) & 0xFF;
+    st = (uint32_t)(t >> 40) & 0xFF;
+    boff = (uint32_t)(t >> 48);
+    if (st == TK_OK) {
+      if (idx >= c.num_lines) {
+        raise_error(c, E_STATE, t);
+      } else {
+        waiting = true;
+      }
+    }
+  }
+  spin_t sp;
+  bool okay = true;
+  while (ballot(waiting)) {
+    if (waiting) {
+      const uint64_t m = ld_acq(c.meta + idx);
+      if (m_state(m) != ST_FETCHING) {
+        waiting = false;
+        if (m_gen(m) != gen || m_rc(m) == 0) raise_error(c, E_STATE, ((uint64_t)idx << 8) | gen);
+      }
+    }
+    if (ballot(waiting) && !sp.step(c, 0xE0000000ull | idx)) {
+      okay = false;
+      break;
+    }
+  }
+  if (i < n) {
+    ptrs[i] = (okay && st == TK_OK) ? (void*)(line_ptr(c, idx) + ((uint64_t)boff << 12)) : nullptr;
+  }
+  const uint64_t ne = __popcll(ballot(i < n && st == TK_EAGAIN));
+  if (lane() == 0 && ne) add_rlx(counter(c, C_AUX0), ne);
+  user_wave_done(c);
+}
+
+__global__ __launch_bounds__(WG) void k_release(dev_ctx c, launch_t li, const agile_ticket* tickets,
+                                                uint32_t n) {
+  const uint32_t uw = blockIdx.x * WPB + threadIdx.x / 64;
+  const uint64_t i = (uint64_t)uw * 64 + lane();
+  if (i < n) {
+    const uint64_t t = tickets[i];
+    const uint32_t idx = (uint32_t)t;
+    if (((t >> 40) & 0xFF) == TK_OK && idx < c.num_lines) add_rel(c.meta + idx, (uint64_t)0 - RC_ONE);
+  }
+  user_wave_done(c);
+}
+
+// Flush: every DIRTY, unpinned line becomes WRITEBACK and gets one WRITE; the launch's
+// service wavefronts drain them (WRITEBACK -> READY).  A pinned dirty line is an error.
+__global__ __launch_bounds__(WG) void k_flush(dev_ctx c, launch_t li) {
+  if (blockIdx.x < li.service_blocks) {
+    run_service(c, li);
+    return;
+  }
+  const uint32_t uw = (blockIdx.x - li.service_blocks) * WPB + threadIdx.x / 64;
+  const uint32_t q = uw % c.num_qp;
+  for (uint64_t base = (uint64_t)uw * 64; base < c.num_lines; base += (uint64_t)li.user_waves * 64) {
+    const uint64_t i = base + lane();
+    bool wb = false;
+    uint64_t slba = 0;
+    uint32_t nblk = c.blocks_per_line;
+    if (i < c.num_lines) {
+      uint64_t m = ld_rlx(c.meta + i);
+      if (m_state(m) == ST_DIRTY) {
+        if (m_rc(m) != 0) {
+          raise_error(c, E_STATE, i);
+        } else if (cas(c.meta + i, m, (m & ~M_STATE) | ST_WRITEBACK)) {
+          wb = true;
+          slba = (uint64_t)m_tag(m) * c.blocks_per_line;
+          if (slba + nblk > c.store_blocks) nblk = (uint32_t)(c.store_blocks - slba);
+        } else {
+          raise_error(c, E_STATE, i);
+        }
+      }
+    }
+    const uint64_t nw = __popcll(ballot(wb));
+    if (lane() == 0) count(c, C_WB_FLUSH, nw);
+    if (!submit(c, q, wb, OPC_WRITE, (uint32_t)i, slba, nblk)) break;
+  }
+  user_wave_done(c);
+}
+
+__global__ __launch_bounds__(WG) void k_invalidate(dev_ctx c, launch_t li) {
+  const uint32_t uw = blockIdx.x * WPB + threadIdx.x / 64;
+  const uint64_t i = (uint64_t)uw * 64 + lane();
+  if (i < c.num_lines) {
+    uint64_t m = ld_rlx(c.meta + i);
+    const uint32_t st = m_state(m);
+    if (st == ST_READY && m_rc(m) == 0) {
+      if (!cas(c.meta + i, m, m & ~(M_STATE | M_REF))) raise_error(c, E_STATE, i);
+    } else if (st != ST_INVALID) {
+      raise_error(c, E_STATE, i);
+    }
+  }
+  // clock hands back to way 0 so that a cold cache replays like a fresh one
+  for (uint64_t s = i; s < c.num_sets; s += (uint64_t)li.user_waves * 64) st_rlx(c.hand + s, 0u);
+  user_wave_done(c);
+}
+
+// Serialized request trace for the clock-policy comparison: lane 0 of one wave acquires
+// line ids one at a time (write requests turn the line DIRTY), recording hit/miss and way.
+__global__ __launch_bounds__(WG) void k_trace(dev_ctx c, launch_t li, const uint64_t* lines,
+                                              const uint8_t* writes, uint64_t n, uint8_t* hit,
+                                              int32_t* way) {
+  if (blockIdx.x < li.service_blocks) {
+    run_service(c, li);
+    return;
+  }
+  const uint32_t uw = (blockIdx.x - li.service_blocks) * WPB + threadIdx.x / 64;
+  if (uw == 0) {
+    for (uint64_t i = 0; i < n; ++i) {
+      chunk_t ch;
+      ch.act = lane() == 0;
+      ch.line_id = (uint32_t)lines[i];
+      ch.off = 0;
+      const bool w = writes && writes[i];
+      spin_t sp;
+      for (;;) {
+        if (!chunk_issue(c, ch, 0, true)) goto out;
+        if (!chunk_wait(c, ch)) goto out;
+        if (rdlane(ch.st, 0) != A_EAGAIN) break;
+        if (!sp.step(c, 0xF2000000ull)) goto out;
+      }
+      if (lane() == 0) {
+        hit[i] = (ch.st == A_MISS) ? 0 : 1;
+        way[i] = (int32_t)(ch.idx % c.assoc);
+        if (w) {
+          uint64_t m = ld_rlx(c.meta + ch.idx);
+          while (m_state(m) == ST_READY) {
+            if (cas(c.meta + ch.idx, m, m + 1ull)) break;  // READY -> DIRTY
+          }
+        }
+      }
+      chunk_release(c, ch, w);
+    }
+  }
+out:
+  user_wave_done(c);
+}
+
+// Debug dump: tag (or -1), state, pin count per line.
+__global__ void k_dump(dev_ctx c, int64_t* tags, uint8_t* states, uint32_t* rc) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < c.num_lines) {
+    const uint64_t m = ld_rlx(c.meta + i);
+    tags[i] = m_state(m) == ST_INVALID ? -1 : (int64_t)m_tag(m);
+    states[i] = (uint8_t)m_state(m);
+    rc[i] = m_rc(m);
+  }
+}
+
+}  // namespace
+
+// =============================================================================== host side
+struct agile_store_s {
+  void* host;
+  uint8_t* dev;
+  uint64_t bytes;
+  uint64_t blocks;
+};
+
+struct agile_ctx_s {
+  agile_config cfg;
+  dev_ctx d;
+  uint32_t n_ctrl, n_cq, service_blocks;
+  uint32_t cu_count;
+  uint64_t clock_hz;
+  uint64_t user_done_total = 0;
+  uint64_t work_total = 0;
+  agile_store_s* store = nullptr;
+  std::string last_error;
+  bool poisoned = false;
+  uint32_t* abort_host = nullptr;  // pinned, mapped
+  std::vector<void*> dev_allocs;
+  std::vector<int> occ_cache;  // resident workgroups per CU, per kernel kind
+};
+
+namespace {
+
+constexpr int KIND_EMBBAG1 = 0, KIND_EMBBAG2 = 1, KIND_EMBBAG4 = 2, KIND_READ = 3, KIND_FLUSH = 4,
+              KIND_TRACE = 5, KIND_N = 6;
+
+agile_status fail(agile_ctx ctx, agile_status s, const std::string& msg) {
+  if (ctx) ctx->last_error = msg;
+  return s;
+}
+
+#define HIPCHK(ctx, call)                                                                   \
+  do {                                                                                      \
+    hipError_t e_ = (call);                                                                 \
+    if (e_ != hipSuccess) {                                                                 \
+      return fail(ctx, AGILE_EHIP, std::string(#call) + ": " + hipGetErrorString(e_));       \
+    }                                                                                       \
+  } while (0)
+
+bool is_pow2(uint64_t v) { return v && !(v & (v - 1)); }
+uint32_t log2u(uint64_t v) {
+  uint32_t r = 0;
+  while ((1ull << r) < v) ++r;
+  return r;
+}
+
+template <class T>
+agile_status dalloc(agile_ctx ctx, T** p, size_t bytes) {
+  void* q = nullptr;
+  if (hipMalloc(&q, bytes ? bytes : 64) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(ctx, AGILE_ENOMEM, "hipMalloc failed for " + std::to_string(bytes) + " bytes");
+  }
+  ctx->dev_allocs.push_back(q);
+  *p = reinterpret_cast<T*>(q);
+  return AGILE_OK;
+}
+
+int occupancy(agile_ctx ctx, int kind) {
+  int& v = ctx->occ_cache[kind];
+  if (v > 0) return v;
+  int nb = 0;
+  hipError_t e = hipSuccess;
+  switch (kind) {
+    case KIND_EMBBAG1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_embbag<1>, WG, 0); break;
+    case KIND_EMBBAG2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_embbag<2>, WG, 0); break;
+    case KIND_EMBBAG4: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_embbag<4>, WG, 0); break;
+    case KIND_READ: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_async_read, WG, 0); break;
+    case KIND_FLUSH: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_flush, WG, 0); break;
+    default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_trace, WG, 0); break;
+  }
+  if (e != hipSuccess || nb <= 0) nb = 1;
+  v = nb;
+  return v;
+}
+
+// User wavefronts a launch of `kind` may use so that the whole grid (service included)
+// is resident at once.
+uint32_t user_wave_cap(agile_ctx ctx, int kind) {
+  const uint64_t blocks = (uint64_t)occupancy(ctx, kind) * ctx->cu_count;
+  uint64_t ub = blocks > ctx->service_blocks ? blocks - ctx->service_blocks : 1;
+  uint64_t uw = ub * WPB;
+  if (ctx->cfg.max_user_waves && uw > ctx->cfg.max_user_waves) uw = ctx->cfg.max_user_waves;
+  return (uint32_t)std::max<uint64_t>(uw, 1);
+}
+
+agile_status check_usable(agile_ctx ctx) {
+  if (!ctx) return AGILE_EINVAL;
+  if (ctx->poisoned) return fail(ctx, AGILE_ESTATE, "context has a sticky device error");
+  return AGILE_OK;
+}
+
+// user_waves must be a multiple of WPB (every wave of a user workgroup reports done).
+// `grabs` is the number of work-counter increments the launch will make.
+launch_t make_launch(agile_ctx ctx, uint32_t user_waves, bool service, uint64_t grabs) {
+  launch_t li{};
+  li.service_blocks = service ? ctx->service_blocks : 0;
+  li.n_ctrl = ctx->n_ctrl;
+  li.n_cq = ctx->n_cq;
+  li.user_waves = user_waves;
+  ctx->user_done_total += user_waves;
+  li.user_done_target = ctx->user_done_total;
+  li.work_base = ctx->work_total;
+  ctx->work_total += grabs;
+  li.prio = (ctx->cfg.flags & AGILE_F_NO_PRIO) ? 0 : 1;
+  return li;
+}
+
+void bind_store(agile_ctx ctx) {
+  if (ctx->store) {
+    ctx->d.image = ctx->store->dev;
+    ctx->d.store_blocks = ctx->store->blocks;
+  } else {
+    ctx->d.image = nullptr;
+    ctx->d.store_blocks = 0;
+  }
+}
+
+agile_status map_device_error(agile_ctx ctx) {
+  uint32_t err = 0;
+  uint64_t info = 0;
+  HIPCHK(ctx, hipMemcpy(&err, ctx->d.err, sizeof(err), hipMemcpyDeviceToHost));
+  HIPCHK(ctx, hipMemcpy(&info, ctx->d.err_info, sizeof(info), hipMemcpyDeviceToHost));
+  if (!err && !*ctx->abort_host) return AGILE_OK;
+  ctx->poisoned = true;
+  char buf[160];
+  snprintf(buf, sizeof buf, "device error %u (info 0x%llx)", err, (unsigned long long)info);
+  switch (err) {
+    case E_TIMEDOUT: return fail(ctx, AGILE_ETIMEDOUT, std::string(buf) + ": watchdog timeout");
+    case E_IO: return fail(ctx, AGILE_EIO, std::string(buf) + ": command error status");
+    case E_PROTO: return fail(ctx, AGILE_EPROTO, std::string(buf) + ": queue protocol violation");
+    case E_STATE: return fail(ctx, AGILE_ESTATE, std::string(buf) + ": invalid state or argument");
+    default: return fail(ctx, AGILE_ETIMEDOUT, std::string(buf) + ": aborted");
+  }
+}
+
+// Host-side watchdog: polls the stream; past the limit it raises the pinned abort flag
+// (every device wait checks it) and keeps waiting for the kernels to drain.
+agile_status sync_stream(agile_ctx ctx, hipStream_t s) {
+  const double limit_s = 4.0 * (double)ctx->cfg.timeout_ns * 1e-9 + 30.0;
+  auto t0 = std::chrono::steady_clock::now();
+  bool raised = false;
+  for (;;) {
+    hipError_t e = hipStreamQuery(s);
+    if (e == hipSuccess) break;
+    if (e != hipErrorNotReady) return fail(ctx, AGILE_EHIP, std::string("hipStreamQuery: ") + hipGetErrorString(e));
+    const double el = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (!raised && el > limit_s) {
+      __atomic_store_n(ctx->abort_host, 1u, __ATOMIC_SEQ_CST);
+      raised = true;
+    }
+    if (raised && el > 2 * limit_s) {
+      ctx->poisoned = true;
+      return fail(ctx, AGILE_ETIMEDOUT, "stream did not drain after the abort flag was raised");
+    }
+    std::this_thread::sleep_for(std::chrono::microseconds(el < 0.01 ? 20 : 500));
+  }
+  return map_device_error(ctx);
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------------ public API
+extern "C" {
+
+const char* agile_status_string(agile_status s) {
+  switch (s) {
+    case AGILE_OK: return "AGILE_OK";
+    case AGILE_EINVAL: return "AGILE_EINVAL: invalid argument or configuration";
+    case AGILE_ENOMEM: return "AGILE_ENOMEM: allocation failed";
+    case AGILE_EHIP: return "AGILE_EHIP: HIP runtime error";
+    case AGILE_ETIMEDOUT: return "AGILE_ETIMEDOUT: device watchdog timeout";
+    case AGILE_EAGAIN: return "AGILE_EAGAIN: no evictable line; retry";
+    case AGILE_EIO: return "AGILE_EIO: command completed with error status";
+    case AGILE_EPROTO: return "AGILE_EPROTO: queue protocol violation";
+    case AGILE_ESTATE: return "AGILE_ESTATE: call not allowed in this state";
+  }
+  return "unknown agile_status";
+}
+
+const char* agile_last_error(agile_ctx ctx) {
+  return ctx ? ctx->last_error.c_str() : "no context";
+}
+
+void agile_config_default(agile_config* cfg) {
+  if (!cfg) return;
+  memset(cfg, 0, sizeof(*cfg));
+  cfg->struct_size = sizeof(agile_config);
+  cfg->device = 0;
+  cfg->cache_bytes = 1ull << 20;
+  cfg->line_bytes = 4096;
+  cfg->assoc = 8;
+  cfg->num_qp = 1;
+  cfg->qp_depth = 64;
+  cfg->timeout_ns = 10ull * 1000000000ull;
+}
+
+agile_status agile_init(const agile_config* cfg_in, agile_ctx* out) {
+  if (!cfg_in || !out) return AGILE_EINVAL;
+  *out = nullptr;
+  if (cfg_in->struct_size != sizeof(agile_config)) return AGILE_EINVAL;
+  agile_config cfg = *cfg_in;
+  if (cfg.timeout_ns == 0) cfg.timeout_ns = 10ull * 1000000000ull;
+  // ---- validation (no device work before this point)
+  if (cfg.line_bytes < 4096 || !is_pow2(cfg.line_bytes) || cfg.line_bytes > (1u << 26)) return AGILE_EINVAL;
+  if (cfg.cache_bytes == 0 || cfg.cache_bytes % cfg.line_bytes) return AGILE_EINVAL;
+  const uint64_t lines = cfg.cache_bytes / cfg.line_bytes;
+  if (cfg.assoc == 0 || lines < cfg.assoc || lines % cfg.assoc) return AGILE_EINVAL;
+  if (lines > 0xFFFFFFFFull) return AGILE_EINVAL;
+  if (cfg.num_qp == 0 || cfg.num_qp > 1024) return AGILE_EINVAL;
+  if (cfg.qp_depth < 64 || cfg.qp_depth > 65536 || !is_pow2(cfg.qp_depth)) return AGILE_EINVAL;
+  uint32_t n_ctrl = cfg.ctrl_waves ? cfg.ctrl_waves : cfg.num_qp;
+  uint32_t n_cq = cfg.cq_waves ? cfg.cq_waves : (cfg.num_qp + 7) / 8;
+  if (n_ctrl > 4096 || n_cq > 1024) return AGILE_EINVAL;
+  if ((uint64_t)n_cq * 64 < cfg.num_qp) return AGILE_EINVAL;  // <= 64 CQs per polling wave
+  if (n_cq > cfg.num_qp) n_cq = cfg.num_qp;
+
+  agile_ctx ctx = new agile_ctx_s();
+  ctx->cfg = cfg;
+  ctx->occ_cache.assign(KIND_N, 0);
+  auto bail = [&](agile_status s) {
+    agile_shutdown(ctx);
+    return s;
+  };
+  if (hipSetDevice(cfg.device) != hipSuccess) {
+    (void)hipGetLastError();
+    delete ctx;
+    return AGILE_EHIP;
+  }
+  int cus = 0, wclk_khz = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, cfg.device) != hipSuccess ||
+      hipDeviceGetAttribute(&wclk_khz, hipDeviceAttributeWallClockRate, cfg.device) != hipSuccess) {
+    delete ctx;
+    return AGILE_EHIP;
+  }
+  ctx->cu_count = (uint32_t)cus;
+  ctx->clock_hz = (uint64_t)wclk_khz * 1000ull;
+  ctx->n_ctrl = n_ctrl;
+  ctx->n_cq = n_cq;
+  ctx->service_blocks = (n_ctrl + n_cq + WPB - 1) / WPB;
+
+  dev_ctx& d = ctx->d;
+  memset(&d, 0, sizeof(d));
+  d.num_lines = (uint32_t)lines;
+  d.assoc = cfg.assoc;
+  d.num_sets = (uint32_t)(lines / cfg.assoc);
+  d.sets_pow2 = is_pow2(d.num_sets) ? 1u : 0u;
+  d.line_shift = log2u(cfg.line_bytes);
+  d.blocks_per_line = cfg.line_bytes / 4096;
+  d.num_qp = cfg.num_qp;
+  d.depth = cfg.qp_depth;
+  d.depth_shift = log2u(cfg.qp_depth);
+  d.lat_ticks = (uint64_t)((double)cfg.latency_ns * 1e-9 * (double)ctx->clock_hz + 0.5);
+  d.tok_fp = cfg.iops_cap ? (uint64_t)((double)ctx->clock_hz / (double)cfg.iops_cap * 4294967296.0) : 0;
+  d.timeout_ticks = (uint64_t)((double)cfg.timeout_ns * 1e-9 * (double)ctx->clock_hz);
+  d.flags = cfg.flags;
+
+  agile_status s;
+  const uint64_t nq = (uint64_t)cfg.num_qp * cfg.qp_depth;
+  if ((s = dalloc(ctx, &d.lines, cfg.cache_bytes)) != AGILE_OK) return bail(s);
+  if ((s = dalloc(ctx, &d.meta, lines * 8)) != AGILE_OK) return bail(s);
+  if ((s = dalloc(ctx, &d.hand, (uint64_t)d.num_sets * 4)) != AGILE_OK) return bail(s);
+  if ((s = dalloc(ctx, &d.set_lock, (uint64_t)d.num_sets * 4)) != AGILE_OK) return bail(s);
+  if ((s = dalloc(ctx, &d.sq, nq * sizeof(sqe_t))) != AGILE_OK) return bail(s);
+  if ((s = dalloc(ctx, &d.cq, nq * sizeof(cqe_t))) != AGILE_OK) return bail(s);
+  if ((s = dalloc(ctx, &d.slot, nq * 4)) != AGILE_OK) return bail(s);
+  if ((s = dalloc(ctx, &d.qp, (uint64_t)cfg.num_qp * sizeof(qp_t))) != AGILE_OK) return bail(s);
+  if ((s = dalloc(ctx, &d.next_tok, 128)) != AGILE_OK) return bail(s);
+  if ((s = dalloc(ctx, &d.cnt, (uint64_t)C_COUNT * CSTRIDE * 8)) != AGILE_OK) return bail(s);
+  if ((s = dalloc(ctx, &d.err, 128)) != AGILE_OK) return bail(s);
+  if ((s = dalloc(ctx, &d.err_info, 128)) != AGILE_OK) return bail(s);
+  void* ab = nullptr;
+  if (hipHostMalloc(&ab, 4096, hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess) {
+    (void)hipGetLastError();
+    return bail(AGILE_ENOMEM);
+  }
+  ctx->abort_host = (uint32_t*)ab;
+  *ctx->abort_host = 0;
+  void* abd = nullptr;
+  if (hipHostGetDevicePointer(&abd, ab, 0) != hipSuccess) return bail(AGILE_EHIP);
+  d.abort_flag = (uint32_t*)abd;
+
+  // zero state; SQ slot s starts as EMPTY for ticket s
+  if (hipMemset(d.meta, 0, lines * 8) != hipSuccess || hipMemset(d.hand, 0, (uint64_t)d.num_sets * 4) != hipSuccess ||
+      hipMemset(d.set_lock, 0, (uint64_t)d.num_sets * 4) != hipSuccess ||
+      hipMemset(d.sq, 0, nq * sizeof(sqe_t)) != hipSuccess || hipMemset(d.cq, 0, nq * sizeof(cqe_t)) != hipSuccess ||
+      hipMemset(d.qp, 0, (uint64_t)cfg.num_qp * sizeof(qp_t)) != hipSuccess || hipMemset(d.next_tok, 0, 128) != hipSuccess ||
+      hipMemset(d.cnt, 0, (uint64_t)C_COUNT * CSTRIDE * 8) != hipSuccess || hipMemset(d.err, 0, 128) != hipSuccess ||
+      hipMemset(d.err_info, 0, 128) != hipSuccess)
+    return bail(AGILE_EHIP);
+  std::vector<uint32_t> slots(nq);
+  for (uint64_t i = 0; i < nq; ++i) slots[i] = (uint32_t)((i % cfg.qp_depth) << 2) | SLOT_EMPTY;
+  if (hipMemcpy(d.slot, slots.data(), nq * 4, hipMemcpyHostToDevice) != hipSuccess) return bail(AGILE_EHIP);
+  if (hipDeviceSynchronize() != hipSuccess) return bail(AGILE_EHIP);
+  *out = ctx;
+  return AGILE_OK;
+}
+
+agile_status agile_shutdown(agile_ctx ctx) {
+  if (!ctx) return AGILE_EINVAL;
+  (void)hipDeviceSynchronize();
+  for (void* p : ctx->dev_allocs) (void)hipFree(p);
+  if (ctx->abort_host) (void)hipHostFree(ctx->abort_host);
+  delete ctx->store;
+  delete ctx;
+  return AGILE_OK;
+}
+
+agile_status agile_host_alloc(uint64_t bytes, void** out) {
+  if (!out || bytes == 0) return AGILE_EINVAL;
+  *out = nullptr;
+  if (hipHostMalloc(out, bytes, hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess) {
+    (void)hipGetLastError();
+    return AGILE_ENOMEM;
+  }
+  return AGILE_OK;
+}
+
+agile_status agile_host_free(void* p) {
+  if (!p) return AGILE_EINVAL;
+  return hipHostFree(p) == hipSuccess ? AGILE_OK : AGILE_EHIP;
+}
+
+agile_status agile_open_store(agile_ctx ctx, void* host_image, uint64_t bytes, uint32_t block_bytes,
+                              uint32_t flags, agile_store* out) {
+  agile_status s = check_usable(ctx);
+  if (s) return s;
+  if (!host_image || !out || block_bytes != 4096 || bytes == 0 || bytes % block_bytes)
+    return fail(ctx, AGILE_EINVAL, "open_store: image must be non-null, block_bytes 4096, bytes a multiple of it");
+  (void)flags;
+  if (ctx->store) return fail(ctx, AGILE_ESTATE, "open_store: a store is already open on this context");
+  if ((bytes / 4096) / ctx->d.blocks_per_line >= 0xFFFFFFFFull)
+    return fail(ctx, AGILE_EINVAL, "open_store: store too large for 32-bit line ids");
+  hipPointerAttribute_t attr;
+  memset(&attr, 0, sizeof(attr));
+  if (hipPointerGetAttributes(&attr, host_image) != hipSuccess || attr.type != hipMemoryTypeHost ||
+      attr.devicePointer == nullptr) {
+    (void)hipGetLastError();
+    return fail(ctx, AGILE_EINVAL, "open_store: image is not pinned, device-mapped host memory");
+  }
+  uint8_t* dev = (uint8_t*)attr.devicePointer + ((uint8_t*)host_image - (uint8_t*)attr.hostPointer);
+  agile_store st = new agile_store_s();
+  st->host = host_image;
+  st->dev = dev;
+  st->bytes = bytes;
+  st->blocks = bytes / 4096;
+  ctx->store = st;
+  bind_store(ctx);
+  *out = st;
+  return AGILE_OK;
+}
+
+agile_status agile_sync(agile_ctx ctx, void* stream) {
+  if (!ctx) return AGILE_EINVAL;
+  return sync_stream(ctx, (hipStream_t)stream);
+}
+
+agile_status agile_invalidate(agile_ctx ctx, agile_store store, void* stream) {
+  agile_status s = check_usable(ctx);
+  if (s) return s;
+  if (store != ctx->store) return fail(ctx, AGILE_EINVAL, "invalidate: store is not open on this context");
+  hipStream_t hs = (hipStream_t)stream;
+  uint64_t waves = std::max<uint64_t>((std::max<uint64_t>(ctx->d.num_lines, ctx->d.num_sets) + 63) / 64, 1);
+  waves = (waves + WPB - 1) / WPB * WPB;
+  launch_t li = make_launch(ctx, (uint32_t)waves, false, 0);
+  hipLaunchKernelGGL(k_invalidate, dim3((uint32_t)(waves / WPB)), dim3(WG), 0, hs, ctx->d, li);
+  HIPCHK(ctx, hipGetLastError());
+  return sync_stream(ctx, hs);
+}
+
+agile_status agile_close_store(agile_ctx ctx, agile_store store) {
+  if (!ctx || !store || store != ctx->store) return fail(ctx, AGILE_EINVAL, "close_store: unknown store");
+  agile_status s = AGILE_OK;
+  if (!ctx->poisoned) {
+    s = sync_stream(ctx, nullptr);
+    if (s == AGILE_OK) {
+      HIPCHK(ctx, hipDeviceSynchronize());
+      // drop clean lines; dirty lines are discarded too (documented: flush first)
+      HIPCHK(ctx, hipMemset(ctx->d.meta, 0, (uint64_t)ctx->d.num_lines * 8));
+      HIPCHK(ctx, hipMemset(ctx->d.hand, 0, (uint64_t)ctx->d.num_sets * 4));
+      HIPCHK(ctx, hipDeviceSynchronize());
+    }
+  }
+  ctx->store = nullptr;
+  bind_store(ctx);
+  delete store;
+  return s;
+}
+
+agile_status agile_async_read(agile_ctx ctx, agile_store store, const uint64_t* d_blocks, uint32_t n,
+                              agile_ticket* d_tickets, void* stream) {
+  agile_status s = check_usable(ctx);
+  if (s) return s;
+  if (store != ctx->store) return fail(ctx, AGILE_EINVAL, "async_read: store is not open on this context");
+  if (n == 0) return AGILE_OK;
+  if (!d_blocks || !d_tickets) return fail(ctx, AGILE_EINVAL, "async_read: null pointer");
+  uint32_t uw = std::min<uint32_t>((n + 63) / 64, user_wave_cap(ctx, KIND_READ));
+  uw = (uw + WPB - 1) / WPB * WPB;
+  launch_t li = make_launch(ctx, uw, true, 0);
+  hipLaunchKernelGGL(k_async_read, dim3(li.service_blocks + uw / WPB), dim3(WG), 0, (hipStream_t)stream,
+                     ctx->d, li, d_blocks, n, d_tickets);
+  HIPCHK(ctx, hipGetLastError());
+  return AGILE_OK;
+}
+
+agile_status agile_wait(agile_ctx ctx, const agile_ticket* d_tickets, uint32_t n, void** d_ptrs, void* stream) {
+  agile_status s = check_usable(ctx);
+  if (s) return s;
+  if (n && (!d_tickets || !d_ptrs)) return fail(ctx, AGILE_EINVAL, "wait: null pointer");
+  hipStream_t hs = (hipStream_t)stream;
+  uint64_t e0 = 0;
+  HIPCHK(ctx, hipMemcpy(&e0, ctx->d.cnt + (size_t)C_AUX0 * CSTRIDE, 8, hipMemcpyDeviceToHost));
+  if (n) {
+    uint32_t uw = (n + 63) / 64;
+    uw = (uw + WPB - 1) / WPB * WPB;
+    launch_t li = make_launch(ctx, uw, false, 0);
+    hipLaunchKernelGGL(k_wait, dim3(uw / WPB), dim3(WG), 0, hs, ctx->d, li, d_tickets, n, d_ptrs);
+    HIPCHK(ctx, hipGetLastError());
+  }
+  s = sync_stream(ctx, hs);
+  if (s) return s;
+  uint64_t e1 = 0;
+  HIPCHK(ctx, hipMemcpy(&e1, ctx->d.cnt + (size_t)C_AUX0 * CSTRIDE, 8, hipMemcpyDeviceToHost));
+  return e1 != e0 ? fail(ctx, AGILE_EAGAIN, "wait: some tickets carried EAGAIN") : AGILE_OK;
+}
+
+agile_status agile_release(agile_ctx ctx, const agile_ticket* d_tickets, uint32_t n, void* stream) {
+  agile_status s = check_usable(ctx);
+  if (s) return s;
+  if (n == 0) return AGILE_OK;
+  if (!d_tickets) return fail(ctx, AGILE_EINVAL, "release: null pointer");
+  uint32_t uw = (n + 63) / 64;
+  uw = (uw + WPB - 1) / WPB * WPB;
+  launch_t li = make_launch(ctx, uw, false, 0);
+  hipLaunchKernelGGL(k_release, dim3(uw / WPB), dim3(WG), 0, (hipStream_t)stream, ctx->d, li, d_tickets, n);
+  HIPCHK(ctx, hipGetLastError());
+  return AGILE_OK;
+}
+
+agile_status agile_flush(agile_ctx ctx, agile_store store, void* stream) {
+  agile_status s = check_usable(ctx);
+  if (s) return s;
+  if (store != ctx->store) return fail(ctx, AGILE_EINVAL, "flush: store is not open on this context");
+  hipStream_t hs = (hipStream_t)stream;
+  uint32_t uw = std::min<uint32_t>((ctx->d.num_lines + 63) / 64, user_wave_cap(ctx, KIND_FLUSH));
+  uw = (uw + WPB - 1) / WPB * WPB;
+  launch_t li = make_launch(ctx, uw, true, 0);
+  hipLaunchKernelGGL(k_flush, dim3(li.service_blocks + uw / WPB), dim3(WG), 0, hs, ctx->d, li);
+  HIPCHK(ctx, hipGetLastError());
+  return sync_stream(ctx, hs);
+}
+
+agile_status agile_get_stats(agile_ctx ctx, agile_stats* out, int reset) {
+  if (!ctx || !out) return AGILE_EINVAL;
+  std::vector<uint64_t> c((size_t)C_COUNT * CSTRIDE);
+  HIPCHK(ctx, hipDeviceSynchronize());
+  HIPCHK(ctx, hipMemcpy(c.data(), ctx->d.cnt, c.size() * 8, hipMemcpyDeviceToHost));
+  auto g = [&](uint32_t i) { return c[(size_t)i * CSTRIDE]; };
+  out->requests = g(C_REQUESTS);
+  out->hits = g(C_HITS);
+  out->misses = g(C_MISSES);
+  out->read_cmds = g(C_READS);
+  out->write_cmds = g(C_WRITES);
+  out->wb_evict = g(C_WB_EVICT);
+  out->wb_flush = g(C_WB_FLUSH);
+  out->eagain = g(C_EAGAIN);
+  out->sq_spins = g(C_SQ_SPINS);
+  out->ctrl_cmds = g(C_CTRL_CMDS);
+  out->cq_entries = g(C_CQ_ENTRIES);
+  out->submitted = g(C_SUBMITTED);
+  out->completed = g(C_COMPLETED);
+  out->consumed = g(C_AUX1);
+  if (reset) {
+    const uint32_t keep[] = {C_SUBMITTED, C_COMPLETED, C_USER_DONE, C_WORK};
+    for (uint32_t i = 0; i < C_COUNT; ++i) {
+      if (std::find(std::begin(keep), std::end(keep), i) != std::end(keep)) continue;
+      HIPCHK(ctx, hipMemset(ctx->d.cnt + (size_t)i * CSTRIDE, 0, 8));
+    }
+    HIPCHK(ctx, hipDeviceSynchronize());
+  }
+  return AGILE_OK;
+}
+
+agile_status agile_get_info(agile_ctx ctx, agile_info* out) {
+  if (!ctx || !out) return AGILE_EINVAL;
+  out->num_lines = ctx->d.num_lines;
+  out->num_sets = ctx->d.num_sets;
+  out->assoc = ctx->d.assoc;
+  out->line_bytes = ctx->cfg.line_bytes;
+  out->num_qp = ctx->d.num_qp;
+  out->qp_depth = ctx->d.depth;
+  out->ctrl_waves = ctx->n_ctrl;
+  out->cq_waves = ctx->n_cq;
+  out->cu_count = ctx->cu_count;
+  out->max_user_waves = user_wave_cap(ctx, KIND_EMBBAG2);
+  out->wallclock_hz = ctx->clock_hz;
+  out->cache_base = (uint64_t)(uintptr_t)ctx->d.lines;
+  return AGILE_OK;
+}
+
+static agile_status embbag_launch(agile_ctx ctx, agile_store store, const agile_tables* tb, const int64_t* d_idx,
+                                  const int64_t* d_off, uint64_t B, uint64_t n, uint32_t K, uint32_t mode,
+                                  float* d_out, void* stream, bool gather) {
+  agile_status s = check_usable(ctx);
+  if (s) return s;
+  if (store != ctx->store) return fail(ctx, AGILE_EINVAL, "workload: store is not open on this context");
+  // d_idx may be NULL when every bag is empty (it is only read for existing lookups)
+  if (!tb || !d_out || (!gather && !d_off)) return fail(ctx, AGILE_EINVAL, "workload: null pointer");
+  if (tb->dim == 0 || tb->dim > 256 || tb->num_tables == 0 || tb->rows == 0)
+    return fail(ctx, AGILE_EINVAL, "workload: dim must be 1..256, tables and rows non-zero");
+  const uint64_t row_bytes = (uint64_t)tb->dim * 4;
+  if (4096 % row_bytes) return fail(ctx, AGILE_EINVAL, "workload: row bytes must divide 4096");
+  if (tb->base_offset % row_bytes) return fail(ctx, AGILE_EINVAL, "workload: base_offset must be row aligned");
+  const uint64_t table_bytes = tb->rows * row_bytes;
+  if (tb->base_offset + table_bytes * tb->num_tables > store->bytes)
+    return fail(ctx, AGILE_EINVAL, "workload: tables exceed the store");
+  if (mode > AGILE_MODE_ASYNC) return fail(ctx, AGILE_EINVAL, "workload: bad mode");
+  embbag_args a{};
+  a.idx = d_idx;
+  a.off = d_off;
+  a.out = d_out;
+  a.nbags = gather ? (n + 63) / 64 : B * tb->num_tables;
+  a.n = n;
+  a.rows = tb->rows;
+  a.base_off = tb->base_offset;
+  a.table_bytes = table_bytes;
+  a.T = tb->num_tables;
+  a.dim = tb->dim;
+  a.row_bytes = (uint32_t)row_bytes;
+  a.K = K;
+  a.mode = mode;
+  a.gather = gather ? 1u : 0u;
+  if (a.nbags == 0) return AGILE_OK;
+  const int kind = tb->dim <= 64 ? KIND_EMBBAG1 : (tb->dim <= 128 ? KIND_EMBBAG2 : KIND_EMBBAG4);
+  uint32_t uw, active;
+  if (ctx->cfg.flags & AGILE_F_SERIALIZED) {
+    uw = WPB;
+    active = 1;
+  } else {
+    // admission: a wave pins at most two chunks of 64 lines (the current and, in
+    // asynchronous mode, the next), and the waves' pins together must fit in the cache;
+    // both modes get the same wave count
+    const uint64_t by_cache = std::max<uint64_t>(1, ctx->d.num_lines / 128);
+    active = (uint32_t)std::min<uint64_t>({a.nbags, (uint64_t)user_wave_cap(ctx, kind), by_cache});
+    uw = (active + WPB - 1) / WPB * WPB;
+  }
+  a.active_waves = active;
+  const bool serial = (ctx->cfg.flags & AGILE_F_SERIALIZED) != 0;
+  launch_t li = make_launch(ctx, uw, true, serial ? 0 : a.nbags + active);
+  const dim3 grid(li.service_blocks + uw / WPB);
+  hipStream_t hs = (hipStream_t)stream;
+  if (kind == KIND_EMBBAG1)
+    hipLaunchKernelGGL(k_embbag<1>, grid, dim3(WG), 0, hs, ctx->d, li, a);
+  else if (kind == KIND_EMBBAG2)
+    hipLaunchKernelGGL(k_embbag<2>, grid, dim3(WG), 0, hs, ctx->d, li, a);
+  else
+    hipLaunchKernelGGL(k_embbag<4>, grid, dim3(WG), 0, hs, ctx->d, li, a);
+  HIPCHK(ctx, hipGetLastError());
+  return AGILE_OK;
+}
+
+agile_status agile_gather(agile_ctx ctx, agile_store store, const agile_tables* tb, const int64_t* d_idx,
+                          uint64_t n, uint32_t mode, float* d_out, void* stream) {
+  if (n == 0) return check_usable(ctx);
+  return embbag_launch(ctx, store, tb, d_idx, nullptr, 0, n, 0, mode, d_out, stream, true);
+}
+
+agile_status agile_embbag_forward(agile_ctx ctx, agile_store store, const agile_tables* tb, const int64_t* d_idx,
+                                  const int64_t* d_off, uint64_t B, uint32_t K, uint32_t mode, float* d_out,
+                                  void* stream) {
+  if (B == 0) return check_usable(ctx);
+  return embbag_launch(ctx, store, tb, d_idx, d_off, B, 0, K, mode, d_out, stream, false);
+}
+
+// ---- diagnostics used by tests (declared in agile.h)
+agile_status agile_debug_trace(agile_ctx ctx, agile_store store, const uint64_t* d_lines, const uint8_t* d_writes,
+                               uint64_t n, uint8_t* d_hit, int32_t* d_way, void* stream) {
+  agile_status s = check_usable(ctx);
+  if (s) return s;
+  if (store != ctx->store) return fail(ctx, AGILE_EINVAL, "trace: store is not open on this context");
+  if (n == 0) return AGILE_OK;
+  if (!d_lines || !d_hit || !d_way) return fail(ctx, AGILE_EINVAL, "trace: null pointer");
+  launch_t li = make_launch(ctx, WPB, true, 0);
+  hipLaunchKernelGGL(k_trace, dim3(li.service_blocks + 1), dim3(WG), 0, (hipStream_t)stream, ctx->d, li, d_lines,
+                     d_writes, n, d_hit, d_way);
+  HIPCHK(ctx, hipGetLastError());
+  return sync_stream(ctx, (hipStream_t)stream);
+}
+
+agile_status agile_debug_counters(agile_ctx ctx, uint64_t* out, uint32_t n) {
+  if (!ctx || !out) return AGILE_EINVAL;
+  std::vector<uint64_t> c((size_t)C_COUNT * CSTRIDE);
+  HIPCHK(ctx, hipDeviceSynchronize());
+  HIPCHK(ctx, hipMemcpy(c.data(), ctx->d.cnt, c.size() * 8, hipMemcpyDeviceToHost));
+  for (uint32_t i = 0; i < n; ++i) out[i] = i < C_COUNT ? c[(size_t)i * CSTRIDE] : 0;
+  return AGILE_OK;
+}
+
+agile_status agile_debug_dump(agile_ctx ctx, int64_t* d_tags, uint8_t* d_states, uint32_t* d_rc, void* stream) {
+  if (!ctx || !d_tags || !d_states || !d_rc) return AGILE_EINVAL;
+  const uint32_t nb = (ctx->d.num_lines + 255) / 256;
+  hipLaunchKernelGGL(k_dump, dim3(nb), dim3(256), 0, (hipStream_t)stream, ctx->d, d_tags, d_states, d_rc);
+  HIPCHK(ctx, hipGetLastError());
+  HIPCHK(ctx, hipStreamSynchronize((hipStream_t)stream));
+  return AGILE_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,942 @@
+// agile_dev.hpp - device side of the block-I/O path for gfx950 (wave64, 8 XCDs).
+//
+// Contents, bottom-up:
+//   * memory-model helpers (agent scope = every XCD of the device),
+//   * wavefront helpers (ballot / mbcnt / readlane),
+//   * NVMe-style queue pair: 64-byte SQE, 16-byte CQE, lap-tagged slot states,
+//   * wavefront-aggregated submission with the doorbell serialisation of Alg. 2,
+//   * the emulated NVMe controller (service wavefronts, latency + IOPS cap),
+//   * the completion service (Alg. 1, one 64-entry window per wavefront),
+//   * the cache line state machine of Sec. 3.4 with clock replacement,
+//   * the wavefront-level "request chunk" API used by every workload kernel.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ag {
+
+// ------------------------------------------------------------------ memory model
+template <class T>
+__device__ __forceinline__ T ld_acq(const T* p) {
+  return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <class T>
+__device__ __forceinline__ T ld_rlx(const T* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <class T, class U>
+__device__ __forceinline__ void st_rel(T* p, U v) {
+  __hip_atomic_store(p, (T)v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <class T, class U>
+__device__ __forceinline__ void st_rlx(T* p, U v) {
+  __hip_atomic_store(p, (T)v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <class T, class U>
+__device__ __forceinline__ T add_rlx(T* p, U v) {
+  return __hip_atomic_fetch_add(p, (T)v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <class T, class U>
+__device__ __forceinline__ T add_acqrel(T* p, U v) {
+  return __hip_atomic_fetch_add(p, (T)v, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <class T, class U>
+__device__ __forceinline__ T add_rel(T* p, U v) {
+  return __hip_atomic_fetch_add(p, (T)v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <class T, class U>
+__device__ __forceinline__ bool cas(T* p, T& expected, U desired) {
+  return __hip_atomic_compare_exchange_strong(p, &expected, (T)desired, __ATOMIC_ACQ_REL,
+                                              __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <class T, class U>
+__device__ __forceinline__ T and_rlx(T* p, U v) {
+  return __hip_atomic_fetch_and(p, (T)v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <class T, class U>
+__device__ __forceinline__ T or_rlx(T* p, U v) {
+  return __hip_atomic_fetch_or(p, (T)v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void fence_acq() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent"); }
+__device__ __forceinline__ void fence_rel() { __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent"); }
+__device__ __forceinline__ void fence_rel_sys() { __builtin_amdgcn_fence(__ATOMIC_RELEASE, ""); }
+// Completes this wave's outstanding loads before a following relaxed atomic; enough to
+// retire read-only pins (no stores need publishing).
+__device__ __forceinline__ void loads_done() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+}
+
+__device__ __forceinline__ uint64_t now() { return __builtin_amdgcn_s_memrealtime(); }
+
+// ------------------------------------------------------------------ wave64 helpers
+__device__ __forceinline__ uint32_t lane() { return __lane_id(); }
+__device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
+__device__ __forceinline__ uint32_t mbcnt(uint64_t m) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+__device__ __forceinline__ uint32_t rdlane(uint32_t v, uint32_t l) {
+  return (uint32_t)__builtin_amdgcn_readlane((int)v, (int)l);
+}
+__device__ __forceinline__ uint64_t rdlane64(uint64_t v, uint32_t l) {
+  return ((uint64_t)rdlane((uint32_t)(v >> 32), l) << 32) | rdlane((uint32_t)v, l);
+}
+// Makes a value wave-uniform (every lane takes the first active lane's value).
+__device__ __forceinline__ uint32_t uni(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_readfirstlane((int)v);
+}
+__device__ __forceinline__ uint64_t uni64(uint64_t v) {
+  return ((uint64_t)uni((uint32_t)(v >> 32)) << 32) | uni((uint32_t)v);
+}
+__device__ __forceinline__ uint32_t ffs64(uint64_t m) { return (uint32_t)__builtin_ctzll(m); }
+__device__ __forceinline__ uint32_t shfl32(uint32_t v, uint32_t src) {
+  return (uint32_t)__shfl((int)v, (int)src, 64);
+}
+
+// ------------------------------------------------------------------ shared layouts
+// Cache line metadata word:
+//   bits 0-2 state, bit 3 clock reference bit, bits 4-23 pin count,
+//   bits 24-31 generation (bumped on every refill), bits 32-63 tag (line id in store).
+enum : uint32_t { ST_INVALID = 0, ST_FETCHING = 1, ST_READY = 2, ST_DIRTY = 3, ST_WRITEBACK = 4 };
+constexpr uint64_t M_STATE = 7ull, M_REF = 8ull, RC_ONE = 1ull << 4, RC_MASK = 0xFFFFFull << 4;
+constexpr uint32_t GEN_SHIFT = 24, TAG_SHIFT = 32;
+__device__ __forceinline__ uint32_t m_state(uint64_t m) { return (uint32_t)(m & M_STATE); }
+__device__ __forceinline__ uint32_t m_rc(uint64_t m) { return (uint32_t)((m & RC_MASK) >> 4); }
+__device__ __forceinline__ uint32_t m_gen(uint64_t m) { return (uint32_t)(m >> GEN_SHIFT) & 0xFF; }
+__device__ __forceinline__ uint32_t m_tag(uint64_t m) { return (uint32_t)(m >> TAG_SHIFT); }
+__device__ __forceinline__ bool m_valid_data(uint32_t st) {
+  return st == ST_READY || st == ST_DIRTY || st == ST_WRITEBACK;
+}
+
+// Slot state word of an SQ entry: (ticket << 2) | state, modulo 2^32.  The ticket is the
+// lap-unique sequence number of the command that owns (or may next own) the slot.
+enum : uint32_t { SLOT_EMPTY = 0, SLOT_UPDATED = 1, SLOT_ISSUED = 2 };
+
+// NVM command set opcodes.
+enum : uint32_t { OPC_WRITE = 0x01, OPC_READ = 0x02 };
+
+// 64-byte submission entry with the field positions of an NVMe command: CDW0 holds the
+// opcode and the command identifier (CID = slot index), PRP1 the HBM line address,
+// CDW10-11 the starting block (SLBA), CDW12 bits 0-15 the block count minus one.  CDW2
+// (reserved in NVMe) carries the cache line index so the completion can find it.
+struct alignas(64) sqe_t {
+  uint32_t cdw0, nsid, cdw2, cdw3;
+  uint64_t mptr, prp1, prp2, slba;
+  uint32_t cdw12, cdw13, cdw14, cdw15;
+};
+// 16-byte completion entry: DW0 command specific (the cache line index), DW1 the opcode,
+// DW2 SQ head | SQ id << 16, DW3 CID | phase << 16 | status << 17.
+struct alignas(16) cqe_t {
+  uint32_t dw0, dw1, dw2, dw3;
+};
+
+// Per queue pair control words, one 128-byte segment per writer group.
+struct alignas(128) qp_t {
+  uint32_t ticket;            // submitters: next reservation
+  uint32_t _p0[31];
+  uint32_t db;                // SQ tail doorbell (written under db_lock)
+  uint32_t db_lock;
+  uint32_t _p1[30];
+  uint32_t fetch;             // controller: next SQE to fetch
+  uint32_t cq_tail;           // controller: next CQ slot to post
+  uint32_t _p2[30];
+  uint32_t cq_head;           // completion service: CQ head doorbell (window start)
+  uint32_t cq_mask_lo, cq_mask_hi;  // completion service: window mask kept between launches
+  uint32_t _p3[29];
+};
+
+// Counters, one 128-byte segment each.
+enum : uint32_t {
+  C_SUBMITTED = 0, C_COMPLETED, C_USER_DONE, C_WORK, C_REQUESTS, C_HITS, C_MISSES, C_READS,
+  C_WRITES, C_WB_EVICT, C_WB_FLUSH, C_EAGAIN, C_SQ_SPINS, C_CTRL_CMDS, C_CQ_ENTRIES, C_AUX0,
+  C_AUX1, C_SVC_START, C_CTRL_FETCH, C_CTRL_LOOPS, C_CQ_LOOPS, C_COUNT
+};
+constexpr uint32_t CSTRIDE = 16;  // u64 per counter
+
+// Device error codes (mapped to agile_status on the host).
+enum : uint32_t { E_NONE = 0, E_TIMEDOUT = 1, E_IO = 2, E_PROTO = 3, E_STATE = 4 };
+
+struct dev_ctx {
+  // cache
+  uint8_t* lines;
+  uint64_t* meta;
+  uint32_t* hand;
+  uint32_t* set_lock;
+  uint32_t num_lines, num_sets, assoc, line_shift;
+  uint32_t sets_pow2, blocks_per_line;
+  // queues
+  sqe_t* sq;
+  cqe_t* cq;
+  uint32_t* slot;
+  qp_t* qp;
+  uint32_t num_qp, depth, depth_shift, _q0;
+  // store (4 KiB blocks)
+  uint8_t* image;
+  uint64_t store_blocks;
+  // emulator
+  uint64_t lat_ticks;
+  uint64_t tok_fp;  // ticks per command, 32.32 fixed point; 0 = no cap
+  uint64_t* next_tok;
+  // control
+  uint64_t* cnt;
+  uint32_t* err;
+  uint32_t* abort_flag;
+  uint64_t* err_info;
+  uint64_t timeout_ticks;
+  uint32_t flags;
+  uint32_t _c0;
+};
+
+struct launch_t {
+  uint32_t service_blocks;  // leading workgroups that run service wavefronts
+  uint32_t n_ctrl, n_cq;    // controller / completion wavefronts
+  uint32_t user_waves;      // user wavefronts in this launch
+  uint64_t user_done_target;
+  uint64_t work_base;
+  uint32_t prio;            // raise service issue priority
+  uint32_t _l0;
+};
+
+constexpr uint32_t WG = 256;  // threads per workgroup: 4 wavefronts
+constexpr uint32_t WPB = WG / 64;
+
+__device__ __forceinline__ uint64_t* counter(const dev_ctx& c, uint32_t i) {
+  return c.cnt + (size_t)i * CSTRIDE;
+}
+__device__ __forceinline__ void count(const dev_ctx& c, uint32_t i, uint64_t v) {
+  if (v) add_rlx(counter(c, i), v);
+}
+// The abort flag lives in pinned host memory so that the host can also raise it while
+// kernels run (host-side watchdog); it is read with system scope.
+__device__ __forceinline__ bool aborted(const dev_ctx& c) {
+  return uni(__hip_atomic_load(c.abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM)) != 0;
+}
+__device__ __noinline__ void raise_error(const dev_ctx& c, uint32_t code, uint64_t info) {
+  uint32_t z = 0;
+  if (cas(c.err, z, code)) st_rlx(c.err_info, info);
+  __hip_atomic_store(c.abort_flag, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+// Bounded spin helper: returns false (and raises E_TIMEDOUT) when the deadline passes or
+// the context is aborted.
+struct spin_t {
+  uint64_t t0;
+  uint32_t n;
+  __device__ spin_t() : t0(now()), n(0) {}
+  __device__ __forceinline__ bool step(const dev_ctx& c, uint64_t info) {
+    ++n;
+    if (n < 8) {
+      __builtin_amdgcn_s_sleep(1);
+    } else {
+      __builtin_amdgcn_s_sleep(8);
+    }
+    if ((n & 15) == 0) {
+      if (aborted(c)) return false;
+      if (now() - t0 > c.timeout_ticks) {
+        if (lane() == ffs64(ballot(true))) raise_error(c, E_TIMEDOUT, info);
+        return false;
+      }
+    }
+    return true;
+  }
+};
+
+__device__ __forceinline__ uint32_t set_of(const dev_ctx& c, uint32_t line_id) {
+  return c.sets_pow2 ? (line_id & (c.num_sets - 1)) : (line_id % c.num_sets);
+}
+__device__ __forceinline__ uint8_t* line_ptr(const dev_ctx& c, uint32_t idx) {
+  return c.lines + ((uint64_t)idx << c.line_shift);
+}
+
+// ------------------------------------------------------------------ submission (Alg. 2)
+// Wavefront-aggregated: the lanes with `want` reserve consecutive tickets of SQ `q` with
+// one atomic, then every lane waits until its slot's previous lap is EMPTY, writes its
+// 64-byte command and marks the slot UPDATED.  While any of its commands is unissued the
+// wave also tries the doorbell lock; the holder scans forward 64 slots at a time,
+// turning UPDATED slots of the expected lap into ISSUED until the first slot that is not
+// (an unwritten or empty entry), then stores the new tail into the doorbell.  The wave
+// returns once its last ticket is behind the doorbell.  Returns false on abort/timeout.
+__device__ bool submit(const dev_ctx& c, uint32_t q, bool want, uint32_t opc, uint32_t line_idx,
+                       uint64_t slba, uint32_t nblk) {
+  const uint64_t m = ballot(want);
+  if (!m) return true;
+  const uint32_t n = __popcll(m);
+  const uint32_t rank = mbcnt(m);
+  qp_t* qs = c.qp + q;
+  uint32_t base = 0;
+  if (lane() == ffs64(m)) {
+    base = add_rlx(&qs->ticket, n);
+    add_rlx(counter(c, C_SUBMITTED), (uint64_t)n);
+    add_rlx(counter(c, opc == OPC_READ ? C_READS : C_WRITES), (uint64_t)n);
+  }
+  base = rdlane(base, ffs64(m));
+  const uint32_t T = base + rank;
+  const uint32_t dmask = c.depth - 1;
+  const uint32_t s = T & dmask;
+  uint32_t* slots = c.slot + (size_t)q * c.depth;
+  bool written = !want;
+  spin_t sp;
+  uint32_t spins = 0;
+  for (;;) {
+    bool progress = false;
+    if (!written) {
+      if (ld_acq(slots + s) == ((T << 2) | SLOT_EMPTY)) {
+        sqe_t* e = c.sq + (size_t)q * c.depth + s;
+        uint4* w = reinterpret_cast<uint4*>(e);
+        const uint64_t prp1 = (uint64_t)(uintptr_t)line_ptr(c, line_idx);
+        w[0] = make_uint4(opc | (s << 16), 1u, line_idx, T);
+        w[1] = make_uint4(0u, 0u, (uint32_t)prp1, (uint32_t)(prp1 >> 32));
+        w[2] = make_uint4(0u, 0u, (uint32_t)slba, (uint32_t)(slba >> 32));
+        w[3] = make_uint4(nblk - 1, 0u, 0u, 0u);
+        st_rel(slots + s, (T << 2) | SLOT_UPDATED);
+        written = true;
+        progress = true;
+      }
+    }
+    progress = ballot(progress) != 0;
+    const uint32_t db = uni(ld_acq(&qs->db));
+    if ((int32_t)(db - (base + n)) >= 0) break;  // every command of this wave is issued
+    if (ballot(written && want)) {
+      uint32_t got = 0;
+      if (lane() == 0) {
+        uint32_t z = 0;
+        got = cas(&qs->db_lock, z, 1u) ? 1u : 0u;
+      }
+      got = rdlane(got, 0);
+      if (got) {
+        uint32_t p = ld_acq(&qs->db);
+        const uint32_t p0 = p;
+        for (;;) {
+          const uint32_t t = p + lane();
+          const bool upd = ld_acq(slots + (t & dmask)) == ((t << 2) | SLOT_UPDATED);
+          const uint64_t b = ballot(upd);
+          const uint32_t k = (~b == 0ull) ? 64u : ffs64(~b);
+          if (lane() < k) st_rlx(slots + (t & dmask), (t << 2) | SLOT_ISSUED);
+          p += k;
+          if (k < 64) break;
+        }
+        if (lane() == 0) {
+          if (p != p0) st_rel(&qs->db, p);  // the doorbell write
+          st_rel(&qs->db_lock, 0u);
+        }
+        if (p != p0) progress = true;
+      }
+    }
+    if (!progress) {
+      ++spins;
+      if (!sp.step(c, ((uint64_t)q << 32) | T)) return false;
+    }
+  }
+  if (spins && lane() == 0) count(c, C_SQ_SPINS, spins);
+  return true;
+}
+
+// ------------------------------------------------------------------ service wavefronts
+__device__ __forceinline__ bool service_should_exit(const dev_ctx& c, const launch_t& li) {
+  if (aborted(c)) return true;
+  if (uni64(ld_acq(counter(c, C_USER_DONE))) < li.user_done_target) return false;
+  const uint64_t sub = uni64(ld_acq(counter(c, C_SUBMITTED)));
+  const uint64_t com = uni64(ld_acq(counter(c, C_COMPLETED)));
+  return com == sub;
+}
+
+// Copies two 4 KiB blocks with the whole wave: 16-byte lanes, 1 KiB per instruction,
+// all eight loads issued before the stores.  A null source skips that block.
+__device__ __forceinline__ void copy2(uint8_t* d0, const uint8_t* s0, uint8_t* d1, const uint8_t* s1) {
+  uint4 a[4], b[4];
+  const uint4* x0 = reinterpret_cast<const uint4*>(s0);
+  const uint4* x1 = reinterpret_cast<const uint4*>(s1);
+  if (s0) {
+#pragma unroll
+    for (uint32_t i = 0; i < 4; ++i) a[i] = x0[i * 64 + lane()];
+  }
+  if (s1) {
+#pragma unroll
+    for (uint32_t i = 0; i < 4; ++i) b[i] = x1[i * 64 + lane()];
+  }
+  if (s0) {
+    uint4* y0 = reinterpret_cast<uint4*>(d0);
+#pragma unroll
+    for (uint32_t i = 0; i < 4; ++i) y0[i * 64 + lane()] = a[i];
+  }
+  if (s1) {
+    uint4* y1 = reinterpret_cast<uint4*>(d1);
+#pragma unroll
+    for (uint32_t i = 0; i < 4; ++i) y1[i * 64 + lane()] = b[i];
+  }
+}
+
+// Emulated NVMe controller wavefront (Sec. 2.1 device side).  It keeps up to 64 commands
+// in flight, one per lane: it fetches new entries from its queue pairs once their doorbell
+// moves, stamps the fetch time with s_memrealtime, takes a token from the store's global
+// bucket when an IOPS cap is set, and completes a command once
+// now >= max(fetch + latency, token time): the block(s) are copied across PCIe between
+// the pinned image and the HBM line, then a phase-tagged CQE is posted.
+__device__ void controller(const dev_ctx& c, const launch_t& li, uint32_t cw) {
+  const uint32_t dmask = c.depth - 1;
+  const bool shared = li.n_ctrl > c.num_qp;
+  const uint32_t qstep = li.n_ctrl < c.num_qp ? li.n_ctrl : c.num_qp;
+  const uint32_t q0 = cw % c.num_qp;
+  // per-lane pending command
+  bool pend = false, p_copied = false;
+  uint32_t p_q = 0, p_opc = 0, p_cid = 0, p_line = 0, p_nblk = 0, p_status = 0;
+  uint64_t p_slba = 0, p_prp = 0, p_deadline = 0;
+  uint64_t idle_since = now();
+  uint64_t busy = 0;
+  uint32_t loops = 0;
+  for (;;) {
+    if (((++loops) & 1023) == 0 && lane() == 0) count(c, C_CTRL_LOOPS, 1);
+    const uint64_t t = now();
+    bool progress = false;
+    // 1. fetch into free lanes
+    uint64_t freem = ballot(!pend);
+    for (uint32_t q = q0; q < c.num_qp && freem; q += qstep) {
+      qp_t* qs = c.qp + q;
+      const uint32_t db = ld_acq(&qs->db);
+      const uint32_t f = ld_rlx(&qs->fetch);
+      uint32_t avail = db - f;
+      if (avail == 0) continue;
+      const uint32_t nfree = __popcll(freem);
+      const uint32_t k = avail < nfree ? avail : nfree;
+      if (shared) {
+        uint32_t ok = 0;
+        if (lane() == 0) {
+          uint32_t e = f;
+          ok = cas(&qs->fetch, e, f + k) ? 1u : 0u;
+        }
+        if (!rdlane(ok, 0)) continue;
+      } else if (lane() == 0) {
+        st_rlx(&qs->fetch, f + k);
+      }
+      if (lane() == 0) count(c, C_CTRL_FETCH, k);
+      const uint32_t r = mbcnt(freem);
+      const bool take = ((freem >> lane()) & 1ull) && r < k;
+      uint64_t tok0 = 0;
+      if (c.tok_fp) {
+        if (lane() == 0) {
+          uint64_t old = ld_rlx(c.next_tok);
+          for (;;) {
+            const uint64_t tn = t << 32;
+            const uint64_t first = old > tn ? old : tn;
+            if (cas(c.next_tok, old, first + (uint64_t)k * c.tok_fp)) {
+              tok0 = first;
+              break;
+            }
+          }
+        }
+        tok0 = rdlane64(tok0, 0);
+      }
+      if (take) {
+        const uint32_t s = (f + r) & dmask;
+        const sqe_t* e = c.sq + (size_t)q * c.depth + s;
+        const uint4 w0 = reinterpret_cast<const uint4*>(e)[0];
+        const uint4 w1 = reinterpret_cast<const uint4*>(e)[1];
+        const uint4 w2 = reinterpret_cast<const uint4*>(e)[2];
+        const uint4 w3 = reinterpret_cast<const uint4*>(e)[3];
+        p_q = q;
+        p_opc = w0.x & 0xFF;
+        p_cid = w0.x >> 16;
+        p_line = w0.z;
+        p_prp = ((uint64_t)w1.w << 32) | w1.z;
+        p_slba = ((uint64_t)w2.w << 32) | w2.z;
+        p_nblk = (w3.x & 0xFFFF) + 1;
+        p_status = 0;
+        const uint64_t lo = (uint64_t)(uintptr_t)c.lines;
+        const uint64_t hi = lo + ((uint64_t)c.num_lines << c.line_shift);
+        if (p_cid != s || (p_opc != OPC_READ && p_opc != OPC_WRITE) || w0.w != f + r ||
+            p_prp < lo || p_prp + ((uint64_t)p_nblk << 12) > hi || p_nblk > c.blocks_per_line) {
+          raise_error(c, E_PROTO, ((uint64_t)q << 32) | s);
+          p_status = 0x4;  // invalid field
+        } else if (p_slba + p_nblk > c.store_blocks) {
+          p_status = 0x80;  // LBA out of range
+        }
+        uint64_t dl = t + c.lat_ticks;
+        if (c.tok_fp) {
+          const uint64_t tk = (tok0 + (uint64_t)r * c.tok_fp) >> 32;
+          if (tk > dl) dl = tk;
+        }
+        p_deadline = dl;
+        pend = true;
+      }
+      freem &= ~ballot(take);
+      progress = true;
+    }
+    // 2. execute ready commands: copy their blocks across PCIe
+    const uint64_t tn = now();
+    const uint64_t ready = ballot(pend && !p_copied && p_deadline <= tn);
+    if (ready) {
+      uint64_t rem = ready;
+      while (rem) {
+        const uint32_t l0 = ffs64(rem);
+        rem &= rem - 1;
+        const uint32_t l1 = rem ? ffs64(rem) : 64u;
+        if (rem) rem &= rem - 1;
+        const uint32_t nb0 = rdlane(p_status, l0) ? 0u : rdlane(p_nblk, l0);
+        const uint32_t nb1 = (l1 < 64 && !rdlane(p_status, l1)) ? rdlane(p_nblk, l1) : 0u;
+        const bool rd0 = rdlane(p_opc, l0) == OPC_READ;
+        const bool rd1 = l1 < 64 && rdlane(p_opc, l1) == OPC_READ;
+        uint8_t* hbm0 = (uint8_t*)(uintptr_t)rdlane64(p_prp, l0);
+        uint8_t* img0 = c.image + (rdlane64(p_slba, l0) << 12);
+        uint8_t* hbm1 = l1 < 64 ? (uint8_t*)(uintptr_t)rdlane64(p_prp, l1) : nullptr;
+        uint8_t* img1 = l1 < 64 ? c.image + (rdlane64(p_slba, l1) << 12) : nullptr;
+        const uint32_t maxb = nb0 > nb1 ? nb0 : nb1;
+        for (uint32_t b = 0; b < maxb; ++b) {
+          const uint64_t o = (uint64_t)b << 12;
+          const uint8_t* s0 = b < nb0 ? (rd0 ? img0 : hbm0) + o : nullptr;
+          uint8_t* t0 = b < nb0 ? (rd0 ? hbm0 : img0) + o : nullptr;
+          const uint8_t* s1 = b < nb1 ? (rd1 ? img1 : hbm1) + o : nullptr;
+          uint8_t* t1 = b < nb1 ? (rd1 ? hbm1 : img1) + o : nullptr;
+          copy2(t0, s0, t1, s1);
+        }
+      }
+      if ((ready >> lane()) & 1ull) p_copied = true;
+      if (lane() == 0) count(c, C_CTRL_CMDS, __popcll(ready));
+      progress = true;
+    }
+    // 3. post completions for executed commands, as many as each CQ has room for.  A
+    //    command that does not fit stays pending; the controller never waits for CQ
+    //    room (the room frees only when the completion service sees a full window,
+    //    which may need the very entries this wave is holding).
+    const uint64_t done = ballot(pend && p_copied);
+    if (done) {
+      if (ballot(pend && p_copied && p_opc == OPC_WRITE)) fence_rel_sys(); else fence_rel();
+      uint64_t todo = done;
+      while (todo) {
+        const uint32_t q = rdlane(p_q, ffs64(todo));
+        const uint64_t mm = ballot(((todo >> lane()) & 1ull) && p_q == q);
+        const uint32_t k = __popcll(mm);
+        qp_t* qs = c.qp + q;
+        uint32_t base = 0, kk = 0;
+        if (lane() == 0) {
+          uint32_t tail = ld_rlx(&qs->cq_tail);
+          for (;;) {
+            const uint32_t head = ld_acq(&qs->cq_head);
+            const uint32_t room = c.depth - (tail - head);
+            kk = room < k ? room : k;
+            if (kk == 0) break;
+            if (!shared) {
+              st_rlx(&qs->cq_tail, tail + kk);
+              break;
+            }
+            if (cas(&qs->cq_tail, tail, tail + kk)) break;
+          }
+          base = tail;
+        }
+        base = rdlane(base, 0);
+        kk = rdlane(kk, 0);
+        const bool mine = ((mm >> lane()) & 1ull) && mbcnt(mm) < kk;
+        if (mine) {
+          const uint32_t pos = base + mbcnt(mm);
+          cqe_t* e = c.cq + (size_t)q * c.depth + (pos & dmask);
+          const uint32_t phase = ((pos >> c.depth_shift) & 1u) ^ 1u;
+          e->dw0 = p_line;
+          e->dw1 = p_opc;
+          e->dw2 = (p_cid & 0xFFFF) | (q << 16);
+        }
+        fence_rel();
+        if (mine) {
+          const uint32_t pos = base + mbcnt(mm);
+          cqe_t* e = c.cq + (size_t)q * c.depth + (pos & dmask);
+          const uint32_t phase = ((pos >> c.depth_shift) & 1u) ^ 1u;
+          st_rlx(&e->dw3, (p_cid & 0xFFFF) | (phase << 16) | (p_status << 17));
+          pend = false;
+          p_copied = false;
+        }
+        if (kk) progress = true;
+        todo &= ~mm;
+      }
+    }
+    if (progress) {
+      idle_since = now();
+      continue;
+    }
+    if (!ballot(pend)) {
+      if (service_should_exit(c, li)) break;
+      __builtin_amdgcn_s_sleep(2);
+    } else {
+      __builtin_amdgcn_s_sleep(1);
+    }
+    if (aborted(c)) break;
+    if (now() - idle_since > c.timeout_ticks) {
+      if (ballot(pend)) raise_error(c, E_TIMEDOUT, 0xC1000000ull | cw);
+      // idle for a whole timeout while users still run: keep waiting for them unless
+      // the context was aborted (their own waits carry deadlines).
+      idle_since = now();
+    }
+    (void)busy;
+  }
+}
+
+// Completion service wavefront (Alg. 1 with a 64-entry window): CQs q = w, w + n_cq, ...
+// Lane k keeps the window start and done-mask of the k-th of them in registers (they
+// are also saved in the queue pair between launches).  For one CQ, lane i checks entry
+// start + i against the phase expected for that lap; each new entry frees its SQ slot for
+// the slot's next lap, moves its line from FETCHING to READY (or WRITEBACK to READY), and
+// sets its mask bit.  When the mask is full the window advances by 64 and the CQ head
+// doorbell is written.
+__device__ void completion(const dev_ctx& c, const launch_t& li, uint32_t w) {
+  const uint32_t dmask = c.depth - 1;
+  const uint32_t nmy = (c.num_qp > w) ? (c.num_qp - w + li.n_cq - 1) / li.n_cq : 0;
+  if (nmy == 0) return;
+  // state of my k-th CQ lives in lane k
+  uint32_t off = 0;
+  uint64_t mask = 0;
+  if (lane() < nmy) {
+    qp_t* qs = c.qp + (w + lane() * li.n_cq);
+    off = ld_rlx(&qs->cq_head);
+    mask = ((uint64_t)ld_rlx(&qs->cq_mask_hi) << 32) | ld_rlx(&qs->cq_mask_lo);
+  }
+  uint64_t idle_since = now();
+  uint32_t loops = 0;
+  for (;;) {
+    if (((++loops) & 1023) == 0 && lane() == 0) count(c, C_CQ_LOOPS, 1);
+    bool any = false;
+    for (uint32_t k = 0; k < nmy && k < 64; ++k) {
+      const uint32_t q = w + k * li.n_cq;
+      uint32_t o = rdlane(off, k);
+      uint64_t mk = rdlane64(mask, k);
+      const uint32_t pos = o + lane();
+      bool fresh = false;
+      if (!((mk >> lane()) & 1ull)) {
+        cqe_t* e = c.cq + (size_t)q * c.depth + (pos & dmask);
+        const uint32_t dw3 = ld_acq(&e->dw3);
+        const uint32_t expect = ((pos >> c.depth_shift) & 1u) ^ 1u;
+        if (((dw3 >> 16) & 1u) == expect) {
+          fresh = true;
+          const uint32_t line = e->dw0;
+          const uint32_t opc = e->dw1;
+          const uint32_t cid = dw3 & 0xFFFF;
+          const uint32_t status = dw3 >> 17;
+          if (status) raise_error(c, E_IO, ((uint64_t)q << 32) | cid);
+          if (line < c.num_lines) {
+            if (opc == OPC_READ)
+              add_rel(c.meta + line, 1ull);  // FETCHING -> READY
+            else
+              add_rel(c.meta + line, (uint64_t)0 - 2ull);  // WRITEBACK -> READY
+          } else {
+            raise_error(c, E_PROTO, ((uint64_t)q << 32) | cid);
+          }
+          uint32_t* sl = c.slot + (size_t)q * c.depth + (cid & dmask);
+          const uint32_t sw = ld_rlx(sl);
+          st_rel(sl, (((sw >> 2) + c.depth) << 2) | SLOT_EMPTY);
+        }
+      }
+      const uint64_t nb = ballot(fresh);
+      if (nb) {
+        any = true;
+        mk |= nb;
+        if (lane() == 0) {
+          add_rel(counter(c, C_COMPLETED), (uint64_t)__popcll(nb));
+          add_rlx(counter(c, C_CQ_ENTRIES), (uint64_t)__popcll(nb));
+        }
+        if (mk == ~0ull) {
+          o += 64;
+          mk = 0;
+          if (lane() == 0) st_rel(&c.qp[q].cq_head, o);
+        }
+        if (lane() == k) {
+          off = o;
+          mask = mk;
+        }
+      }
+    }
+    if (any) {
+      idle_since = now();
+      continue;
+    }
+    if (service_should_exit(c, li)) break;
+    __builtin_amdgcn_s_sleep(1);
+    if (now() - idle_since > 4 * c.timeout_ticks) {
+      raise_error(c, E_TIMEDOUT, 0xC2000000ull | w);
+      break;
+    }
+  }
+  if (lane() < nmy) {
+    qp_t* qs = c.qp + (w + lane() * li.n_cq);
+    st_rlx(&qs->cq_mask_lo, (uint32_t)mask);
+    st_rlx(&qs->cq_mask_hi, (uint32_t)(mask >> 32));
+  }
+}
+
+__device__ void run_service(const dev_ctx& c, const launch_t& li) {
+  const uint32_t sw = blockIdx.x * WPB + threadIdx.x / 64;
+  if (li.prio) __builtin_amdgcn_s_setprio(3);
+  if (lane() == 0 && sw < li.n_ctrl + li.n_cq) count(c, C_SVC_START, 1);
+  if (sw < li.n_ctrl)
+    controller(c, li, sw);
+  else if (sw < li.n_ctrl + li.n_cq)
+    completion(c, li, sw - li.n_ctrl);
+}
+
+// Called by every user wavefront when it is done with this launch.
+__device__ __forceinline__ void user_wave_done(const dev_ctx& c) {
+  if (lane() == 0) add_rel(counter(c, C_USER_DONE), 1ull);
+}
+
+// ------------------------------------------------------------------ cache (Sec. 3.4)
+enum : uint32_t { A_NONE = 0, A_HIT = 1, A_JOIN = 2, A_MISS = 3, A_NEED_WB = 4, A_EAGAIN = 5 };
+
+struct acq_t {
+  uint32_t res;   // A_*
+  uint32_t idx;   // cache line index (HIT/JOIN/MISS/NEED_WB)
+  uint32_t gen;
+};
+
+__device__ __forceinline__ bool try_lock(uint32_t* l) {
+  uint32_t z = 0;
+  return cas(l, z, 1u);
+}
+__device__ __forceinline__ void unlock(uint32_t* l) { st_rel(l, 0u); }
+
+// Pins a way whose probe showed `tag` valid.  The pin is an atomic add of the pin
+// count; if the word it returns no longer carries `tag` in a non-INVALID state the add is
+// undone.  Returns the old word (0 state INVALID on failure).
+__device__ __forceinline__ bool pin_way(const dev_ctx& c, uint32_t idx, uint32_t tag, uint32_t cnt,
+                                        uint32_t& res, uint32_t& gen) {
+  const uint64_t old = add_acqrel(c.meta + idx, RC_ONE * cnt);
+  if (m_tag(old) == tag && m_state(old) != ST_INVALID) {
+    res = (m_state(old) == ST_FETCHING) ? A_JOIN : A_HIT;
+    gen = m_gen(old);
+    if (!(old & M_REF)) or_rlx(c.meta + idx, M_REF);
+    return true;
+  }
+  add_rlx(c.meta + idx, (uint64_t)0 - RC_ONE * cnt);
+  return false;
+}
+
+// One acquisition attempt for `line_id` by this lane, pinning `cnt` references.
+//  * HIT / JOIN: the tag is present (READY, DIRTY, WRITEBACK / FETCHING): pinned.
+//  * MISS: a victim was claimed as FETCHING(line_id) with the pins; the caller must
+//    submit the READ.
+//  * NEED_WB: the clock chose a DIRTY victim; it is now WRITEBACK with one pin of ours;
+//    the caller submits its WRITE, waits for it, and calls again with `retake` = the line.
+//  * EAGAIN: every way is pinned or in flight (cache deadlock avoidance, Sec. 2.3.2).
+// Misses take the set lock so that a tag is never inserted twice; hits never lock.
+__device__ acq_t acquire_try(const dev_ctx& c, uint32_t line_id, uint32_t cnt, int retake) {
+  acq_t r{A_NONE, 0, 0};
+  const uint32_t set = set_of(c, line_id);
+  const uint32_t base = set * c.assoc;
+  if (retake < 0) {
+    // lock-free probe
+    for (uint32_t w = 0; w < c.assoc; ++w) {
+      const uint64_t m = ld_rlx(c.meta + base + w);
+      if (m_tag(m) == line_id && m_state(m) != ST_INVALID) {
+        if (pin_way(c, base + w, line_id, cnt, r.res, r.gen)) {
+          r.idx = base + w;
+          return r;
+        }
+        break;
+      }
+    }
+  }
+  if (!try_lock(c.set_lock + set)) return r;  // A_NONE: retry later
+  // re-probe under the lock: tags only change while the lock is held
+  for (uint32_t w = 0; w < c.assoc; ++w) {
+    const uint64_t m = ld_rlx(c.meta + base + w);
+    if (m_tag(m) == line_id && m_state(m) != ST_INVALID) {
+      if (pin_way(c, base + w, line_id, cnt, r.res, r.gen)) {
+        r.idx = base + w;
+        if (retake >= 0) add_rel(c.meta + retake, (uint64_t)0 - RC_ONE);  // drop our WB pin
+        unlock(c.set_lock + set);
+        return r;
+      }
+    }
+  }
+  if (retake >= 0) {
+    // our written-back line: READY(old tag) holding exactly our one pin -> FETCHING(new)
+    uint64_t m = ld_rlx(c.meta + retake);
+    if (m_state(m) == ST_READY && m_rc(m) == 1) {
+      const uint64_t nw = ((uint64_t)line_id << TAG_SHIFT) |
+                          ((uint64_t)((m_gen(m) + 1) & 0xFF) << GEN_SHIFT) | (RC_ONE * cnt) |
+                          M_REF | ST_FETCHING;
+      if (cas(c.meta + retake, m, nw)) {
+        r.res = A_MISS;
+        r.idx = retake;
+        r.gen = (m_gen(m) + 1) & 0xFF;
+        unlock(c.set_lock + set);
+        return r;
+      }
+    }
+    add_rel(c.meta + retake, (uint64_t)0 - RC_ONE);
+  }
+  // clock sweep from the hand (second chance); pinned / in-flight ways are skipped
+  const uint32_t h0 = ld_rlx(c.hand + set);
+  uint32_t h = h0;
+  for (uint32_t step = 0; step < 2 * c.assoc + 1; ++step) {
+    const uint32_t idx = base + h;
+    uint64_t m = ld_rlx(c.meta + idx);
+    const uint32_t st = m_state(m);
+    const bool unpinned = m_rc(m) == 0;
+    bool victim = false, dirty = false;
+    if (st == ST_INVALID) {
+      victim = true;
+    } else if ((st == ST_READY || st == ST_DIRTY) && unpinned) {
+      if (m & M_REF) {
+        and_rlx(c.meta + idx, ~M_REF);
+      } else {
+        victim = true;
+        dirty = st == ST_DIRTY;
+      }
+    }
+    if (victim) {
+      uint64_t nw;
+      if (dirty) {
+        nw = (m & ~(M_STATE | M_REF | RC_MASK)) | RC_ONE | ST_WRITEBACK;
+      } else {
+        nw = ((uint64_t)line_id << TAG_SHIFT) | ((uint64_t)((m_gen(m) + 1) & 0xFF) << GEN_SHIFT) |
+             (RC_ONE * cnt) | M_REF | ST_FETCHING;
+      }
+      if (cas(c.meta + idx, m, nw)) {
+        st_rlx(c.hand + set, (h + 1) % c.assoc);
+        r.res = dirty ? A_NEED_WB : A_MISS;
+        r.idx = idx;
+        r.gen = dirty ? m_gen(m) : ((m_gen(m) + 1) & 0xFF);
+        unlock(c.set_lock + set);
+        return r;
+      }
+      continue;  // lost a race on this way: look at it again
+    }
+    h = (h + 1) % c.assoc;
+  }
+  st_rlx(c.hand + set, h);
+  unlock(c.set_lock + set);
+  r.res = A_EAGAIN;
+  return r;
+}
+
+// ------------------------------------------------------------------ wave request chunks
+// A chunk is up to 64 lookups, one per lane.  issue() coalesces duplicate lines within the
+// wave (level-1 coalescing, Sec. 3.3.2: one leader lane per distinct line), acquires the
+// leaders' lines (level-2 coalescing in the cache), submits the wave's READs with one
+// reservation, and broadcasts each leader's line to its followers.
+struct chunk_t {
+  uint32_t line_id;  // requested line (valid when act)
+  uint32_t off;      // byte offset inside the line
+  uint32_t idx;      // cache line index (valid when st == A_HIT/JOIN/MISS)
+  uint32_t st;       // A_* result for this lane (followers copy their leader)
+  uint32_t leader;   // leader lane of this lane's line
+  uint32_t cnt;      // leader: lanes sharing its line
+  uint32_t gen;      // generation of the line when acquired
+  bool act;          // this lane carries a lookup
+};
+
+__device__ __forceinline__ void dedup(chunk_t& ch) {
+  uint64_t todo = ballot(ch.act);
+  ch.leader = lane();
+  ch.cnt = 0;
+  while (todo) {
+    const uint32_t l = ffs64(todo);
+    const uint32_t v = rdlane(ch.line_id, l);
+    const uint64_t same = ballot(ch.act && ch.line_id == v);
+    if ((same >> lane()) & 1ull) ch.leader = l;
+    if (lane() == l) ch.cnt = __popcll(same);
+    todo &= ~same;
+  }
+}
+
+// Acquire + submit for the leaders of `ch`.  On return every active lane has st in
+// {A_HIT, A_JOIN, A_MISS, A_EAGAIN} (or the context aborted).  Counts stats.
+// pin_each: every lane gets its own pin (host tickets); otherwise one pin per line.
+__device__ bool chunk_issue(const dev_ctx& c, chunk_t& ch, uint32_t q, bool count_stats,
+                            bool pin_each = false) {
+  dedup(ch);
+  const bool lead = ch.act && ch.leader == lane();
+  const uint32_t npin = pin_each ? ch.cnt : 1u;
+  uint32_t st = A_NONE, idx = 0, gen = 0;
+  int retake = -1;
+  bool pending = lead;
+  spin_t sp;
+  while (ballot(pending)) {
+    bool wb = false, rd = false;
+    if (pending) {
+      const acq_t a = acquire_try(c, ch.line_id, npin, retake);
+      if (a.res != A_NONE) {
+        st = a.res;
+        idx = a.idx;
+        gen = a.gen;
+        if (a.res == A_NEED_WB) {
+          wb = true;
+          retake = (int)a.idx;
+        } else {
+          pending = false;
+          rd = a.res == A_MISS;
+        }
+      }
+    }
+    // one wave-wide submission per round; READs and WRITEs may share the queue pair
+    const uint32_t blk_per_line = c.blocks_per_line;
+    uint64_t slba = 0;
+    uint32_t nblk = blk_per_line;
+    if (rd || wb) {
+      uint32_t lid = ch.line_id;
+      if (wb) lid = m_tag(ld_rlx(c.meta + idx));
+      slba = (uint64_t)lid * blk_per_line;
+      if (slba + nblk > c.store_blocks) nblk = (uint32_t)(c.store_blocks - slba);
+    }
+    if (!submit(c, q, rd, OPC_READ, idx, slba, nblk)) return false;
+    if (!submit(c, q, wb, OPC_WRITE, idx, slba, nblk)) return false;
+    if (ballot(wb)) {
+      const uint64_t nwb = __popcll(ballot(wb));
+      if (lane() == 0) count(c, C_WB_EVICT, nwb);
+      // wait for our write-backs to finish before retaking the line
+      spin_t sw;
+      bool waiting = wb;
+      while (ballot(waiting)) {
+        if (waiting && m_state(ld_acq(c.meta + idx)) != ST_WRITEBACK) waiting = false;
+        if (ballot(waiting) && !sw.step(c, 0xB0000000ull | idx)) return false;
+      }
+    }
+    if (ballot(pending && st == A_NONE)) {
+      if (!sp.step(c, 0xA0000000ull | ch.line_id)) return false;
+    }
+  }
+  // broadcast to followers
+  const uint32_t lst = shfl32(st, ch.leader);
+  const uint32_t lidx = shfl32(idx, ch.leader);
+  const uint32_t lgen = shfl32(gen, ch.leader);
+  if (ch.act) {
+    ch.st = lst;
+    ch.idx = lidx;
+    ch.gen = lgen;
+  } else {
+    ch.st = A_NONE;
+  }
+  if (count_stats) {
+    const uint64_t nreq = __popcll(ballot(ch.act && ch.st != A_EAGAIN));
+    const uint64_t nmiss = __popcll(ballot(ch.act && ch.st == A_MISS));
+    const uint64_t nea = __popcll(ballot(lead && st == A_EAGAIN));
+    if (lane() == 0) {
+      count(c, C_REQUESTS, nreq);
+      count(c, C_MISSES, nmiss);
+      count(c, C_HITS, nreq - nmiss);
+      count(c, C_EAGAIN, nea);
+    }
+  }
+  return true;
+}
+
+// Waits until every pinned line of the chunk has left FETCHING (acquire).
+__device__ bool chunk_wait(const dev_ctx& c, const chunk_t& ch) {
+  bool waiting = ch.act && (ch.st == A_HIT || ch.st == A_JOIN || ch.st == A_MISS);
+  spin_t sp;
+  while (true) {
+    if (waiting && m_state(ld_acq(c.meta + ch.idx)) != ST_FETCHING) waiting = false;
+    if (!ballot(waiting)) break;
+    if (!sp.step(c, 0xD0000000ull | ch.idx)) return false;
+  }
+  return true;
+}
+
+// Unpins the chunk's lines (leaders only; one pin per distinct line).
+__device__ __forceinline__ void chunk_release(const dev_ctx& c, chunk_t& ch, bool wrote) {
+  const bool lead = ch.act && ch.leader == lane() &&
+                    (ch.st == A_HIT || ch.st == A_JOIN || ch.st == A_MISS);
+  if (wrote) {
+    if (lead) add_rel(c.meta + ch.idx, (uint64_t)0 - RC_ONE);
+  } else {
+    loads_done();
+    if (lead) add_rlx(c.meta + ch.idx, (uint64_t)0 - RC_ONE);
+  }
+  ch.act = false;
+}
+
+}  // namespace ag

@@ -264,6 +264,15 @@ def test_protocol_model_ringing_only_after_all_writes_deadlocks():
     assert dead is None
 
 
+def test_protocol_model_all_or_nothing_completion_posting_deadlocks():
+    # a controller that posts its executed commands all at once (or none) can wait for
+    # CQ room that only a full polling window frees
+    n, dead = pm.explore("agile_batch_post", 4, (3, 2), window=4)
+    assert dead is not None
+    n, dead = pm.explore("agile", 4, (3, 2), window=4)
+    assert dead is None
+
+
 def test_protocol_model_naive_deadlocks_as_in_fig1():
     # Fig. 1: two threads each holding SQ entries, both spinning on a full queue
     n, dead = pm.explore("naive", 2, (2, 2))
