@@ -40,7 +40,7 @@ def parse():
     ap.add_argument("--tables", type=int, default=8)
     ap.add_argument("--batch", type=int, default=2048)
     ap.add_argument("--cache-gib", type=float, default=2.0)
-    ap.add_argument("--sweep", default="0,64,512,bal", help="K values for async/sync; '' = skip")
+    ap.add_argument("--sweep", default="0,64,512", help="K values for async/sync; '' = skip")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--profile-only", action="store_true",
@@ -158,46 +158,75 @@ def main():
     hit_gbs = hit_bytes / (np.median(ms_hit) * 1e-3) / 1e9
     log(f"hit replay: {np.median(ms_hit):.3f} ms, misses {hit_misses}, {hit_gbs:.0f} GB/s")
 
-    # ---- compute sweep: async vs sync at identical outputs, CTC and the Eq. 1 bound
+    # ---- compute sweep at full occupancy: async vs sync at identical outputs
+    def t_hit(K, ids=(last,), waves=0):
+        ctx.set_max_user_waves(waves)
+        run(agile.MODE_ASYNC, K, list(ids), time_each=False)  # warm these lines
+        ms, _ = run(agile.MODE_ASYNC, K, list(ids) * 2)
+        ctx.set_max_user_waves(0)
+        return float(np.median(ms))
+
+    def pair(K, ids, warm, waves=0):
+        res = {}
+        ctx.set_max_user_waves(waves)
+        for mode, name in ((agile.MODE_SYNC, "sync"), (agile.MODE_ASYNC, "async")):
+            cold()
+            run(mode, K, warm, time_each=False)
+            ms, _ = run(mode, K, ids)
+            res[name] = float(np.mean(ms))
+            res[name + "_out"] = [outs[i].clone() for i in ids]
+        ctx.set_max_user_waves(0)
+        res["identical"] = all(torch.equal(a, b) for a, b in zip(res["sync_out"], res["async_out"]))
+        return res
+
     sweep = []
     if args.sweep:
-        t_io = float(np.mean(ms_sync)) if args.K == 0 else None
-        ks = [k for k in args.sweep.split(",") if k]
-        t_hit0 = float(np.median(ms_hit))
-        # per-K compute time measured on the hit-only replay
-        def t_comp(K):
-            ms, _ = run(agile.MODE_ASYNC, K, [last, last])
-            return float(np.median(ms))
-        if "bal" in ks:
-            if t_io is None:
-                cold()
-                ms0, _ = run(agile.MODE_SYNC, 0, timed_ids[:3])
-                t_io = float(np.mean(ms0))
-            c512 = t_comp(512)
-            slope = max((c512 - t_hit0) / 512.0, 1e-9)
-            kbal = int(max(64, (0.9 * t_io - t_hit0) / slope))
-        for k in ks:
-            K = kbal if k == "bal" else int(k)
-            comp = t_comp(K)
-            res = {}
-            for mode, name in ((agile.MODE_SYNC, "sync"), (agile.MODE_ASYNC, "async")):
-                cold()
-                run(mode, K, warm_ids[:1], time_each=False)
-                ms, _ = run(mode, K, timed_ids[:3])
-                res[name] = float(np.mean(ms))
-                res[name + "_out"] = [outs[i].clone() for i in timed_ids[:3]]
-            identical = all(torch.equal(a, b) for a, b in zip(res["sync_out"], res["async_out"]))
-            io = t_io if t_io else res["sync"]
-            ctc = comp / io if io else 0.0
+        ids3 = timed_ids[:3]
+        t_io = None
+        for k in [k for k in args.sweep.split(",") if k and k != "bal"]:
+            K = int(k)
+            res = pair(K, ids3, warm_ids[:1])
+            if K == 0:
+                t_io = res["sync"]
+            comp = t_hit(K)
+            io = t_io or res["sync"]
+            ctc = comp / io
             bound = 1 + ctc if ctc <= 1 else 1 + 1 / ctc
-            sweep.append({"K": K, "label": k, "sync_ms": round(res["sync"], 3),
-                          "async_ms": round(res["async"], 3),
-                          "speedup": round(res["sync"] / res["async"], 3),
-                          "ctc": round(ctc, 4), "eq1_bound": round(bound, 3),
-                          "identical": identical})
-            log(f"K={K}: sync {res['sync']:.2f} ms async {res['async']:.2f} ms "
+            sweep.append({"K": K, "sync_ms": round(res["sync"], 3), "async_ms": round(res["async"], 3),
+                          "speedup": round(res["sync"] / res["async"], 3), "ctc": round(ctc, 4),
+                          "eq1_bound": round(bound, 3), "identical": res["identical"]})
+            log(f"full GPU K={K}: sync {res['sync']:.2f} async {res['async']:.2f} "
                 f"speedup {res['sync'] / res['async']:.3f} ctc {ctc:.3f} bound {bound:.3f} "
-                f"identical {identical}")
+                f"identical {res['identical']}")
+
+    # ---- thread-level overlap (Sec. 4.2): one 1024-thread group (16 wavefronts) for both
+    # modes, K set so that the computation-to-communication ratio spans 0..2
+    overlap = []
+    if args.sweep:
+        W = 16
+        small = [i for i in timed_ids[:2]]
+        ctx.set_max_user_waves(W)
+        cold()
+        run(agile.MODE_SYNC, 0, warm_ids[:1], time_each=False)
+        ms_io, _ = run(agile.MODE_SYNC, 0, small)
+        ctx.set_max_user_waves(0)
+        comm = float(np.mean(ms_io))
+        c0 = t_hit(0, (small[0],), W)
+        c1 = t_hit(256, (small[0],), W)
+        slope = max((c1 - c0) / 256.0, 1e-9)
+        for target in (0.0, 0.25, 0.5, 0.9, 1.25, 2.0):
+            K = 0 if target == 0 else int(max(1, (target * comm - c0) / slope))
+            comp = t_hit(K, (small[0],), W) if K else c0
+            ctc = comp / comm
+            bound = 1 + ctc if ctc <= 1 else 1 + 1 / ctc
+            res = pair(K, small, warm_ids[:1], W)
+            overlap.append({"K": K, "ctc": round(ctc, 4), "sync_ms": round(res["sync"], 3),
+                            "async_ms": round(res["async"], 3),
+                            "speedup": round(res["sync"] / res["async"], 3),
+                            "eq1_bound": round(bound, 3), "identical": res["identical"]})
+            log(f"16 waves K={K}: ctc {ctc:.3f} sync {res['sync']:.2f} async {res['async']:.2f} "
+                f"speedup {res['sync'] / res['async']:.3f} bound {bound:.3f} "
+                f"identical {res['identical']}")
 
     # ---- CPU baseline: the oracle on a bounded sample of the same workload
     cpu = None
@@ -258,7 +287,8 @@ def main():
         "hit_path": {"gbs": round(hit_gbs, 1), "frac_hbm_peak": round(hit_gbs / HBM_PEAK_GBS, 4),
                      "ms": round(float(np.median(ms_hit)), 4), "misses_in_replay": hit_misses,
                      "lookups": n_last},
-        "compute_sweep": sweep,
+        "compute_sweep_full_gpu": sweep,
+        "overlap_1024_threads": overlap,
         "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 6), "traffic": None,
                      "kernel": "k_embbag<2>",

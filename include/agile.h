@@ -59,6 +59,7 @@ typedef uint64_t agile_ticket;
 /* agile_config.flags */
 #define AGILE_F_SERIALIZED 0x1u /* workloads run one request at a time on one lane */
 #define AGILE_F_NO_PRIO 0x2u    /* do not raise the service wavefronts' issue priority */
+#define AGILE_F_PROFILE 0x4u    /* accumulate per-stage timers (see agile_debug_counters) */
 
 typedef struct agile_config {
   uint32_t struct_size;  /* sizeof(agile_config) */
@@ -69,7 +70,7 @@ typedef struct agile_config {
   uint32_t num_qp;       /* queue pairs, 1..1024 */
   uint32_t qp_depth;     /* entries per SQ and per CQ: power of two in [64, 65536] */
   uint32_t ctrl_waves;   /* emulated-controller wavefronts (0 = num_qp) */
-  uint32_t cq_waves;     /* completion-service wavefronts (0 = ceil(num_qp / 8)) */
+  uint32_t cq_waves;     /* completion-service wavefronts (0 = min(num_qp, 64)) */
   uint32_t max_user_waves; /* cap on user wavefronts per launch (0 = fill the GPU) */
   uint64_t latency_ns;   /* emulated per-command latency, fetch to completion */
   uint64_t iops_cap;     /* emulated commands per second over the store (0 = none) */
@@ -160,6 +161,7 @@ typedef struct agile_stats {
   uint64_t submitted;  /* commands submitted (monotonic, not reset) */
   uint64_t completed;  /* commands completed (monotonic, not reset) */
   uint64_t consumed;   /* workload rows read out of the cache and used */
+  uint64_t rows_updated; /* rows written by the backward pass (one per distinct row) */
 } agile_stats;
 agile_status agile_get_stats(agile_ctx ctx, agile_stats* out, int reset);
 
@@ -177,6 +179,10 @@ typedef struct agile_info {
   uint64_t cache_base;               /* device address of line 0 */
 } agile_info;
 agile_status agile_get_info(agile_ctx ctx, agile_info* out);
+
+/* Caps the user wavefronts of later workload launches (0 = fill the GPU), e.g. to run
+ * the thread-level overlap experiment of Sec. 4.2 on one 1024-thread group. */
+agile_status agile_set_max_user_waves(agile_ctx ctx, uint32_t n);
 
 /* ---------------------------------------------------------------- workloads --------
  * Tables: `num_tables` fp32 tables of `rows` x `dim`, concatenated row-major in the
@@ -228,6 +234,18 @@ agile_status agile_debug_counters(agile_ctx ctx, uint64_t* out, uint32_t n);
  * Blocks. */
 agile_status agile_debug_dump(agile_ctx ctx, int64_t* d_tags, uint8_t* d_states,
                               uint32_t* d_rc, void* stream);
+
+/* Embedding-bag backward fused with SGD, for the loss L = sum_g sum_d grad[g][d] *
+ * pooled[g][d] of agile_embbag_forward with K = 0: for every distinct row r of table t
+ * looked up by the batch, g = the sum of d_grad[bag] over the row's occurrences in
+ * ascending lookup position (fp32 from +0.0f), then w = fmaf(-lr, g, w) is applied to the
+ * row inside its HBM cache line, which becomes MODIFIED (Sec. 3.4) and is written back to
+ * the store when evicted or at agile_flush.  n is the total number of lookups
+ * (d_off[B*T]); d_grad is [B*T, dim] fp32 (device).  Stream-ordered; uses a work area the
+ * context grows on demand. */
+agile_status agile_embbag_backward_sgd(agile_ctx ctx, agile_store store, const agile_tables* tb,
+                                       const int64_t* d_idx, const int64_t* d_off, uint64_t B,
+                                       uint64_t n, const float* d_grad, float lr, void* stream);
 
 #ifdef __cplusplus
 }

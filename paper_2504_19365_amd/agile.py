@@ -15,7 +15,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libagile.so")
 
 OK, EINVAL, ENOMEM, EHIP, ETIMEDOUT, EAGAIN, EIO, EPROTO, ESTATE = 0, -1, -2, -3, -4, -5, -6, -7, -8
-F_SERIALIZED, F_NO_PRIO = 0x1, 0x2
+F_SERIALIZED, F_NO_PRIO, F_PROFILE = 0x1, 0x2, 0x4
 MODE_SYNC, MODE_ASYNC = 0, 1
 
 
@@ -38,7 +38,7 @@ class Stats(C.Structure):
     _fields_ = [(n, C.c_uint64) for n in (
         "requests", "hits", "misses", "read_cmds", "write_cmds", "wb_evict", "wb_flush",
         "eagain", "sq_spins", "ctrl_cmds", "cq_entries", "submitted", "completed",
-        "consumed")]
+        "consumed", "rows_updated")]
 
     def as_dict(self):
         return {n: int(getattr(self, n)) for n, _ in self._fields_}
@@ -92,10 +92,13 @@ def lib():
             "agile_status_string": (C.c_char_p, [st]),
             "agile_last_error": (C.c_char_p, [vp]),
             "agile_get_info": (st, [vp, C.POINTER(Info)]),
+            "agile_set_max_user_waves": (st, [vp, u32]),
             "agile_gather": (st, [vp, vp, C.POINTER(Tables), vp, u64, u32, vp, vp]),
             "agile_embbag_forward": (st, [vp, vp, C.POINTER(Tables), vp, vp, u64, u32, u32, vp,
                                           vp]),
             "agile_debug_trace": (st, [vp, vp, vp, vp, u64, vp, vp, vp]),
+            "agile_embbag_backward_sgd": (st, [vp, vp, C.POINTER(Tables), vp, vp, u64, u64, vp,
+                                               C.c_float, vp]),
             "agile_debug_dump": (st, [vp, vp, vp, vp, vp]),
             "agile_debug_counters": (st, [vp, vp, u32]),
         }
@@ -258,6 +261,9 @@ class Context:
                     "agile_get_stats")
         return st.as_dict()
 
+    def set_max_user_waves(self, n: int):
+        self._check(lib().agile_set_max_user_waves(self.h, n), "agile_set_max_user_waves")
+
     def info(self) -> dict:
         inf = Info()
         self._check(lib().agile_get_info(self.h, C.byref(inf)), "agile_get_info")
@@ -280,6 +286,14 @@ class Context:
                                                _ptr(off), B, K, mode, _ptr(out), _stream(stream)),
                     "agile_embbag_forward")
 
+    def embbag_backward_sgd(self, tb: Tables, idx, off, B: int, grad, lr: float, stream=None,
+                            store=None):
+        store = store or self.store
+        self._check(lib().agile_embbag_backward_sgd(self.h, store.handle, C.byref(tb), _ptr(idx),
+                                                    _ptr(off), B, idx.numel(), _ptr(grad), lr,
+                                                    _stream(stream)),
+                    "agile_embbag_backward_sgd")
+
     # ---- diagnostics
     def debug_trace(self, lines, writes, hit, way, stream=None, store=None):
         store = store or self.store
@@ -290,7 +304,10 @@ class Context:
     COUNTER_NAMES = ("submitted", "completed", "user_done", "work", "requests", "hits",
                      "misses", "reads", "writes", "wb_evict", "wb_flush", "eagain", "sq_spins",
                      "ctrl_cmds", "cq_entries", "aux0", "aux1", "svc_start", "ctrl_fetch",
-                     "ctrl_loops", "cq_loops")
+                     "ctrl_loops", "cq_loops", "wrows", "t_ctrl_fetch", "t_ctrl_copy", "t_ctrl_post",
+                     "t_ctrl_hold", "t_ctrl_idle", "ctrl_noroom", "t_cq_busy", "t_cq_idle",
+                     "t_u_issue", "t_u_submit", "t_u_wait", "t_u_consume", "tok_lead",
+                     "tok_n")
 
     def debug_counters(self) -> dict:
         n = len(self.COUNTER_NAMES)

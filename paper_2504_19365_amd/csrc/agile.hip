@@ -15,6 +15,8 @@
 #include <thread>
 #include <vector>
 
+#include <hipcub/hipcub.hpp>
+
 #include "agile.h"
 #include "agile_dev.hpp"
 
@@ -131,41 +133,62 @@ __device__ __forceinline__ void make_chunk(const dev_ctx& c, const embbag_args& 
   }
 }
 
-// Consumes rows of the chunk in order until the first row whose lane is not pinned.
-// Returns the number consumed.  Four rows' loads are in flight before their compute.
+// Row loads are device-coherent (they bypass any stale copy a previous tenant of the
+// line left in this XCD's L2), so reads need no cache invalidation.
+template <int VPL>
+__device__ __forceinline__ void ld_row(const float* p, float (&v)[VPL]) {
+  if constexpr (VPL == 1) {
+    v[0] = __uint_as_float(ld_rlx(reinterpret_cast<const uint32_t*>(p)));
+  } else {
+#pragma unroll
+    for (int h = 0; h < VPL / 2; ++h) {
+      const uint64_t x = ld_rlx(reinterpret_cast<const uint64_t*>(p) + h);
+      v[2 * h] = __uint_as_float((uint32_t)x);
+      v[2 * h + 1] = __uint_as_float((uint32_t)(x >> 32));
+    }
+  }
+}
+
+// Consumes rows of the chunk in order, eight rows' loads in flight at a time, until the
+// first row whose lane has no line or (with `validate`) whose unpinned line changed
+// tenant while it was read (seqlock-style: the metadata is re-read after the data loads
+// have completed).  Returns the number of rows consumed.
 template <int VPL>
 __device__ uint32_t consume(const dev_ctx& c, const embbag_args& a, const desc_t& d,
-                            const chunk_t& ch, float (&acc)[VPL]) {
-  const uint64_t okm = ballot(ch.act && (ch.st == A_HIT || ch.st == A_JOIN || ch.st == A_MISS));
+                            const chunk_t& ch, float (&acc)[VPL], bool validate) {
+  const uint64_t okm = ballot(ch.act && st_ok(ch.st));
   const uint32_t nok = (~okm == 0ull) ? 64u : ffs64(~okm);
   const uint32_t n = nok < d.n ? nok : d.n;
   const uint32_t d0 = lane() * VPL;
   const bool mine = d0 < a.dim;
-  uint32_t j = 0;
-  for (; j < n; j += 4) {
-    float v[4][VPL];
+  for (uint32_t j = 0; j < n; j += 8) {
+    const uint32_t g = (n - j) < 8 ? (n - j) : 8;
+    float v[8][VPL];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      if (j + u < n) {
+    for (uint32_t u = 0; u < 8; ++u) {
+      if (u < g) {
         const uint32_t idx = rdlane(ch.idx, j + u);
         const uint32_t off = rdlane(ch.off, j + u);
         const float* p = reinterpret_cast<const float*>(line_ptr(c, idx) + off) + d0;
-        if (mine) {
-          if constexpr (VPL == 4) {
-            const float4 t = *reinterpret_cast<const float4*>(p);
-            v[u][0] = t.x; v[u][1] = t.y; v[u][2] = t.z; v[u][3] = t.w;
-          } else if constexpr (VPL == 2) {
-            const float2 t = *reinterpret_cast<const float2*>(p);
-            v[u][0] = t.x; v[u][1] = t.y;
-          } else {
-            v[u][0] = p[0];
-          }
-        }
+        if (mine) ld_row<VPL>(p, v[u]);
       }
     }
+    uint32_t good = g;
+    if (validate) {
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");  // data loads have completed
+      const uint32_t r = (j + lane()) & 63;
+      const uint32_t ridx = shfl32(ch.idx, r);
+      const uint32_t rtag = shfl32(ch.line_id, r);
+      const uint32_t rgen = shfl32(ch.gen, r);
+      const uint32_t rpin = shfl32(ch.pinned ? 1u : 0u, r);
+      bool bad = false;
+      if (lane() < g && !rpin) bad = !line_still_valid(c, ridx, rtag, rgen);
+      const uint64_t bm = ballot(bad);
+      if (bm) good = ffs64(bm);
+    }
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      if (j + u < n && mine) {
+    for (uint32_t u = 0; u < 8; ++u) {
+      if (u < good && mine) {
         if (a.gather) {
           float* o = a.out + (uint64_t)(d.j + j + u) * a.dim + d0;
 #pragma unroll
@@ -176,6 +199,7 @@ __device__ uint32_t consume(const dev_ctx& c, const embbag_args& a, const desc_t
         }
       }
     }
+    if (good < g) return j + good;
   }
   return n;
 }
@@ -194,7 +218,7 @@ __device__ void embbag_wave(const dev_ctx& c, const launch_t& li, const embbag_a
   if (!dc.valid) return;
   chunk_t cc, cn;
   make_chunk(c, a, dc, cc);
-  if (!chunk_issue(c, cc, q, true)) return;
+  if (!chunk_issue(c, cc, q, true, PIN_NONE)) return;
   while (dc.valid) {
     desc_t dn;
     bool n_issued = false;
@@ -202,21 +226,23 @@ __device__ void embbag_wave(const dev_ctx& c, const launch_t& li, const embbag_a
       dn = next_desc<VPL>(c, li, a, dc);
       if (dn.valid) {
         make_chunk(c, a, dn, cn);
-        if (!chunk_issue(c, cn, q, true)) return;
+        if (!chunk_issue(c, cn, q, true, PIN_NONE)) return;
         n_issued = true;
       }
     }
     // consume the current chunk in order up to its first row without a line
-    if (!chunk_wait(c, cc)) return;
-    const uint32_t k = consume<VPL>(c, a, dc, cc, acc);
+    if (!chunk_wait(c, cc, false)) return;
+    const uint64_t t_cons = now();
+    const uint32_t k = consume<VPL>(c, a, dc, cc, acc, true);
     chunk_release(c, cc, false);
+    ptick(c, P_U_CONSUME, t_cons);
     if (lane() == 0) count(c, C_AUX1, k);
     if (k < dc.n) {
       // EAGAIN: drop every pin this wave holds (including the prefetched chunk), then
       // drain the rest of the chunk one row at a time, acquiring each row while holding
       // nothing, so that no wave ever waits for a line while it pins others (Sec. 2.3.2).
       if (n_issued) {
-        if (!chunk_wait(c, cn)) return;
+        if (!chunk_wait(c, cn, false)) return;
         chunk_release(c, cn, false);
         n_issued = false;
       }
@@ -228,12 +254,12 @@ __device__ void embbag_wave(const dev_ctx& c, const launch_t& li, const embbag_a
         spin_t sp;
         for (;;) {
           make_chunk(c, a, one, cc);
-          if (!chunk_issue(c, cc, q, true)) return;
+          if (!chunk_issue(c, cc, q, true, PIN_LINE)) return;
           if (rdlane(cc.st, 0) != A_EAGAIN) break;
           if (!sp.step(c, 0xF0000000ull | (uint32_t)dc.g)) return;
         }
-        if (!chunk_wait(c, cc)) return;
-        consume<VPL>(c, a, one, cc, acc);
+        if (!chunk_wait(c, cc, false)) return;
+        consume<VPL>(c, a, one, cc, acc, false);
         chunk_release(c, cc, false);
         if (lane() == 0) count(c, C_AUX1, 1);
         dc.j += 1;
@@ -252,7 +278,7 @@ __device__ void embbag_wave(const dev_ctx& c, const launch_t& li, const embbag_a
       cc = cn;
     } else {
       make_chunk(c, a, dc, cc);
-      if (!chunk_issue(c, cc, q, true)) return;
+      if (!chunk_issue(c, cc, q, true, PIN_NONE)) return;
     }
   }
 }
@@ -280,9 +306,9 @@ __device__ void embbag_serial(const dev_ctx& c, const launch_t& li, const embbag
       spin_t sp;
       for (;;) {
         make_chunk(c, a, d, ch);
-        if (!chunk_issue(c, ch, 0, true)) return;
-        if (!chunk_wait(c, ch)) return;
-        const uint32_t k = consume<VPL>(c, a, d, ch, acc);
+        if (!chunk_issue(c, ch, 0, true, PIN_LINE)) return;
+        if (!chunk_wait(c, ch, false)) return;
+        const uint32_t k = consume<VPL>(c, a, d, ch, acc, false);
         chunk_release(c, ch, false);
         if (k == 1) {
           if (lane() == 0) count(c, C_AUX1, 1);
@@ -333,7 +359,7 @@ __global__ __launch_bounds__(WG) void k_async_read(dev_ctx c, launch_t li, const
       ch.line_id = (uint32_t)(blk / c.blocks_per_line);
       ch.off = (uint32_t)((blk % c.blocks_per_line) << 12);
     }
-    if (!chunk_issue(c, ch, q, true, true)) break;
+    if (!chunk_issue(c, ch, q, true, PIN_EACH)) break;
     if (ch.act) {
       const bool ok = ch.st == A_HIT || ch.st == A_JOIN || ch.st == A_MISS;
       tickets[i] = (uint64_t)ch.idx | ((uint64_t)(ch.gen & 0xFF) << 32) |
@@ -367,7 +393,7 @@ __global__ __launch_bounds__(WG) void k_wait(dev_ctx c, launch_t li, const agile
   bool okay = true;
   while (ballot(waiting)) {
     if (waiting) {
-      const uint64_t m = ld_acq(c.meta + idx);
+      const uint64_t m = ld_rlx(c.meta + idx);
       if (m_state(m) != ST_FETCHING) {
         waiting = false;
         if (m_gen(m) != gen || m_rc(m) == 0) raise_error(c, E_STATE, ((uint64_t)idx << 8) | gen);
@@ -378,6 +404,7 @@ __global__ __launch_bounds__(WG) void k_wait(dev_ctx c, launch_t li, const agile
       break;
     }
   }
+  fence_acq();
   if (i < n) {
     ptrs[i] = (okay && st == TK_OK) ? (void*)(line_ptr(c, idx) + ((uint64_t)boff << 12)) : nullptr;
   }
@@ -469,7 +496,7 @@ __global__ __launch_bounds__(WG) void k_trace(dev_ctx c, launch_t li, const uint
       const bool w = writes && writes[i];
       spin_t sp;
       for (;;) {
-        if (!chunk_issue(c, ch, 0, true)) goto out;
+        if (!chunk_issue(c, ch, 0, true, PIN_LINE)) goto out;
         if (!chunk_wait(c, ch)) goto out;
         if (rdlane(ch.st, 0) != A_EAGAIN) break;
         if (!sp.step(c, 0xF2000000ull)) goto out;
@@ -488,6 +515,144 @@ __global__ __launch_bounds__(WG) void k_trace(dev_ctx c, launch_t li, const uint
     }
   }
 out:
+  user_wave_done(c);
+}
+
+// ---- embedding-bag backward fused with SGD (write path)
+struct bwd_args {
+  const int64_t* idx;
+  const int64_t* off;
+  const float* grad;      // [B*T, dim] upstream gradient of the pooled output
+  uint64_t* keys;         // (global row << 32 | lookup position), sorted
+  uint32_t* bagid;        // bag of each lookup position
+  uint32_t* heads;        // first sorted position of every distinct row (unordered)
+  uint32_t* ctr;          // [0] = number of heads, [1] = group counter
+  uint64_t n, nbags, rows, base_off;
+  uint32_t T, dim, row_bytes;
+  float lr;
+};
+
+__global__ void k_bwd_keys(bwd_args a, uint64_t* keys_in) {
+  const uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= a.nbags) return;
+  const uint64_t t = g % a.T;
+  for (int64_t j = a.off[g]; j < a.off[g + 1]; ++j) {
+    keys_in[j] = ((t * a.rows + (uint64_t)a.idx[j]) << 32) | (uint64_t)j;
+    a.bagid[j] = (uint32_t)g;
+  }
+}
+
+__global__ void k_bwd_heads(bwd_args a) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= a.n) return;
+  if (i == 0 || (a.keys[i] >> 32) != (a.keys[i - 1] >> 32)) {
+    const uint32_t k = atomicAdd(a.ctr, 1u);
+    a.heads[k] = (uint32_t)i;
+  }
+}
+
+// One user wave takes 64 distinct rows at a time: pins their lines for writing, sums each
+// row's upstream gradients over its occurrences in ascending lookup position (fp32, from
+// +0.0f), applies w = fmaf(-lr, g, w) in the cached line, marks the line MODIFIED and
+// unpins it with release ordering.  A MODIFIED line is written back when the clock evicts
+// it or at flush (Sec. 3.4, case d).
+template <int VPL>
+__device__ void bwd_wave(const dev_ctx& c, const bwd_args& a, uint32_t uw) {
+  const uint32_t q = uw % c.num_qp;
+  const uint32_t nheads = ld_rlx(a.ctr);
+  const uint32_t d0 = lane() * VPL;
+  const bool mine = d0 < a.dim;
+  for (;;) {
+    uint32_t gidx = 0;
+    if (lane() == 0) gidx = add_rlx(a.ctr + 1, 1u);
+    gidx = rdlane(gidx, 0);
+    const uint64_t base = (uint64_t)gidx * 64;
+    if (base >= nheads) break;
+    bool todo = base + lane() < nheads;
+    uint32_t start = 0;
+    uint64_t row = 0;
+    if (todo) {
+      start = a.heads[base + lane()];
+      row = a.keys[start] >> 32;
+    }
+    spin_t sp;
+    while (ballot(todo)) {
+      chunk_t ch;
+      ch.act = todo;
+      if (todo) {
+        const uint64_t byte = a.base_off + row * a.row_bytes;
+        ch.line_id = (uint32_t)(byte >> c.line_shift);
+        ch.off = (uint32_t)(byte & ((1ull << c.line_shift) - 1));
+      }
+      if (!chunk_issue(c, ch, q, true, PIN_LINE)) return;
+      if (!chunk_wait(c, ch, true)) return;
+      // a line pinned while its earlier write-back was in flight: wait for it to finish
+      bool wbw = ch.act && st_ok(ch.st) && ch.leader == lane();
+      while (ballot(wbw)) {
+        if (wbw && m_state(ld_rlx(c.meta + ch.idx)) != ST_WRITEBACK) wbw = false;
+        if (ballot(wbw) && !sp.step(c, 0xB1000000ull | ch.idx)) return;
+      }
+      fence_acq();
+      const uint64_t okm = ballot(ch.act && st_ok(ch.st));
+      for (uint64_t m = okm; m; m &= m - 1) {
+        const uint32_t k = ffs64(m);
+        const uint32_t s0 = rdlane(start, k);
+        const uint64_t r = rdlane64(row, k);
+        // segment end: first sorted position past s0 with another row
+        uint64_t e = s0 + 1;
+        for (;;) {
+          const uint64_t i = e + lane();
+          const bool same = i < a.n && (a.keys[i] >> 32) == r;
+          const uint64_t b = ballot(same);
+          const uint32_t run = (~b == 0ull) ? 64u : ffs64(~b);
+          e += run;
+          if (run < 64) break;
+        }
+        float acc[VPL];
+#pragma unroll
+        for (int v = 0; v < VPL; ++v) acc[v] = 0.0f;
+        for (uint64_t i = s0; i < e; ++i) {
+          const uint32_t j = (uint32_t)a.keys[i];
+          const uint32_t gb = a.bagid[j];
+          if (mine) {
+            const float* gp = a.grad + (uint64_t)gb * a.dim + d0;
+#pragma unroll
+            for (int v = 0; v < VPL; ++v) acc[v] = acc[v] + gp[v];
+          }
+        }
+        const uint32_t idx = rdlane(ch.idx, k);
+        const uint32_t off = rdlane(ch.off, k);
+        float* w = reinterpret_cast<float*>(line_ptr(c, idx) + off) + d0;
+        if (mine) {
+#pragma unroll
+          for (int v = 0; v < VPL; ++v) w[v] = __builtin_fmaf(-a.lr, acc[v], w[v]);
+        }
+      }
+      // mark the written lines MODIFIED (leaders), then unpin with release ordering
+      if (ch.act && st_ok(ch.st) && ch.leader == lane()) {
+        uint64_t mv = ld_rlx(c.meta + ch.idx);
+        while (m_state(mv) == ST_READY) {
+          if (cas(c.meta + ch.idx, mv, mv + 1ull)) break;  // READY -> DIRTY
+        }
+      }
+      if (lane() == 0) count(c, C_WROWS, __popcll(okm));
+      chunk_release(c, ch, true);
+      if (okm && ((okm >> lane()) & 1ull)) todo = false;
+      if (ballot(todo) && !okm) {
+        if (!sp.step(c, 0xF3000000ull | gidx)) return;
+      }
+    }
+  }
+}
+
+template <int VPL>
+__global__ __launch_bounds__(WG) void k_bwd_sgd(dev_ctx c, launch_t li, bwd_args a) {
+  if (blockIdx.x < li.service_blocks) {
+    run_service(c, li);
+    return;
+  }
+  const uint32_t uw = (blockIdx.x - li.service_blocks) * WPB + threadIdx.x / 64;
+  bwd_wave<VPL>(c, a, uw);
   user_wave_done(c);
 }
 
@@ -526,12 +691,14 @@ struct agile_ctx_s {
   uint32_t* abort_host = nullptr;  // pinned, mapped
   std::vector<void*> dev_allocs;
   std::vector<int> occ_cache;  // resident workgroups per CU, per kernel kind
+  void* scratch = nullptr;     // backward-pass work arrays, grown on demand
+  size_t scratch_bytes = 0;
 };
 
 namespace {
 
 constexpr int KIND_EMBBAG1 = 0, KIND_EMBBAG2 = 1, KIND_EMBBAG4 = 2, KIND_READ = 3, KIND_FLUSH = 4,
-              KIND_TRACE = 5, KIND_N = 6;
+              KIND_TRACE = 5, KIND_BWD1 = 6, KIND_BWD2 = 7, KIND_BWD4 = 8, KIND_N = 9;
 
 agile_status fail(agile_ctx ctx, agile_status s, const std::string& msg) {
   if (ctx) ctx->last_error = msg;
@@ -576,6 +743,9 @@ int occupancy(agile_ctx ctx, int kind) {
     case KIND_EMBBAG4: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_embbag<4>, WG, 0); break;
     case KIND_READ: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_async_read, WG, 0); break;
     case KIND_FLUSH: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_flush, WG, 0); break;
+    case KIND_BWD1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_bwd_sgd<1>, WG, 0); break;
+    case KIND_BWD2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_bwd_sgd<2>, WG, 0); break;
+    case KIND_BWD4: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_bwd_sgd<4>, WG, 0); break;
     default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_trace, WG, 0); break;
   }
   if (e != hipSuccess || nb <= 0) nb = 1;
@@ -719,7 +889,7 @@ agile_status agile_init(const agile_config* cfg_in, agile_ctx* out) {
   if (cfg.num_qp == 0 || cfg.num_qp > 1024) return AGILE_EINVAL;
   if (cfg.qp_depth < 64 || cfg.qp_depth > 65536 || !is_pow2(cfg.qp_depth)) return AGILE_EINVAL;
   uint32_t n_ctrl = cfg.ctrl_waves ? cfg.ctrl_waves : cfg.num_qp;
-  uint32_t n_cq = cfg.cq_waves ? cfg.cq_waves : (cfg.num_qp + 7) / 8;
+  uint32_t n_cq = cfg.cq_waves ? cfg.cq_waves : std::min<uint32_t>(cfg.num_qp, 64);
   if (n_ctrl > 4096 || n_cq > 1024) return AGILE_EINVAL;
   if ((uint64_t)n_cq * 64 < cfg.num_qp) return AGILE_EINVAL;  // <= 64 CQs per polling wave
   if (n_cq > cfg.num_qp) n_cq = cfg.num_qp;
@@ -810,6 +980,7 @@ agile_status agile_shutdown(agile_ctx ctx) {
   (void)hipDeviceSynchronize();
   for (void* p : ctx->dev_allocs) (void)hipFree(p);
   if (ctx->abort_host) (void)hipHostFree(ctx->abort_host);
+  if (ctx->scratch) (void)hipFree(ctx->scratch);
   delete ctx->store;
   delete ctx;
   return AGILE_OK;
@@ -979,6 +1150,7 @@ agile_status agile_get_stats(agile_ctx ctx, agile_stats* out, int reset) {
   out->submitted = g(C_SUBMITTED);
   out->completed = g(C_COMPLETED);
   out->consumed = g(C_AUX1);
+  out->rows_updated = g(C_WROWS);
   if (reset) {
     const uint32_t keep[] = {C_SUBMITTED, C_COMPLETED, C_USER_DONE, C_WORK};
     for (uint32_t i = 0; i < C_COUNT; ++i) {
@@ -987,6 +1159,12 @@ agile_status agile_get_stats(agile_ctx ctx, agile_stats* out, int reset) {
     }
     HIPCHK(ctx, hipDeviceSynchronize());
   }
+  return AGILE_OK;
+}
+
+agile_status agile_set_max_user_waves(agile_ctx ctx, uint32_t n) {
+  if (!ctx) return AGILE_EINVAL;
+  ctx->cfg.max_user_waves = n;
   return AGILE_OK;
 }
 
@@ -1079,6 +1257,83 @@ agile_status agile_embbag_forward(agile_ctx ctx, agile_store store, const agile_
                                   void* stream) {
   if (B == 0) return check_usable(ctx);
   return embbag_launch(ctx, store, tb, d_idx, d_off, B, 0, K, mode, d_out, stream, false);
+}
+
+agile_status agile_embbag_backward_sgd(agile_ctx ctx, agile_store store, const agile_tables* tb,
+                                       const int64_t* d_idx, const int64_t* d_off, uint64_t B, uint64_t n,
+                                       const float* d_grad, float lr, void* stream) {
+  agile_status s = check_usable(ctx);
+  if (s) return s;
+  if (store != ctx->store) return fail(ctx, AGILE_EINVAL, "backward: store is not open on this context");
+  if (!tb || !d_off || !d_grad || (n && !d_idx)) return fail(ctx, AGILE_EINVAL, "backward: null pointer");
+  if (tb->dim == 0 || tb->dim > 256 || tb->num_tables == 0 || tb->rows == 0)
+    return fail(ctx, AGILE_EINVAL, "backward: dim must be 1..256, tables and rows non-zero");
+  const uint64_t row_bytes = (uint64_t)tb->dim * 4;
+  if (4096 % row_bytes || tb->base_offset % row_bytes)
+    return fail(ctx, AGILE_EINVAL, "backward: row bytes must divide 4096 and align base_offset");
+  if (tb->base_offset + tb->rows * row_bytes * tb->num_tables > store->bytes)
+    return fail(ctx, AGILE_EINVAL, "backward: tables exceed the store");
+  if (n >= (1ull << 32) || tb->rows * tb->num_tables >= (1ull << 32))
+    return fail(ctx, AGILE_EINVAL, "backward: too many lookups or rows");
+  if (n == 0 || B == 0) return AGILE_OK;
+  hipStream_t hs = (hipStream_t)stream;
+  const uint64_t nbags = B * tb->num_tables;
+  // scratch: keys in/out, bag ids, heads, counters, sort workspace
+  size_t sort_bytes = 0;
+  HIPCHK(ctx, hipcub::DeviceRadixSort::SortKeys(nullptr, sort_bytes, (uint64_t*)nullptr, (uint64_t*)nullptr,
+                                                (int)n, 0, 64, hs));
+  auto al = [](size_t v) { return (v + 255) & ~(size_t)255; };
+  const size_t o_kin = 0, o_kout = o_kin + al(n * 8), o_bag = o_kout + al(n * 8), o_head = o_bag + al(n * 4),
+               o_ctr = o_head + al(n * 4), o_sort = o_ctr + 256, need = o_sort + al(sort_bytes);
+  if (need > ctx->scratch_bytes) {
+    HIPCHK(ctx, hipStreamSynchronize(hs));
+    if (ctx->scratch) HIPCHK(ctx, hipFree(ctx->scratch));
+    ctx->scratch = nullptr;
+    ctx->scratch_bytes = 0;
+    if (hipMalloc(&ctx->scratch, need) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(ctx, AGILE_ENOMEM, "backward: scratch allocation failed");
+    }
+    ctx->scratch_bytes = need;
+  }
+  uint8_t* sb = (uint8_t*)ctx->scratch;
+  bwd_args a{};
+  a.idx = d_idx;
+  a.off = d_off;
+  a.grad = d_grad;
+  a.keys = (uint64_t*)(sb + o_kout);
+  a.bagid = (uint32_t*)(sb + o_bag);
+  a.heads = (uint32_t*)(sb + o_head);
+  a.ctr = (uint32_t*)(sb + o_ctr);
+  a.n = n;
+  a.nbags = nbags;
+  a.rows = tb->rows;
+  a.base_off = tb->base_offset;
+  a.T = tb->num_tables;
+  a.dim = tb->dim;
+  a.row_bytes = (uint32_t)row_bytes;
+  a.lr = lr;
+  HIPCHK(ctx, hipMemsetAsync(a.ctr, 0, 256, hs));
+  hipLaunchKernelGGL(k_bwd_keys, dim3((uint32_t)((nbags + 255) / 256)), dim3(256), 0, hs, a, (uint64_t*)(sb + o_kin));
+  HIPCHK(ctx, hipGetLastError());
+  HIPCHK(ctx, hipcub::DeviceRadixSort::SortKeys(sb + o_sort, sort_bytes, (uint64_t*)(sb + o_kin), a.keys, (int)n, 0,
+                                                64, hs));
+  hipLaunchKernelGGL(k_bwd_heads, dim3((uint32_t)((n + 255) / 256)), dim3(256), 0, hs, a);
+  HIPCHK(ctx, hipGetLastError());
+  const int kind = tb->dim <= 64 ? KIND_BWD1 : (tb->dim <= 128 ? KIND_BWD2 : KIND_BWD4);
+  const uint64_t by_cache = std::max<uint64_t>(1, ctx->d.num_lines / 128);
+  uint32_t uw = (uint32_t)std::min<uint64_t>({(n + 63) / 64, (uint64_t)user_wave_cap(ctx, kind), by_cache});
+  uw = (uw + WPB - 1) / WPB * WPB;
+  launch_t li = make_launch(ctx, uw, true, 0);
+  const dim3 grid(li.service_blocks + uw / WPB);
+  if (kind == KIND_BWD1)
+    hipLaunchKernelGGL(k_bwd_sgd<1>, grid, dim3(WG), 0, hs, ctx->d, li, a);
+  else if (kind == KIND_BWD2)
+    hipLaunchKernelGGL(k_bwd_sgd<2>, grid, dim3(WG), 0, hs, ctx->d, li, a);
+  else
+    hipLaunchKernelGGL(k_bwd_sgd<4>, grid, dim3(WG), 0, hs, ctx->d, li, a);
+  HIPCHK(ctx, hipGetLastError());
+  return AGILE_OK;
 }
 
 // ---- diagnostics used by tests (declared in agile.h)

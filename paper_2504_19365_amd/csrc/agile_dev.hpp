@@ -148,7 +148,10 @@ struct alignas(128) qp_t {
 enum : uint32_t {
   C_SUBMITTED = 0, C_COMPLETED, C_USER_DONE, C_WORK, C_REQUESTS, C_HITS, C_MISSES, C_READS,
   C_WRITES, C_WB_EVICT, C_WB_FLUSH, C_EAGAIN, C_SQ_SPINS, C_CTRL_CMDS, C_CQ_ENTRIES, C_AUX0,
-  C_AUX1, C_SVC_START, C_CTRL_FETCH, C_CTRL_LOOPS, C_CQ_LOOPS, C_COUNT
+  C_AUX1, C_SVC_START, C_CTRL_FETCH, C_CTRL_LOOPS, C_CQ_LOOPS, C_WROWS,
+  // stage timers (ticks of s_memrealtime, summed over wavefronts; profile flag only)
+  P_CTRL_FETCH, P_CTRL_COPY, P_CTRL_POST, P_CTRL_HOLD, P_CTRL_IDLE, P_CTRL_NOROOM, P_CQ_BUSY,
+  P_CQ_IDLE, P_U_ISSUE, P_U_SUBMIT, P_U_WAIT, P_U_CONSUME, P_TOK_LEAD, P_TOK_N, C_COUNT
 };
 constexpr uint32_t CSTRIDE = 16;  // u64 per counter
 
@@ -197,6 +200,7 @@ struct launch_t {
 };
 
 constexpr uint32_t WG = 256;  // threads per workgroup: 4 wavefronts
+constexpr uint32_t FLAG_PROFILE = 0x4;
 constexpr uint32_t WPB = WG / 64;
 
 __device__ __forceinline__ uint64_t* counter(const dev_ctx& c, uint32_t i) {
@@ -207,6 +211,14 @@ __device__ __forceinline__ void count(const dev_ctx& c, uint32_t i, uint64_t v) 
 }
 // The abort flag lives in pinned host memory so that the host can also raise it while
 // kernels run (host-side watchdog); it is read with system scope.
+__device__ __forceinline__ bool profiling(const dev_ctx& c) { return (c.flags & FLAG_PROFILE) != 0; }
+// Adds now() - t to timer i (lane 0 only, profile flag only); returns now().
+__device__ __forceinline__ uint64_t ptick(const dev_ctx& c, uint32_t i, uint64_t t) {
+  if (!profiling(c)) return 0;
+  const uint64_t n = now();
+  if (lane() == 0) add_rlx(c.cnt + (size_t)i * CSTRIDE, n - t);
+  return n;
+}
 __device__ __forceinline__ bool aborted(const dev_ctx& c) {
   return uni(__hip_atomic_load(c.abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM)) != 0;
 }
@@ -279,7 +291,7 @@ __device__ bool submit(const dev_ctx& c, uint32_t q, bool want, uint32_t opc, ui
   for (;;) {
     bool progress = false;
     if (!written) {
-      if (ld_acq(slots + s) == ((T << 2) | SLOT_EMPTY)) {
+      if (ld_rlx(slots + s) == ((T << 2) | SLOT_EMPTY)) {
         sqe_t* e = c.sq + (size_t)q * c.depth + s;
         uint4* w = reinterpret_cast<uint4*>(e);
         const uint64_t prp1 = (uint64_t)(uintptr_t)line_ptr(c, line_idx);
@@ -293,7 +305,7 @@ __device__ bool submit(const dev_ctx& c, uint32_t q, bool want, uint32_t opc, ui
       }
     }
     progress = ballot(progress) != 0;
-    const uint32_t db = uni(ld_acq(&qs->db));
+    const uint32_t db = uni(ld_rlx(&qs->db));
     if ((int32_t)(db - (base + n)) >= 0) break;  // every command of this wave is issued
     if (ballot(written && want)) {
       uint32_t got = 0;
@@ -303,20 +315,23 @@ __device__ bool submit(const dev_ctx& c, uint32_t q, bool want, uint32_t opc, ui
       }
       got = rdlane(got, 0);
       if (got) {
-        uint32_t p = ld_acq(&qs->db);
+        uint32_t p = ld_rlx(&qs->db);
         const uint32_t p0 = p;
         for (;;) {
           const uint32_t t = p + lane();
-          const bool upd = ld_acq(slots + (t & dmask)) == ((t << 2) | SLOT_UPDATED);
+          const bool upd = ld_rlx(slots + (t & dmask)) == ((t << 2) | SLOT_UPDATED);
           const uint64_t b = ballot(upd);
           const uint32_t k = (~b == 0ull) ? 64u : ffs64(~b);
           if (lane() < k) st_rlx(slots + (t & dmask), (t << 2) | SLOT_ISSUED);
           p += k;
           if (k < 64) break;
         }
+        // one acquire for the scanned entries, one release for the doorbell and the lock
+        fence_acq();
+        fence_rel();
         if (lane() == 0) {
-          if (p != p0) st_rel(&qs->db, p);  // the doorbell write
-          st_rel(&qs->db_lock, 0u);
+          if (p != p0) st_rlx(&qs->db, p);  // the doorbell write
+          st_rlx(&qs->db_lock, 0u);
         }
         if (p != p0) progress = true;
       }
@@ -333,9 +348,9 @@ __device__ bool submit(const dev_ctx& c, uint32_t q, bool want, uint32_t opc, ui
 // ------------------------------------------------------------------ service wavefronts
 __device__ __forceinline__ bool service_should_exit(const dev_ctx& c, const launch_t& li) {
   if (aborted(c)) return true;
-  if (uni64(ld_acq(counter(c, C_USER_DONE))) < li.user_done_target) return false;
-  const uint64_t sub = uni64(ld_acq(counter(c, C_SUBMITTED)));
-  const uint64_t com = uni64(ld_acq(counter(c, C_COMPLETED)));
+  if (uni64(ld_rlx(counter(c, C_USER_DONE))) < li.user_done_target) return false;
+  const uint64_t sub = uni64(ld_rlx(counter(c, C_SUBMITTED)));
+  const uint64_t com = uni64(ld_rlx(counter(c, C_COMPLETED)));
   return com == sub;
 }
 
@@ -386,15 +401,17 @@ __device__ void controller(const dev_ctx& c, const launch_t& li, uint32_t cw) {
   for (;;) {
     if (((++loops) & 1023) == 0 && lane() == 0) count(c, C_CTRL_LOOPS, 1);
     const uint64_t t = now();
+    uint64_t tp = t;
     bool progress = false;
     // 1. fetch into free lanes
     uint64_t freem = ballot(!pend);
     for (uint32_t q = q0; q < c.num_qp && freem; q += qstep) {
       qp_t* qs = c.qp + q;
-      const uint32_t db = ld_acq(&qs->db);
-      const uint32_t f = ld_rlx(&qs->fetch);
+      const uint32_t db = uni(ld_rlx(&qs->db));
+      const uint32_t f = uni(ld_rlx(&qs->fetch));
       uint32_t avail = db - f;
       if (avail == 0) continue;
+      fence_acq();  // the entries behind the doorbell are visible from here on
       const uint32_t nfree = __popcll(freem);
       const uint32_t k = avail < nfree ? avail : nfree;
       if (shared) {
@@ -419,6 +436,10 @@ __device__ void controller(const dev_ctx& c, const launch_t& li, uint32_t cw) {
             const uint64_t first = old > tn ? old : tn;
             if (cas(c.next_tok, old, first + (uint64_t)k * c.tok_fp)) {
               tok0 = first;
+              if (profiling(c)) {
+                count(c, P_TOK_LEAD, (first - tn) >> 32);
+                count(c, P_TOK_N, 1);
+              }
               break;
             }
           }
@@ -460,6 +481,7 @@ __device__ void controller(const dev_ctx& c, const launch_t& li, uint32_t cw) {
       freem &= ~ballot(take);
       progress = true;
     }
+    tp = ptick(c, P_CTRL_FETCH, tp);
     // 2. execute ready commands: copy their blocks across PCIe
     const uint64_t tn = now();
     const uint64_t ready = ballot(pend && !p_copied && p_deadline <= tn);
@@ -496,10 +518,12 @@ __device__ void controller(const dev_ctx& c, const launch_t& li, uint32_t cw) {
     //    command that does not fit stays pending; the controller never waits for CQ
     //    room (the room frees only when the completion service sees a full window,
     //    which may need the very entries this wave is holding).
+    tp = ptick(c, P_CTRL_COPY, tp);
     const uint64_t done = ballot(pend && p_copied);
     if (done) {
-      if (ballot(pend && p_copied && p_opc == OPC_WRITE)) fence_rel_sys(); else fence_rel();
       uint64_t todo = done;
+      bool posting = false;
+      uint32_t pos = 0;
       while (todo) {
         const uint32_t q = rdlane(p_q, ffs64(todo));
         const uint64_t mm = ballot(((todo >> lane()) & 1ull) && p_q == q);
@@ -509,7 +533,7 @@ __device__ void controller(const dev_ctx& c, const launch_t& li, uint32_t cw) {
         if (lane() == 0) {
           uint32_t tail = ld_rlx(&qs->cq_tail);
           for (;;) {
-            const uint32_t head = ld_acq(&qs->cq_head);
+            const uint32_t head = ld_rlx(&qs->cq_head);
             const uint32_t room = c.depth - (tail - head);
             kk = room < k ? room : k;
             if (kk == 0) break;
@@ -523,27 +547,36 @@ __device__ void controller(const dev_ctx& c, const launch_t& li, uint32_t cw) {
         }
         base = rdlane(base, 0);
         kk = rdlane(kk, 0);
-        const bool mine = ((mm >> lane()) & 1ull) && mbcnt(mm) < kk;
-        if (mine) {
-          const uint32_t pos = base + mbcnt(mm);
+        if (((mm >> lane()) & 1ull) && mbcnt(mm) < kk) {
+          pos = base + mbcnt(mm);
           cqe_t* e = c.cq + (size_t)q * c.depth + (pos & dmask);
-          const uint32_t phase = ((pos >> c.depth_shift) & 1u) ^ 1u;
           e->dw0 = p_line;
           e->dw1 = p_opc;
           e->dw2 = (p_cid & 0xFFFF) | (q << 16);
+          posting = true;
         }
-        fence_rel();
-        if (mine) {
-          const uint32_t pos = base + mbcnt(mm);
-          cqe_t* e = c.cq + (size_t)q * c.depth + (pos & dmask);
+        todo &= ~mm;
+      }
+      const uint64_t pm = ballot(posting);
+      if (pm) {
+        // one release for the copied blocks (system scope when host memory was written)
+        // and the entry bodies, then the phase words that make the entries visible
+        if (ballot(posting && p_opc == OPC_WRITE)) fence_rel_sys(); else fence_rel();
+        if (posting) {
+          cqe_t* e = c.cq + (size_t)p_q * c.depth + (pos & dmask);
           const uint32_t phase = ((pos >> c.depth_shift) & 1u) ^ 1u;
           st_rlx(&e->dw3, (p_cid & 0xFFFF) | (phase << 16) | (p_status << 17));
           pend = false;
           p_copied = false;
         }
-        if (kk) progress = true;
-        todo &= ~mm;
+        progress = true;
       }
+      if (profiling(c) && pm != done && lane() == 0) count(c, P_CTRL_NOROOM, 1);
+    }
+    tp = ptick(c, P_CTRL_POST, tp);
+    if (!progress && profiling(c)) {
+      const bool any_pend = ballot(pend) != 0;
+      tp = ptick(c, any_pend ? P_CTRL_HOLD : P_CTRL_IDLE, t);
     }
     if (progress) {
       idle_since = now();
@@ -589,6 +622,7 @@ __device__ void completion(const dev_ctx& c, const launch_t& li, uint32_t w) {
   uint32_t loops = 0;
   for (;;) {
     if (((++loops) & 1023) == 0 && lane() == 0) count(c, C_CQ_LOOPS, 1);
+    const uint64_t tl = now();
     bool any = false;
     for (uint32_t k = 0; k < nmy && k < 64; ++k) {
       const uint32_t q = w + k * li.n_cq;
@@ -598,10 +632,21 @@ __device__ void completion(const dev_ctx& c, const launch_t& li, uint32_t w) {
       bool fresh = false;
       if (!((mk >> lane()) & 1ull)) {
         cqe_t* e = c.cq + (size_t)q * c.depth + (pos & dmask);
-        const uint32_t dw3 = ld_acq(&e->dw3);
+        const uint32_t dw3 = ld_rlx(&e->dw3);
         const uint32_t expect = ((pos >> c.depth_shift) & 1u) ^ 1u;
-        if (((dw3 >> 16) & 1u) == expect) {
-          fresh = true;
+        fresh = ((dw3 >> 16) & 1u) == expect;
+      }
+      // one acquire (the entries and the data they announce) and one release (the line
+      // states that publish that data) per window visit
+      const uint64_t nb = ballot(fresh);
+      if (nb) {
+        fence_acq();
+        fence_rel();
+      }
+      if (fresh) {
+        {
+          cqe_t* e = c.cq + (size_t)q * c.depth + (pos & dmask);
+          const uint32_t dw3 = ld_rlx(&e->dw3);
           const uint32_t line = e->dw0;
           const uint32_t opc = e->dw1;
           const uint32_t cid = dw3 & 0xFFFF;
@@ -609,29 +654,28 @@ __device__ void completion(const dev_ctx& c, const launch_t& li, uint32_t w) {
           if (status) raise_error(c, E_IO, ((uint64_t)q << 32) | cid);
           if (line < c.num_lines) {
             if (opc == OPC_READ)
-              add_rel(c.meta + line, 1ull);  // FETCHING -> READY
+              add_rlx(c.meta + line, 1ull);  // FETCHING -> READY
             else
-              add_rel(c.meta + line, (uint64_t)0 - 2ull);  // WRITEBACK -> READY
+              add_rlx(c.meta + line, (uint64_t)0 - 2ull);  // WRITEBACK -> READY
           } else {
             raise_error(c, E_PROTO, ((uint64_t)q << 32) | cid);
           }
           uint32_t* sl = c.slot + (size_t)q * c.depth + (cid & dmask);
           const uint32_t sw = ld_rlx(sl);
-          st_rel(sl, (((sw >> 2) + c.depth) << 2) | SLOT_EMPTY);
+          st_rlx(sl, (((sw >> 2) + c.depth) << 2) | SLOT_EMPTY);
         }
       }
-      const uint64_t nb = ballot(fresh);
       if (nb) {
         any = true;
         mk |= nb;
         if (lane() == 0) {
-          add_rel(counter(c, C_COMPLETED), (uint64_t)__popcll(nb));
+          add_rlx(counter(c, C_COMPLETED), (uint64_t)__popcll(nb));
           add_rlx(counter(c, C_CQ_ENTRIES), (uint64_t)__popcll(nb));
         }
         if (mk == ~0ull) {
           o += 64;
           mk = 0;
-          if (lane() == 0) st_rel(&c.qp[q].cq_head, o);
+          if (lane() == 0) st_rlx(&c.qp[q].cq_head, o);
         }
         if (lane() == k) {
           off = o;
@@ -639,6 +683,7 @@ __device__ void completion(const dev_ctx& c, const launch_t& li, uint32_t w) {
         }
       }
     }
+    ptick(c, any ? P_CQ_BUSY : P_CQ_IDLE, tl);
     if (any) {
       idle_since = now();
       continue;
@@ -692,7 +737,7 @@ __device__ __forceinline__ void unlock(uint32_t* l) { st_rel(l, 0u); }
 // undone.  Returns the old word (0 state INVALID on failure).
 __device__ __forceinline__ bool pin_way(const dev_ctx& c, uint32_t idx, uint32_t tag, uint32_t cnt,
                                         uint32_t& res, uint32_t& gen) {
-  const uint64_t old = add_acqrel(c.meta + idx, RC_ONE * cnt);
+  const uint64_t old = add_rlx(c.meta + idx, RC_ONE * cnt);
   if (m_tag(old) == tag && m_state(old) != ST_INVALID) {
     res = (m_state(old) == ST_FETCHING) ? A_JOIN : A_HIT;
     gen = m_gen(old);
@@ -711,20 +756,50 @@ __device__ __forceinline__ bool pin_way(const dev_ctx& c, uint32_t idx, uint32_t
 //    the caller submits its WRITE, waits for it, and calls again with `retake` = the line.
 //  * EAGAIN: every way is pinned or in flight (cache deadlock avoidance, Sec. 2.3.2).
 // Misses take the set lock so that a tag is never inserted twice; hits never lock.
+// Probes a set for `tag`: every way's metadata word is loaded before any is compared
+// (16 device-coherent loads in flight per lane), so a probe costs one round trip for up
+// to 16 ways.  Returns the way or -1, and the word seen.
+__device__ __forceinline__ int probe_set(const dev_ctx& c, uint32_t base, uint32_t tag, uint64_t& seen) {
+  for (uint32_t g = 0; g < c.assoc; g += 16) {
+    uint64_t w[16];
+#pragma unroll
+    for (uint32_t i = 0; i < 16; ++i) w[i] = (g + i < c.assoc) ? ld_rlx(c.meta + base + g + i) : 0ull;
+    int f = -1;
+#pragma unroll
+    for (uint32_t i = 0; i < 16; ++i)
+      if (f < 0 && g + i < c.assoc && m_tag(w[i]) == tag && m_state(w[i]) != ST_INVALID) {
+        f = (int)(g + i);
+        seen = w[i];
+      }
+    if (f >= 0) return f;
+  }
+  return -1;
+}
+
+// `cnt` == 0 asks for an unpinned hit: a resident or in-flight line is reported with its
+// generation and not pinned (the caller validates after reading); a miss still pins its
+// claim with one reference.
 __device__ acq_t acquire_try(const dev_ctx& c, uint32_t line_id, uint32_t cnt, int retake) {
   acq_t r{A_NONE, 0, 0};
   const uint32_t set = set_of(c, line_id);
   const uint32_t base = set * c.assoc;
+  const bool pin_hits = cnt != 0;
+  if (cnt == 0) cnt = 1;
   if (retake < 0) {
     // lock-free probe
-    for (uint32_t w = 0; w < c.assoc; ++w) {
-      const uint64_t m = ld_rlx(c.meta + base + w);
-      if (m_tag(m) == line_id && m_state(m) != ST_INVALID) {
-        if (pin_way(c, base + w, line_id, cnt, r.res, r.gen)) {
-          r.idx = base + w;
-          return r;
-        }
-        break;
+    uint64_t m = 0;
+    const int w = probe_set(c, base, line_id, m);
+    if (w >= 0) {
+      if (!pin_hits) {
+        r.res = (m_state(m) == ST_FETCHING) ? A_JOIN : A_HIT;
+        r.gen = m_gen(m);
+        r.idx = base + (uint32_t)w;
+        if (!(m & M_REF)) or_rlx(c.meta + r.idx, M_REF);
+        return r;
+      }
+      if (pin_way(c, base + (uint32_t)w, line_id, cnt, r.res, r.gen)) {
+        r.idx = base + (uint32_t)w;
+        return r;
       }
     }
   }
@@ -733,6 +808,15 @@ __device__ acq_t acquire_try(const dev_ctx& c, uint32_t line_id, uint32_t cnt, i
   for (uint32_t w = 0; w < c.assoc; ++w) {
     const uint64_t m = ld_rlx(c.meta + base + w);
     if (m_tag(m) == line_id && m_state(m) != ST_INVALID) {
+      if (!pin_hits) {
+        r.res = (m_state(m) == ST_FETCHING) ? A_JOIN : A_HIT;
+        r.gen = m_gen(m);
+        r.idx = base + w;
+        if (!(m & M_REF)) or_rlx(c.meta + r.idx, M_REF);
+        if (retake >= 0) add_rel(c.meta + retake, (uint64_t)0 - RC_ONE);
+        unlock(c.set_lock + set);
+        return r;
+      }
       if (pin_way(c, base + w, line_id, cnt, r.res, r.gen)) {
         r.idx = base + w;
         if (retake >= 0) add_rel(c.meta + retake, (uint64_t)0 - RC_ONE);  // drop our WB pin
@@ -808,6 +892,13 @@ __device__ acq_t acquire_try(const dev_ctx& c, uint32_t line_id, uint32_t cnt, i
 // wave (level-1 coalescing, Sec. 3.3.2: one leader lane per distinct line), acquires the
 // leaders' lines (level-2 coalescing in the cache), submits the wave's READs with one
 // reservation, and broadcasts each leader's line to its followers.
+// Pinning modes of a chunk.
+enum : uint32_t {
+  PIN_LINE = 0,  // one pin per distinct line (writers, serialized traces)
+  PIN_EACH = 1,  // one pin per lane (host tickets)
+  PIN_NONE = 2   // optimistic readers: hits are not pinned, a wave's own misses are
+};
+
 struct chunk_t {
   uint32_t line_id;  // requested line (valid when act)
   uint32_t off;      // byte offset inside the line
@@ -817,7 +908,12 @@ struct chunk_t {
   uint32_t cnt;      // leader: lanes sharing its line
   uint32_t gen;      // generation of the line when acquired
   bool act;          // this lane carries a lookup
+  bool pinned;       // this lane's line holds a pin taken by this chunk
 };
+
+__device__ __forceinline__ bool st_ok(uint32_t st) {
+  return st == A_HIT || st == A_JOIN || st == A_MISS;
+}
 
 __device__ __forceinline__ void dedup(chunk_t& ch) {
   uint64_t todo = ballot(ch.act);
@@ -835,12 +931,12 @@ __device__ __forceinline__ void dedup(chunk_t& ch) {
 
 // Acquire + submit for the leaders of `ch`.  On return every active lane has st in
 // {A_HIT, A_JOIN, A_MISS, A_EAGAIN} (or the context aborted).  Counts stats.
-// pin_each: every lane gets its own pin (host tickets); otherwise one pin per line.
 __device__ bool chunk_issue(const dev_ctx& c, chunk_t& ch, uint32_t q, bool count_stats,
-                            bool pin_each = false) {
+                            uint32_t pin_mode = PIN_LINE) {
+  const uint64_t t_issue = now();
   dedup(ch);
   const bool lead = ch.act && ch.leader == lane();
-  const uint32_t npin = pin_each ? ch.cnt : 1u;
+  const uint32_t npin = pin_mode == PIN_EACH ? ch.cnt : (pin_mode == PIN_LINE ? 1u : 0u);
   uint32_t st = A_NONE, idx = 0, gen = 0;
   int retake = -1;
   bool pending = lead;
@@ -872,8 +968,10 @@ __device__ bool chunk_issue(const dev_ctx& c, chunk_t& ch, uint32_t q, bool coun
       slba = (uint64_t)lid * blk_per_line;
       if (slba + nblk > c.store_blocks) nblk = (uint32_t)(c.store_blocks - slba);
     }
+    const uint64_t ts = now();
     if (!submit(c, q, rd, OPC_READ, idx, slba, nblk)) return false;
     if (!submit(c, q, wb, OPC_WRITE, idx, slba, nblk)) return false;
+    ptick(c, P_U_SUBMIT, ts);
     if (ballot(wb)) {
       const uint64_t nwb = __popcll(ballot(wb));
       if (lane() == 0) count(c, C_WB_EVICT, nwb);
@@ -881,25 +979,31 @@ __device__ bool chunk_issue(const dev_ctx& c, chunk_t& ch, uint32_t q, bool coun
       spin_t sw;
       bool waiting = wb;
       while (ballot(waiting)) {
-        if (waiting && m_state(ld_acq(c.meta + idx)) != ST_WRITEBACK) waiting = false;
+        if (waiting && m_state(ld_rlx(c.meta + idx)) != ST_WRITEBACK) waiting = false;
         if (ballot(waiting) && !sw.step(c, 0xB0000000ull | idx)) return false;
       }
+      fence_acq();
     }
     if (ballot(pending && st == A_NONE)) {
       if (!sp.step(c, 0xA0000000ull | ch.line_id)) return false;
     }
   }
+  const bool pin = lead && (npin ? st_ok(st) : st == A_MISS);
   // broadcast to followers
   const uint32_t lst = shfl32(st, ch.leader);
   const uint32_t lidx = shfl32(idx, ch.leader);
   const uint32_t lgen = shfl32(gen, ch.leader);
+  const uint32_t lpin = shfl32(pin ? 1u : 0u, ch.leader);
   if (ch.act) {
     ch.st = lst;
     ch.idx = lidx;
     ch.gen = lgen;
+    ch.pinned = lpin != 0;
   } else {
     ch.st = A_NONE;
+    ch.pinned = false;
   }
+  ptick(c, P_U_ISSUE, t_issue);
   if (count_stats) {
     const uint64_t nreq = __popcll(ballot(ch.act && ch.st != A_EAGAIN));
     const uint64_t nmiss = __popcll(ballot(ch.act && ch.st == A_MISS));
@@ -914,22 +1018,41 @@ __device__ bool chunk_issue(const dev_ctx& c, chunk_t& ch, uint32_t q, bool coun
   return true;
 }
 
-// Waits until every pinned line of the chunk has left FETCHING (acquire).
-__device__ bool chunk_wait(const dev_ctx& c, const chunk_t& ch) {
-  bool waiting = ch.act && (ch.st == A_HIT || ch.st == A_JOIN || ch.st == A_MISS);
+// Waits until the chunk's in-flight lines have been filled: a lane waits while its line
+// still carries its tag and generation in the FETCHING state.  With `acquire`, one
+// acquire fence follows (plain loads of the line data are then safe); without it the
+// caller reads the data with device-coherent loads.
+__device__ bool chunk_wait(const dev_ctx& c, const chunk_t& ch, bool acquire = true) {
+  const uint64_t t_wait = now();
+  bool waiting = ch.act && (ch.st == A_JOIN || ch.st == A_MISS);
   spin_t sp;
   while (true) {
-    if (waiting && m_state(ld_acq(c.meta + ch.idx)) != ST_FETCHING) waiting = false;
+    if (waiting) {
+      const uint64_t m = ld_rlx(c.meta + ch.idx);
+      if (m_state(m) != ST_FETCHING || m_tag(m) != ch.line_id || m_gen(m) != ch.gen) waiting = false;
+    }
     if (!ballot(waiting)) break;
     if (!sp.step(c, 0xD0000000ull | ch.idx)) return false;
   }
+  if (acquire) fence_acq();
+  ptick(c, P_U_WAIT, t_wait);
   return true;
 }
 
-// Unpins the chunk's lines (leaders only; one pin per distinct line).
+// True when the line of this lane still holds the data the chunk saw: same tag and
+// generation, in a state with valid data.  Loaded device-coherently after the caller's
+// data loads have completed.
+__device__ __forceinline__ bool line_still_valid(const dev_ctx& c, uint32_t idx, uint32_t tag,
+                                                 uint32_t gen) {
+  const uint64_t m = ld_rlx(c.meta + idx);
+  const uint32_t st = m_state(m);
+  return m_tag(m) == tag && m_gen(m) == gen &&
+         (st == ST_READY || st == ST_DIRTY || st == ST_WRITEBACK);
+}
+
+// Drops the pins the chunk holds (leaders only).
 __device__ __forceinline__ void chunk_release(const dev_ctx& c, chunk_t& ch, bool wrote) {
-  const bool lead = ch.act && ch.leader == lane() &&
-                    (ch.st == A_HIT || ch.st == A_JOIN || ch.st == A_MISS);
+  const bool lead = ch.act && ch.leader == lane() && ch.pinned;
   if (wrote) {
     if (lead) add_rel(c.meta + ch.idx, (uint64_t)0 - RC_ONE);
   } else {

@@ -55,10 +55,9 @@ def test_gather_bit_exact(image, lookups, mode):
                               .reshape(ROWS, DIM)[lookups])
         st = ctx.stats()
         assert st["consumed"] == lookups.size
-        if mode == agile.MODE_SYNC:
-            assert st["requests"] == lookups.size
-        else:  # dropped prefetches are presented again
-            assert st["requests"] >= lookups.size
+        # a lookup is presented again when its unpinned line changed tenant while it was
+        # read, or when its prefetched chunk was dropped after an EAGAIN
+        assert st["requests"] >= lookups.size
         assert st["hits"] + st["misses"] == st["requests"]
         distinct_lines = np.unique(lookups // 16).size
         assert distinct_lines <= st["read_cmds"] <= st["misses"]

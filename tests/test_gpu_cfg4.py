@@ -1,0 +1,154 @@
+"""GPU parity of the write path (differentiation): embedding-bag backward fused with SGD
+into cached rows, dirty lines written back on eviction and at flush.  Expected values
+come from the oracle (C8) and from central finite differences of the linear loss."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2504_19365_amd import agile, gen
+
+from gpu_helpers import check_quiescent_invariants, cuda, dump_meta, table_store
+
+pytestmark = pytest.mark.gpu
+
+
+def _batch(rows, T, B, lmax, alpha, seed):
+    return gen.embbag_batch(gen.zipf_cum(rows, alpha), B, T, 1, lmax, seed=seed)
+
+
+def _run_bwd(ctx, tb, off, idx, B, g, lr):
+    ctx.embbag_backward_sgd(tb, cuda(idx), cuda(off), B, cuda(g), lr)
+    ctx.sync()
+
+
+@pytest.mark.parametrize("cache_kw", [dict(cache_bytes=8 << 20, assoc=16),
+                                      dict(cache_bytes=16 * 4096, assoc=4)])
+def test_backward_sgd_flush_equals_oracle(cache_kw):
+    rows, dim, T, B, lr = 65536, 64, 4, 512, 0.01
+    buf = table_store(rows, dim, [20, 21, 22, 23])
+    ref = buf.array.copy()
+    ctx = agile.Context(line_bytes=4096, num_qp=4, qp_depth=256, timeout_ns=int(10e9),
+                        **cache_kw)
+    try:
+        ctx.open_store(buf)
+        tb = ctx.tables(rows, dim, T)
+        for step in range(2):
+            off, idx = _batch(rows, T, B, 40, 1.1, seed=30 + step)
+            g = gen.normal_f32(31 + step, B * T * dim).reshape(B * T, dim)
+            ctx.stats(reset=True)
+            _run_bwd(ctx, tb, off, idx, B, g, lr)
+            st = ctx.stats()
+            uniq = oracle.embbag_backward_sgd(ref, rows, dim, T, idx, off, B, g, lr)
+            assert st["rows_updated"] == uniq
+        tags, states, rc = dump_meta(ctx)
+        ndirty = int((states == 3).sum())
+        wb_evict = ctx.stats()["wb_evict"]
+        ctx.stats(reset=True)
+        ctx.flush()
+        s = ctx.stats()
+        assert s["wb_flush"] == ndirty  # each dirty line written back exactly once
+        check_quiescent_invariants(ctx, cache_kw["assoc"])
+        assert not np.any(dump_meta(ctx)[1] == 3)
+        got = buf.array.view(np.float32)
+        exp = ref.view(np.float32)
+        assert np.array_equal(got.view(np.uint32), exp.view(np.uint32))
+        if cache_kw["cache_bytes"] < (1 << 20):
+            assert wb_evict > 0  # the tiny cache had to write dirty victims back
+        # the forward now reads the updated values through the cache
+        off, idx = _batch(rows, T, B, 40, 1.1, seed=99)
+        import torch
+        out = torch.empty((B * T, dim), device="cuda")
+        ctx.embbag_forward(tb, cuda(idx), cuda(off), B, 0, out)
+        ctx.sync()
+        exp_f = oracle.embbag_forward(ref, rows, dim, T, idx, off, B, 0)
+        assert np.array_equal(out.cpu().numpy(), exp_f)
+    finally:
+        ctx.close_store()
+        ctx.shutdown()
+        buf.free()
+
+
+def test_finite_differences_on_small_table():
+    """Central differences (eps = 1e-3) of L = sum g * pooled, evaluated with GPU
+    forwards on a 256 x 8 table, against the gradient the GPU applied."""
+    import torch
+    rows, dim, B = 256, 8, 64
+    buf = table_store(rows, dim, [0], extra_bytes=0)
+    base = buf.array.copy()
+    off, idx = _batch(rows, 1, B, 40, 1.1, seed=0)
+    gout = gen.normal_f32(31, B * dim).reshape(B, dim)
+    ctx = agile.Context(cache_bytes=1 << 20, line_bytes=4096, assoc=8, num_qp=1, qp_depth=64,
+                        timeout_ns=int(5e9))
+    try:
+        ctx.open_store(buf)
+        tb = ctx.tables(rows, dim, 1)
+        d_idx, d_off = cuda(idx), cuda(off)
+        out = torch.empty((B, dim), device="cuda")
+
+        def loss():
+            ctx.invalidate()
+            ctx.embbag_forward(tb, d_idx, d_off, B, 0, out)
+            ctx.sync()
+            return float((gout.astype(np.float64) * out.cpu().numpy().astype(np.float64)).sum())
+
+        W = buf.array[:rows * dim * 4].view(np.float32)
+        rng = np.random.default_rng(0)
+        used = np.unique(idx)
+        picks = [(int(r), int(d)) for r in rng.choice(used, 24) for d in rng.choice(dim, 1)]
+        picks += [(int(r), 0) for r in np.setdiff1d(np.arange(rows), used)[:4]]
+        fds = {}
+        for r, d in picks:
+            w = np.float32(W[r * dim + d])
+            wp, wm = np.float32(w + np.float32(1e-3)), np.float32(w - np.float32(1e-3))
+            W[r * dim + d] = wp
+            lp = loss()
+            W[r * dim + d] = wm
+            lm = loss()
+            W[r * dim + d] = w
+            fds[(r, d)] = (lp - lm) / (float(wp) - float(wm))
+        ctx.invalidate()
+        # GPU gradient with lr = 1: g = w - fl(w - g), exact up to the rounding of w - g
+        ctx.embbag_backward_sgd(tb, d_idx, d_off, B, cuda(gout), 1.0)
+        ctx.sync()
+        ctx.flush()
+        grad = (base.view(np.float32)[:rows * dim].astype(np.float64) -
+                buf.array.view(np.float32)[:rows * dim].astype(np.float64)).reshape(rows, dim)
+        ref = base.copy()
+        oracle.embbag_backward_sgd(ref, rows, dim, 1, idx, off, B, gout, 1.0)
+        assert np.array_equal(buf.array.view(np.uint32), ref.view(np.uint32))
+        U = 2.0 ** -24
+        for (r, d), fd in fds.items():
+            gr = grad[r, d]
+            tol = 1e-3 * max(1.0, abs(gr)) + 4 * U * (abs(float(base.view(np.float32)[r * dim + d])) + abs(gr))
+            assert abs(fd - gr) <= tol, (r, d, fd, gr)
+    finally:
+        ctx.close_store()
+        ctx.shutdown()
+        buf.free()
+
+
+def test_autograd_function_matches_direct_calls():
+    import torch
+    from paper_2504_19365_amd.autograd import EmbeddingBag
+    rows, dim, T, B, lr = 16384, 64, 2, 128, 0.01
+    buf = table_store(rows, dim, [5, 6])
+    ref = buf.array.copy()
+    ctx = agile.Context(cache_bytes=4 << 20, line_bytes=4096, assoc=16, num_qp=2, qp_depth=128,
+                        timeout_ns=int(5e9))
+    try:
+        ctx.open_store(buf)
+        emb = EmbeddingBag(ctx, rows, dim, T, lr)
+        off, idx = _batch(rows, T, B, 40, 1.1, seed=7)
+        g = gen.normal_f32(8, B * T * dim).reshape(B * T, dim)
+        pooled = emb(cuda(idx), cuda(off), B)
+        exp = oracle.embbag_forward(ref, rows, dim, T, idx, off, B, 0)
+        assert np.array_equal(pooled.detach().cpu().numpy(), exp)
+        (pooled * cuda(g)).sum().backward()
+        ctx.sync()
+        ctx.flush()
+        oracle.embbag_backward_sgd(ref, rows, dim, T, idx, off, B, g, lr)
+        assert np.array_equal(buf.array.view(np.uint32), ref.view(np.uint32))
+    finally:
+        ctx.close_store()
+        ctx.shutdown()
+        buf.free()
