@@ -40,7 +40,7 @@ def parse():
     ap.add_argument("--tables", type=int, default=8)
     ap.add_argument("--batch", type=int, default=2048)
     ap.add_argument("--cache-gib", type=float, default=2.0)
-    ap.add_argument("--sweep", default="0,64,512", help="K values for async/sync; '' = skip")
+    ap.add_argument("--sweep", default="0,512", help="K values for async/sync; '' = skip")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--profile-only", action="store_true",

@@ -94,8 +94,10 @@ agile_status agile_init(const agile_config* cfg, agile_ctx* out);
  * Open stores are closed without a flush. */
 agile_status agile_shutdown(agile_ctx ctx);
 
-/* Pinned, device-mapped host memory for store images (hipHostMalloc).  The caller owns
- * it and frees it with agile_host_free after closing any store on it. */
+/* Pinned, device-mapped host memory for store images (hipHostMalloc, non-coherent so
+ * that the GPU reads it in whole cache lines).  The caller owns it and frees it with
+ * agile_host_free after closing any store on it.  Host writes to it must happen while
+ * no kernel of the context runs. */
 agile_status agile_host_alloc(uint64_t bytes, void** out);
 agile_status agile_host_free(void* p);
 
@@ -225,6 +227,14 @@ agile_status agile_embbag_forward(agile_ctx ctx, agile_store store, const agile_
 agile_status agile_debug_trace(agile_ctx ctx, agile_store store, const uint64_t* d_lines,
                                const uint8_t* d_writes, uint64_t n, uint8_t* d_hit,
                                int32_t* d_way, void* stream);
+
+/* Roofline probe (measurement only): `waves` wavefronts copy n 4 KiB blocks from src
+ * (pinned host memory or device memory) into d_dst (device, dst_blocks blocks), block i
+ * being src block d_list[i] (device uint64; NULL = i), `per_wave` (1..4) blocks in flight
+ * per wave, with the emulated controller's copy routine.  Stream-ordered. */
+agile_status agile_probe_copy(const void* src, const uint64_t* d_list, uint64_t n, void* d_dst,
+                              uint64_t dst_blocks, uint32_t waves, uint32_t per_wave,
+                              void* stream);
 
 /* Raw device counters in their internal order (for diagnostics): out[i] for i < n. */
 agile_status agile_debug_counters(agile_ctx ctx, uint64_t* out, uint32_t n);

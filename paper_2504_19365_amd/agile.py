@@ -101,6 +101,7 @@ def lib():
                                                C.c_float, vp]),
             "agile_debug_dump": (st, [vp, vp, vp, vp, vp]),
             "agile_debug_counters": (st, [vp, vp, u32]),
+            "agile_probe_copy": (st, [vp, vp, u64, vp, u64, u32, u32, vp]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -132,6 +133,14 @@ def _stream(stream) -> int:
     if isinstance(stream, int):
         return stream
     return stream.cuda_stream
+
+
+def probe_copy(src, lst, n: int, dst, dst_blocks: int, waves: int, per_wave: int, stream=None):
+    """Roofline probe: copies n 4 KiB blocks (see agile_probe_copy)."""
+    s = lib().agile_probe_copy(_ptr(src), _ptr(lst), n, _ptr(dst), dst_blocks, waves, per_wave,
+                               _stream(stream))
+    if s != OK:
+        raise AgileError(s, "agile_probe_copy")
 
 
 def default_config(**kw) -> Config:

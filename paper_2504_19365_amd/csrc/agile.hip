@@ -656,6 +656,29 @@ __global__ __launch_bounds__(WG) void k_bwd_sgd(dev_ctx c, launch_t li, bwd_args
   user_wave_done(c);
 }
 
+// Roofline probe: waves copy 4 KiB blocks from `src` (pinned host or HBM) to `dst`
+// (HBM), `per` blocks in flight per wave, with the same wave-cooperative copy the emulated
+// controller uses.  Block i is src block `list[i]` (or i when list is NULL) and lands in
+// dst block (i % dst_blocks).
+__global__ __launch_bounds__(WG) void k_probe_copy(const uint8_t* src, const uint64_t* list, uint64_t n,
+                                                   uint8_t* dst, uint64_t dst_blocks, uint32_t per) {
+  const uint32_t w = blockIdx.x * WPB + threadIdx.x / 64;
+  const uint32_t W = gridDim.x * WPB;
+  for (uint64_t i0 = (uint64_t)w * per; i0 < n; i0 += (uint64_t)W * per) {
+    uint8_t* d[4];
+    const uint8_t* s[4];
+    uint32_t k = 0;
+    for (uint32_t j = 0; j < per && i0 + j < n; ++j) {
+      const uint64_t i = i0 + j;
+      const uint64_t b = list ? list[i] : i;
+      s[k] = src + (b << 12);
+      d[k] = dst + ((i % dst_blocks) << 12);
+      ++k;
+    }
+    copy_blocks(d, s, k);
+  }
+}
+
 // Debug dump: tag (or -1), state, pin count per line.
 __global__ void k_dump(dev_ctx c, int64_t* tags, uint8_t* states, uint32_t* rc) {
   const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -989,7 +1012,11 @@ agile_status agile_shutdown(agile_ctx ctx) {
 agile_status agile_host_alloc(uint64_t bytes, void** out) {
   if (!out || bytes == 0) return AGILE_EINVAL;
   *out = nullptr;
-  if (hipHostMalloc(out, bytes, hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess) {
+  // Non-coherent pinned memory: the GPU reads it through its L2 in whole cache lines
+  // (one PCIe request per line instead of one per 16-byte lane access).  The emulated
+  // controller invalidates with system scope before every copy batch and releases with
+  // system scope after writing, so both directions stay correct.
+  if (hipHostMalloc(out, bytes, hipHostMallocMapped | hipHostMallocNonCoherent) != hipSuccess) {
     (void)hipGetLastError();
     return AGILE_ENOMEM;
   }
@@ -1334,6 +1361,22 @@ agile_status agile_embbag_backward_sgd(agile_ctx ctx, agile_store store, const a
     hipLaunchKernelGGL(k_bwd_sgd<4>, grid, dim3(WG), 0, hs, ctx->d, li, a);
   HIPCHK(ctx, hipGetLastError());
   return AGILE_OK;
+}
+
+agile_status agile_probe_copy(const void* src, const uint64_t* d_list, uint64_t n, void* d_dst, uint64_t dst_blocks,
+                              uint32_t waves, uint32_t per_wave, void* stream) {
+  if (!src || !d_dst || n == 0 || dst_blocks == 0 || waves == 0 || per_wave == 0 || per_wave > 4)
+    return AGILE_EINVAL;
+  hipPointerAttribute_t attr;
+  memset(&attr, 0, sizeof(attr));
+  const uint8_t* s = (const uint8_t*)src;
+  if (hipPointerGetAttributes(&attr, src) == hipSuccess && attr.type == hipMemoryTypeHost && attr.devicePointer)
+    s = (const uint8_t*)attr.devicePointer + ((const uint8_t*)src - (const uint8_t*)attr.hostPointer);
+  (void)hipGetLastError();
+  const uint32_t blocks = (waves + WPB - 1) / WPB;
+  hipLaunchKernelGGL(k_probe_copy, dim3(blocks), dim3(WG), 0, (hipStream_t)stream, s, d_list, n, (uint8_t*)d_dst,
+                     dst_blocks, per_wave);
+  return hipGetLastError() == hipSuccess ? AGILE_OK : AGILE_EHIP;
 }
 
 // ---- diagnostics used by tests (declared in agile.h)

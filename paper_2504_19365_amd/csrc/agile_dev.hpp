@@ -60,6 +60,7 @@ __device__ __forceinline__ T or_rlx(T* p, U v) {
 __device__ __forceinline__ void fence_acq() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent"); }
 __device__ __forceinline__ void fence_rel() { __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent"); }
 __device__ __forceinline__ void fence_rel_sys() { __builtin_amdgcn_fence(__ATOMIC_RELEASE, ""); }
+__device__ __forceinline__ void fence_acq_sys() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, ""); }
 // Completes this wave's outstanding loads before a following relaxed atomic; enough to
 // retire read-only pins (no stores need publishing).
 __device__ __forceinline__ void loads_done() {
@@ -354,30 +355,65 @@ __device__ __forceinline__ bool service_should_exit(const dev_ctx& c, const laun
   return com == sub;
 }
 
-// Copies two 4 KiB blocks with the whole wave: 16-byte lanes, 1 KiB per instruction,
-// all eight loads issued before the stores.  A null source skips that block.
-__device__ __forceinline__ void copy2(uint8_t* d0, const uint8_t* s0, uint8_t* d1, const uint8_t* s1) {
-  uint4 a[4], b[4];
-  const uint4* x0 = reinterpret_cast<const uint4*>(s0);
-  const uint4* x1 = reinterpret_cast<const uint4*>(s1);
-  if (s0) {
+// Position of the r-th (0-based) set bit of m; r < popcount(m).
+__device__ __forceinline__ uint32_t nth_set_bit(uint64_t m, uint32_t r) {
+  uint32_t pos = 0;
 #pragma unroll
-    for (uint32_t i = 0; i < 4; ++i) a[i] = x0[i * 64 + lane()];
-  }
-  if (s1) {
+  for (uint32_t step = 32; step; step >>= 1)
+    if ((uint32_t)__popcll(m & ((1ull << (pos + step)) - 1ull)) <= r) pos += step;
+  return pos;
+}
+__device__ __forceinline__ uint64_t shfl64(uint64_t v, uint32_t src) {
+  return ((uint64_t)shfl32((uint32_t)(v >> 32), src) << 32) | shfl32((uint32_t)v, src);
+}
+
+// Copies one 4 KiB block with the whole wave: 16-byte lanes, 1 KiB per instruction, so
+// that each instruction touches a single page of the pinned image.  `nb` (1..4) blocks
+// are copied together with all their loads issued before the stores.
+__device__ __forceinline__ void copy_blocks(uint8_t* const* dst, const uint8_t* const* src, uint32_t nb) {
+  uint4 v[4][4];
 #pragma unroll
-    for (uint32_t i = 0; i < 4; ++i) b[i] = x1[i * 64 + lane()];
-  }
-  if (s0) {
-    uint4* y0 = reinterpret_cast<uint4*>(d0);
+  for (uint32_t b = 0; b < 4; ++b)
+    if (b < nb) {
+      const uint4* s = reinterpret_cast<const uint4*>(src[b]);
 #pragma unroll
-    for (uint32_t i = 0; i < 4; ++i) y0[i * 64 + lane()] = a[i];
-  }
-  if (s1) {
-    uint4* y1 = reinterpret_cast<uint4*>(d1);
+      for (uint32_t i = 0; i < 4; ++i) v[b][i] = s[i * 64 + lane()];
+    }
 #pragma unroll
-    for (uint32_t i = 0; i < 4; ++i) y1[i * 64 + lane()] = b[i];
+  for (uint32_t b = 0; b < 4; ++b)
+    if (b < nb) {
+      uint4* d = reinterpret_cast<uint4*>(dst[b]);
+#pragma unroll
+      for (uint32_t i = 0; i < 4; ++i) d[i * 64 + lane()] = v[b][i];
+    }
+}
+
+// Copies the blocks of the commands in `ready`, up to four 4 KiB blocks in flight per
+// wave (the store-side memory-level parallelism comes from the number of controller
+// wavefronts).
+__device__ void copy_cmds(const dev_ctx& c, uint64_t ready, uint32_t p_opc, uint32_t p_nblk,
+                          uint32_t p_status, uint64_t p_slba, uint64_t p_prp) {
+  uint8_t* dst[4];
+  const uint8_t* src[4];
+  uint32_t k = 0;
+  for (uint64_t rem = ready; rem; rem &= rem - 1) {
+    const uint32_t l = ffs64(rem);
+    if (rdlane(p_status, l)) continue;
+    const uint32_t nblk = rdlane(p_nblk, l);
+    const bool rd = rdlane(p_opc, l) == OPC_READ;
+    uint8_t* hbm = (uint8_t*)(uintptr_t)rdlane64(p_prp, l);
+    uint8_t* img = c.image + (rdlane64(p_slba, l) << 12);
+    for (uint32_t b = 0; b < nblk; ++b) {
+      const uint64_t o = (uint64_t)b << 12;
+      src[k] = rd ? img + o : hbm + o;
+      dst[k] = rd ? hbm + o : img + o;
+      if (++k == 4) {
+        copy_blocks(dst, src, 4);
+        k = 0;
+      }
+    }
   }
+  if (k) copy_blocks(dst, src, k);
 }
 
 // Emulated NVMe controller wavefront (Sec. 2.1 device side).  It keeps up to 64 commands
@@ -486,30 +522,8 @@ __device__ void controller(const dev_ctx& c, const launch_t& li, uint32_t cw) {
     const uint64_t tn = now();
     const uint64_t ready = ballot(pend && !p_copied && p_deadline <= tn);
     if (ready) {
-      uint64_t rem = ready;
-      while (rem) {
-        const uint32_t l0 = ffs64(rem);
-        rem &= rem - 1;
-        const uint32_t l1 = rem ? ffs64(rem) : 64u;
-        if (rem) rem &= rem - 1;
-        const uint32_t nb0 = rdlane(p_status, l0) ? 0u : rdlane(p_nblk, l0);
-        const uint32_t nb1 = (l1 < 64 && !rdlane(p_status, l1)) ? rdlane(p_nblk, l1) : 0u;
-        const bool rd0 = rdlane(p_opc, l0) == OPC_READ;
-        const bool rd1 = l1 < 64 && rdlane(p_opc, l1) == OPC_READ;
-        uint8_t* hbm0 = (uint8_t*)(uintptr_t)rdlane64(p_prp, l0);
-        uint8_t* img0 = c.image + (rdlane64(p_slba, l0) << 12);
-        uint8_t* hbm1 = l1 < 64 ? (uint8_t*)(uintptr_t)rdlane64(p_prp, l1) : nullptr;
-        uint8_t* img1 = l1 < 64 ? c.image + (rdlane64(p_slba, l1) << 12) : nullptr;
-        const uint32_t maxb = nb0 > nb1 ? nb0 : nb1;
-        for (uint32_t b = 0; b < maxb; ++b) {
-          const uint64_t o = (uint64_t)b << 12;
-          const uint8_t* s0 = b < nb0 ? (rd0 ? img0 : hbm0) + o : nullptr;
-          uint8_t* t0 = b < nb0 ? (rd0 ? hbm0 : img0) + o : nullptr;
-          const uint8_t* s1 = b < nb1 ? (rd1 ? img1 : hbm1) + o : nullptr;
-          uint8_t* t1 = b < nb1 ? (rd1 ? hbm1 : img1) + o : nullptr;
-          copy2(t0, s0, t1, s1);
-        }
-      }
+      fence_acq_sys();  // no stale copy of the store image (or of a line) survives in L2
+      copy_cmds(c, ready, p_opc, p_nblk, p_status, p_slba, p_prp);
       if ((ready >> lane()) & 1ull) p_copied = true;
       if (lane() == 0) count(c, C_CTRL_CMDS, __popcll(ready));
       progress = true;
