@@ -257,6 +257,63 @@ agile_status agile_embbag_backward_sgd(agile_ctx ctx, agile_store store, const a
                                        const int64_t* d_idx, const int64_t* d_off, uint64_t B,
                                        uint64_t n, const float* d_grad, float lr, void* stream);
 
+/* A CSR graph held in the store: row_ptr int64[V+1] at row_ptr_offset, col int32[E] at
+ * col_offset and, for SpMV, val fp32[E] at val_offset (byte offsets into the store). */
+typedef struct agile_csr {
+  uint64_t num_vertices;
+  uint64_t num_edges;
+  uint64_t row_ptr_offset;
+  uint64_t col_offset;
+  uint64_t val_offset;
+} agile_csr;
+
+/* Level-synchronous top-down BFS over out-edges (the graph application of Sec. 4.5,
+ * without application-level optimisation): d_level (int32[V], device) receives the hop
+ * distance from src, -1 when unreached.  row_ptr and col are read through the cache.
+ * Blocks (one host step per level); *out_levels (may be NULL) receives the number of
+ * levels including the source's. */
+agile_status agile_bfs(agile_ctx ctx, agile_store store, const agile_csr* g, uint64_t src,
+                       int32_t* d_level, uint32_t* out_levels, void* stream);
+
+/* CSR SpMV (Sec. 4.5): d_y[i] = fold over k ascending in row i of
+ * acc = fmaf(val[k], d_x[col[k]], acc), acc from +0.0f.  row_ptr, col and val are read
+ * through the cache; d_x and d_y are device fp32[V].  Stream-ordered. */
+agile_status agile_spmv(agile_ctx ctx, agile_store store, const agile_csr* g, const float* d_x,
+                        float* d_y, void* stream);
+
+/* ---------------------------------------------------------------- serving --------- */
+typedef struct agile_serve_opts {
+  uint64_t max_inflight_lookups;  /* queue budget (0 = the SQ slots, or the largest request) */
+  uint64_t max_inflight_requests; /* 0 = 4096 */
+  uint64_t user_waves;            /* 0 = fill the GPU */
+} agile_serve_opts;
+
+typedef struct agile_serve_report {
+  double elapsed_s;
+  uint64_t requests, bags, lookups;
+  uint64_t max_inflight_requests;
+  uint64_t user_waves;
+} agile_serve_report;
+
+/* Continuous-batching serving session (embedding-bag lookups).  One persistent kernel
+ * serves the whole request stream: its wavefronts claim bags in request order, so the
+ * bags of requests that arrive while others are on the GPU are picked up as waves free
+ * up and their I/O overlaps on the device.  The host publishes request r once
+ * arrival_s[r] (seconds from the start, non-decreasing) has passed and the requests in
+ * flight leave room in the queue budget (lookups in flight, every lookup may miss) and
+ * the cache budget (lines in flight, at most half the cache per request); a request that
+ * does not fit waits, and so do the ones behind it.  Request r owns bags
+ * [req_bag0[r], req_bag0[r+1]); bag b owns lookups [bag_off[b], bag_off[b+1]) of idx and
+ * reads table (b - req_bag0[r]) % num_tables.  Outputs (pooled, K as in
+ * agile_embbag_forward) go to out[b*dim ...]; latency_s[r] is the time from arrival to
+ * the host seeing request r's outputs in host memory.  All arrays are host memory;
+ * blocks for the whole session. */
+agile_status agile_serve(agile_ctx ctx, agile_store store, const agile_tables* tb, uint32_t K,
+                         uint32_t mode, uint64_t nreq, const double* arrival_s,
+                         const int64_t* req_bag0, const int64_t* bag_off, const int64_t* idx,
+                         float* out, double* latency_s, const agile_serve_opts* opts,
+                         agile_serve_report* report);
+
 #ifdef __cplusplus
 }
 #endif

@@ -55,6 +55,27 @@ class Info(C.Structure):
         return {n: int(getattr(self, n)) for n, _ in self._fields_}
 
 
+class CSR(C.Structure):
+    _fields_ = [("num_vertices", C.c_uint64), ("num_edges", C.c_uint64),
+                ("row_ptr_offset", C.c_uint64), ("col_offset", C.c_uint64),
+                ("val_offset", C.c_uint64)]
+
+
+class ServeOpts(C.Structure):
+    _fields_ = [("max_inflight_lookups", C.c_uint64), ("max_inflight_requests", C.c_uint64),
+                ("user_waves", C.c_uint64)]
+
+
+class ServeReport(C.Structure):
+    _fields_ = [("elapsed_s", C.c_double), ("requests", C.c_uint64), ("bags", C.c_uint64),
+                ("lookups", C.c_uint64), ("max_inflight_requests", C.c_uint64),
+                ("user_waves", C.c_uint64)]
+
+    def as_dict(self):
+        return {n: (float(getattr(self, n)) if n == "elapsed_s" else int(getattr(self, n)))
+                for n, _ in self._fields_}
+
+
 class Tables(C.Structure):
     _fields_ = [("rows", C.c_uint64), ("dim", C.c_uint32), ("num_tables", C.c_uint32),
                 ("base_offset", C.c_uint64)]
@@ -102,6 +123,10 @@ def lib():
             "agile_debug_dump": (st, [vp, vp, vp, vp, vp]),
             "agile_debug_counters": (st, [vp, vp, u32]),
             "agile_probe_copy": (st, [vp, vp, u64, vp, u64, u32, u32, vp]),
+            "agile_bfs": (st, [vp, vp, C.POINTER(CSR), u64, vp, C.POINTER(C.c_uint32), vp]),
+            "agile_spmv": (st, [vp, vp, C.POINTER(CSR), vp, vp, vp]),
+            "agile_serve": (st, [vp, vp, C.POINTER(Tables), u32, u32, u64, vp, vp, vp, vp, vp,
+                                 vp, C.POINTER(ServeOpts), C.POINTER(ServeReport)]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -302,6 +327,39 @@ class Context:
                                                     _ptr(off), B, idx.numel(), _ptr(grad), lr,
                                                     _stream(stream)),
                     "agile_embbag_backward_sgd")
+
+    def bfs(self, g: CSR, src: int, level, stream=None, store=None) -> int:
+        store = store or self.store
+        nl = C.c_uint32(0)
+        self._check(lib().agile_bfs(self.h, store.handle, C.byref(g), src, _ptr(level),
+                                    C.byref(nl), _stream(stream)), "agile_bfs")
+        return int(nl.value)
+
+    def spmv(self, g: CSR, x, y, stream=None, store=None):
+        store = store or self.store
+        self._check(lib().agile_spmv(self.h, store.handle, C.byref(g), _ptr(x), _ptr(y),
+                                     _stream(stream)), "agile_spmv")
+
+    def serve(self, tb: Tables, K: int, arrival, req_bag0, bag_off, idx,
+              mode: int = MODE_ASYNC, max_inflight_lookups: int = 0,
+              max_inflight_requests: int = 0, user_waves: int = 0, store=None):
+        """Continuous-batching session; returns (out [nbags, dim], latency_s, report)."""
+        store = store or self.store
+        arrival = np.ascontiguousarray(arrival, dtype=np.float64)
+        req_bag0 = np.ascontiguousarray(req_bag0, dtype=np.int64)
+        bag_off = np.ascontiguousarray(bag_off, dtype=np.int64)
+        idx = np.ascontiguousarray(idx, dtype=np.int64)
+        nreq = arrival.size
+        nbags = int(req_bag0[-1])
+        out = np.empty((nbags, tb.dim), dtype=np.float32)
+        lat = np.zeros(nreq, dtype=np.float64)
+        opts = ServeOpts(max_inflight_lookups, max_inflight_requests, user_waves)
+        rep = ServeReport()
+        self._check(lib().agile_serve(self.h, store.handle, C.byref(tb), K, mode, nreq,
+                                      _ptr(arrival), _ptr(req_bag0), _ptr(bag_off),
+                                      _ptr(idx) if idx.size else 0, _ptr(out), _ptr(lat),
+                                      C.byref(opts), C.byref(rep)), "agile_serve")
+        return out, lat, rep.as_dict()
 
     # ---- diagnostics
     def debug_trace(self, lines, writes, hit, way, stream=None, store=None):

@@ -37,7 +37,22 @@ struct embbag_args {
   uint64_t base_off;    // byte offset of table 0 in the store
   uint64_t table_bytes;
   uint32_t T, dim, row_bytes, K;
-  uint32_t mode, gather, active_waves, _a1;
+  uint32_t mode, gather, active_waves, serve;
+  // continuous batching (serve != 0): bags of many requests, published over time
+  const uint32_t* bag_req;    // request of each bag
+  const uint32_t* bag_tab;    // table of each bag
+  const uint32_t* req_nbags;  // bags per request
+  uint32_t* req_cnt;          // bags finished per request (device, zeroed)
+  const uint32_t* pub_dev;    // device mirror of the number of published requests
+  const uint32_t* pub_host;   // pinned: [0] published requests, [1] stop
+  uint32_t* done;             // pinned: done[r] = 1 once request r's outputs are visible
+};
+
+// Per-wave state of the bag source: a bag grabbed before its request was published is
+// kept for later; after the first failed grab the wave grabs no more.
+struct src_state {
+  int64_t stash;
+  bool exhausted;
 };
 
 __device__ __forceinline__ float fK(float v, uint32_t K) {
@@ -61,31 +76,82 @@ __device__ __forceinline__ int64_t grab(const dev_ctx& c, const launch_t& li) {
 }
 
 template <int VPL>
-__device__ __forceinline__ void write_bag(const embbag_args& a, int64_t g, const float (&acc)[VPL]) {
+__device__ __forceinline__ void write_bag(const dev_ctx& c, const embbag_args& a, int64_t g,
+                                          const float (&acc)[VPL]) {
   const uint32_t d0 = lane() * VPL;
   float* o = a.out + (uint64_t)g * a.dim + d0;
 #pragma unroll
   for (int v = 0; v < VPL; ++v)
     if (d0 + v < a.dim) o[v] = acc[v];
+  if (a.serve) {
+    // the request is done when its last bag is written: push the outputs to host memory
+    // first, then count the bag, then raise the request's flag (system scope)
+    fence_rel_sys();
+    if (lane() == 0) {
+      const uint32_t r = a.bag_req[g];
+      const uint32_t k = add_rlx(a.req_cnt + r, 1u) + 1;
+      if (k == a.req_nbags[r]) {
+        fence_rel_sys();
+        __hip_atomic_store(a.done + r, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+      }
+    }
+  }
+}
+
+// Serving: waits until request r is published (the device mirror holds the count).
+// Returns false when the session is stopped or aborted.  No device deadline: requests
+// may arrive seconds apart; the host watchdog bounds the session.
+__device__ bool wait_published(const dev_ctx& c, const embbag_args& a, uint32_t r) {
+  uint32_t n = 0;
+  while (uni(ld_rlx(a.pub_dev)) <= r) {
+    if ((++n & 63) == 0) {
+      if (aborted(c)) return false;
+      if (uni(__hip_atomic_load(a.pub_host + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM))) return false;
+    }
+    __builtin_amdgcn_s_sleep(32);
+  }
+  fence_acq();
+  return true;
 }
 
 // Next chunk after `d` (or the first one when !d.valid): continues the bag or grabs the
 // next non-empty bag; empty bags get their zero output on the way.
 template <int VPL>
 __device__ desc_t next_desc(const dev_ctx& c, const launch_t& li, const embbag_args& a,
-                            const desc_t& d) {
+                            const desc_t& d, src_state& ss, bool may_wait) {
   desc_t r;
+  r.valid = false;
   if (d.valid && !d.last) {
     r.g = d.g;
     r.j = d.j + d.n;
     r.end = d.end;
   } else {
     for (;;) {
-      const int64_t g = grab(c, li);
+      if (ss.exhausted) return r;
+      int64_t g = ss.stash;
+      if (g < 0) g = grab(c, li);
       if (g >= (int64_t)a.nbags) {
-        r.valid = false;
+        ss.exhausted = true;
+        ss.stash = -1;
         return r;
       }
+      if (a.serve) {
+        const uint32_t rq = a.bag_req[g];
+        if (uni(ld_rlx(a.pub_dev)) <= rq) {
+          if (!may_wait) {
+            ss.stash = g;  // consume what the wave holds first
+            return r;
+          }
+          if (!wait_published(c, a, rq)) {
+            ss.exhausted = true;
+            ss.stash = -1;
+            return r;
+          }
+        } else {
+          fence_acq();
+        }
+      }
+      ss.stash = -1;
       int64_t j0, j1;
       if (a.gather) {
         j0 = g * 64;
@@ -104,7 +170,7 @@ __device__ desc_t next_desc(const dev_ctx& c, const launch_t& li, const embbag_a
         float z[VPL];
 #pragma unroll
         for (int v = 0; v < VPL; ++v) z[v] = 0.0f;
-        write_bag<VPL>(a, g, z);
+        write_bag<VPL>(c, a, g, z);
       }
     }
   }
@@ -125,7 +191,7 @@ __device__ __forceinline__ void make_chunk(const dev_ctx& c, const embbag_args& 
     if (a.gather) {
       byte = a.base_off + (uint64_t)row * a.row_bytes;
     } else {
-      const uint32_t t = (uint32_t)(d.g % a.T);
+      const uint32_t t = a.serve ? a.bag_tab[d.g] : (uint32_t)(d.g % a.T);
       byte = a.base_off + (uint64_t)t * a.table_bytes + (uint64_t)row * a.row_bytes;
     }
     ch.line_id = (uint32_t)(byte >> c.line_shift);
@@ -214,7 +280,8 @@ __device__ void embbag_wave(const dev_ctx& c, const launch_t& li, const embbag_a
   for (int v = 0; v < VPL; ++v) acc[v] = 0.0f;
   desc_t none;
   none.valid = false;
-  desc_t dc = next_desc<VPL>(c, li, a, none);
+  src_state ss{-1, false};
+  desc_t dc = next_desc<VPL>(c, li, a, none, ss, true);
   if (!dc.valid) return;
   chunk_t cc, cn;
   make_chunk(c, a, dc, cc);
@@ -222,8 +289,9 @@ __device__ void embbag_wave(const dev_ctx& c, const launch_t& li, const embbag_a
   while (dc.valid) {
     desc_t dn;
     bool n_issued = false;
+    dn.valid = false;
     if (async) {
-      dn = next_desc<VPL>(c, li, a, dc);
+      dn = next_desc<VPL>(c, li, a, dc, ss, false);
       if (dn.valid) {
         make_chunk(c, a, dn, cn);
         if (!chunk_issue(c, cn, q, true, PIN_NONE)) return;
@@ -267,11 +335,11 @@ __device__ void embbag_wave(const dev_ctx& c, const launch_t& li, const embbag_a
       }
     }
     if (dc.last && !a.gather) {
-      write_bag<VPL>(a, dc.g, acc);
+      write_bag<VPL>(c, a, dc.g, acc);
 #pragma unroll
       for (int v = 0; v < VPL; ++v) acc[v] = 0.0f;
     }
-    if (!async) dn = next_desc<VPL>(c, li, a, dc);
+    if (!async || (!dn.valid && ss.stash >= 0)) dn = next_desc<VPL>(c, li, a, dc, ss, true);
     dc = dn;
     if (!dc.valid) break;
     if (n_issued) {
@@ -317,7 +385,7 @@ __device__ void embbag_serial(const dev_ctx& c, const launch_t& li, const embbag
         if (!sp.step(c, 0xF1000000ull)) return;
       }
     }
-    if (!a.gather) write_bag<VPL>(a, (int64_t)g, acc);
+    if (!a.gather) write_bag<VPL>(c, a, (int64_t)g, acc);
   }
 }
 
@@ -333,6 +401,40 @@ __global__ __launch_bounds__(WG) void k_embbag(dev_ctx c, launch_t li, embbag_ar
   } else if (uw < a.active_waves) {
     embbag_wave<VPL>(c, li, a, uw);
   }
+  user_wave_done(c);
+}
+
+// Serving kernel: the embedding-bag wave loop over a stream of requests.  One extra
+// service wavefront mirrors the host's count of published requests into device memory,
+// so that waiting waves poll HBM instead of sending PCIe reads.
+__device__ void mirror_published(const dev_ctx& c, const embbag_args& a, uint32_t nreq, uint32_t* pub_dev) {
+  uint32_t last = 0;
+  for (;;) {
+    const uint32_t v = uni(__hip_atomic_load(a.pub_host, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM));
+    if (v != last) {
+      last = v;
+      if (lane() == 0) st_rlx(pub_dev, v);
+    }
+    if (last >= nreq || aborted(c)) break;
+    if (uni(__hip_atomic_load(a.pub_host + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM))) break;
+    __builtin_amdgcn_s_sleep(16);
+  }
+}
+
+template <int VPL>
+__global__ __launch_bounds__(WG) void k_serve(dev_ctx c, launch_t li, embbag_args a, uint32_t nreq,
+                                              uint32_t* pub_dev) {
+  if (blockIdx.x < li.service_blocks) {
+    const uint32_t sw = blockIdx.x * WPB + threadIdx.x / 64;
+    if (sw == li.n_ctrl + li.n_cq) {
+      mirror_published(c, a, nreq, pub_dev);
+      return;
+    }
+    run_service(c, li);
+    return;
+  }
+  const uint32_t uw = (blockIdx.x - li.service_blocks) * WPB + threadIdx.x / 64;
+  if (uw < a.active_waves) embbag_wave<VPL>(c, li, a, uw);
   user_wave_done(c);
 }
 
@@ -656,6 +758,250 @@ __global__ __launch_bounds__(WG) void k_bwd_sgd(dev_ctx c, launch_t li, bwd_args
   user_wave_done(c);
 }
 
+// ---- graph workloads over a CSR graph held in the store (row_ptr int64, col int32, val fp32)
+struct csr_t {
+  uint64_t V, E, rp_off, col_off, val_off;
+};
+
+// Reads one aligned 4- or 8-byte word per active lane from the store through the cache,
+// optimistically: lines are not pinned unless this wave's own miss filled them, and the
+// line's tag and generation are re-checked after the load.  Lanes whose line changed, or
+// whose set had no evictable way, retry while holding nothing.
+template <typename T>
+__device__ bool cached_read(const dev_ctx& c, uint32_t q, bool act, uint64_t byte, T& out) {
+  bool todo = act;
+  spin_t sp;
+  while (ballot(todo)) {
+    chunk_t ch;
+    ch.act = todo;
+    if (todo) {
+      ch.line_id = (uint32_t)(byte >> c.line_shift);
+      ch.off = (uint32_t)(byte & ((1ull << c.line_shift) - 1));
+    }
+    if (!chunk_issue(c, ch, q, true, PIN_NONE)) return false;
+    if (!chunk_wait(c, ch, false)) return false;
+    const bool got = todo && st_ok(ch.st);
+    T v = 0;
+    if (got) v = ld_rlx(reinterpret_cast<const T*>(line_ptr(c, ch.idx) + ch.off));
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");  // the load has completed
+    bool ok = false;
+    if (got) ok = ch.pinned || line_still_valid(c, ch.idx, ch.line_id, ch.gen);
+    if (ok) out = v;
+    chunk_release(c, ch, false);
+    if (ok) todo = false;
+    if (ballot(todo) && !ballot(ok)) {
+      if (!sp.step(c, 0xF4000000ull)) return false;
+    }
+  }
+  return true;
+}
+
+struct bfs_args {
+  csr_t g;
+  const int32_t* F;   // frontier
+  uint32_t nF;
+  uint64_t* cs;       // compacted: first edge of each frontier vertex with edges
+  uint64_t* cd;       // compacted: its out-degree
+  uint64_t* co;       // exclusive prefix sums of cd
+  uint32_t* ctr;      // [0] compacted count, [1] next-frontier count, [2] work counter
+  int32_t* N;         // next frontier
+  int32_t* level;
+  int32_t L;          // current level
+  uint32_t nC;
+  uint64_t Et;        // edges out of the frontier
+};
+
+// Level step 1: each frontier vertex reads its row_ptr pair through the cache; vertices
+// with edges are compacted (order is irrelevant: levels do not depend on it).
+__global__ __launch_bounds__(WG) void k_bfs_front(dev_ctx c, launch_t li, bfs_args a) {
+  if (blockIdx.x < li.service_blocks) {
+    run_service(c, li);
+    return;
+  }
+  const uint32_t uw = (blockIdx.x - li.service_blocks) * WPB + threadIdx.x / 64;
+  const uint32_t q = uw % c.num_qp;
+  for (uint64_t base = (uint64_t)uw * 64; base < a.nF; base += (uint64_t)li.user_waves * 64) {
+    const bool act = base + lane() < a.nF;
+    const uint64_t v = act ? (uint64_t)a.F[base + lane()] : 0;
+    const uint64_t b0 = a.g.rp_off + 8 * v;
+    int64_t s0 = 0, s1 = 0;
+    if (!cached_read<int64_t>(c, q, act, b0, s0)) break;
+    if (!cached_read<int64_t>(c, q, act, b0 + 8, s1)) break;
+    const bool has = act && s1 > s0;
+    const uint64_t hm = ballot(has);
+    uint32_t pos = 0;
+    if (lane() == 0 && hm) pos = atomicAdd(a.ctr, (uint32_t)__popcll(hm));
+    pos = rdlane(pos, 0) + mbcnt(hm);
+    if (has) {
+      a.cs[pos] = (uint64_t)s0;
+      a.cd[pos] = (uint64_t)(s1 - s0);
+    }
+  }
+  user_wave_done(c);
+}
+
+// Level step 2: the frontier's edges, flattened by the prefix sums, are split into chunks
+// of 1024 so that a hub vertex is spread over many waves.  Each lane reads one col entry
+// through the cache and claims unvisited vertices with a CAS on level[].
+__global__ __launch_bounds__(WG) void k_bfs_edges(dev_ctx c, launch_t li, bfs_args a) {
+  if (blockIdx.x < li.service_blocks) {
+    run_service(c, li);
+    return;
+  }
+  const uint32_t uw = (blockIdx.x - li.service_blocks) * WPB + threadIdx.x / 64;
+  const uint32_t q = uw % c.num_qp;
+  for (;;) {
+    uint32_t g = 0;
+    if (lane() == 0) g = atomicAdd(a.ctr + 2, 1u);
+    g = rdlane(g, 0);
+    const uint64_t e0 = (uint64_t)g * 1024;
+    if (e0 >= a.Et) break;
+    const uint64_t e1 = (e0 + 1024 < a.Et) ? e0 + 1024 : a.Et;
+    // vertex holding edge e0: 64-ary search over co (wave parallel)
+    uint64_t lo = 0, hi = a.nC;  // invariant: co[lo] <= e0 < co[hi] (co[nC] = Et)
+    while (hi - lo > 1) {
+      const uint64_t step = (hi - lo + 63) / 64;
+      const uint64_t p = lo + (uint64_t)lane() * step;
+      const bool le = p < hi && a.co[p] <= e0;
+      const uint64_t m = ballot(le);
+      const uint32_t k = 63 - __builtin_clzll(m);  // last lane with co[p] <= e0
+      const uint64_t nlo = lo + (uint64_t)k * step;
+      const uint64_t nhi = (nlo + step < hi) ? nlo + step : hi;
+      lo = nlo;
+      hi = nhi;
+    }
+    uint64_t i = lo;
+    for (uint64_t e = e0; e < e1; e += 64) {
+      const uint64_t my = e + lane();
+      const bool act = my < e1;
+      // window of 64 vertices from i: every compacted vertex has >= 1 edge, so it covers
+      const uint64_t wi = i + lane();
+      const uint64_t wco = wi < a.nC ? a.co[wi] : ~0ull;
+      uint32_t k = 0;
+#pragma unroll
+      for (uint32_t st = 32; st; st >>= 1) {
+        const uint64_t cand = (uint64_t)shfl32((uint32_t)(wco >> 32), k + st) << 32 |
+                              shfl32((uint32_t)wco, k + st);
+        if (k + st < 64 && cand <= my) k += st;
+      }
+      const uint64_t vo = (uint64_t)shfl32((uint32_t)(wco >> 32), k) << 32 | shfl32((uint32_t)wco, k);
+      const uint64_t vs = act ? a.cs[i + k] : 0;
+      const uint64_t pos = vs + (my - vo);
+      int32_t u = 0;
+      if (!cached_read<int32_t>(c, q, act, a.g.col_off + 4 * pos, u)) goto done;
+      bool added = false;
+      if (act && (uint64_t)u < a.g.V) {
+        if (__hip_atomic_load(a.level + u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == -1) {
+          int32_t expect = -1;
+          added = __hip_atomic_compare_exchange_strong(a.level + u, &expect, a.L + 1, __ATOMIC_RELAXED,
+                                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+      }
+      const uint64_t am = ballot(added);
+      uint32_t pos2 = 0;
+      if (lane() == 0 && am) pos2 = atomicAdd(a.ctr + 1, (uint32_t)__popcll(am));
+      pos2 = rdlane(pos2, 0) + mbcnt(am);
+      if (added) a.N[pos2] = u;
+      // keep i = the vertex of the next step's first edge (e + 64)
+      const uint32_t kl = rdlane(k, 63);
+      uint64_t nxt = ~0ull;
+      if (lane() == 0 && i + kl + 1 < a.nC) nxt = a.co[i + kl + 1];
+      nxt = rdlane64(nxt, 0);
+      i += kl + (nxt == e + 64 ? 1u : 0u);
+    }
+  }
+done:
+  user_wave_done(c);
+}
+
+// SpMV: a wave takes 64 consecutive rows, one per lane, and folds each row in CSR order,
+// acc = fmaf(val[k], x[col[k]], acc) from +0.0f (the same order as the plain definition).
+// The rows' edges are walked in windows of 2048: the window's col and val lines are pinned
+// for the window and their indices kept in LDS, so lanes with long rows walk them freely.
+struct spmv_args {
+  csr_t g;
+  const float* x;
+  float* y;
+  uint32_t* ctr;  // [0] work counter
+};
+
+__global__ __launch_bounds__(WG) void k_spmv(dev_ctx c, launch_t li, spmv_args a) {
+  __shared__ uint32_t win[WPB][16];
+  if (blockIdx.x < li.service_blocks) {
+    run_service(c, li);
+    return;
+  }
+  const uint32_t wv = threadIdx.x / 64;
+  const uint32_t uw = (blockIdx.x - li.service_blocks) * WPB + wv;
+  const uint32_t q = uw % c.num_qp;
+  const uint32_t lmask = (1u << c.line_shift) - 1;
+  for (;;) {
+    uint32_t g = 0;
+    if (lane() == 0) g = atomicAdd(a.ctr, 1u);
+    g = rdlane(g, 0);
+    const uint64_t r0 = (uint64_t)g * 64;
+    if (r0 >= a.g.V) break;
+    const uint32_t nr = (uint32_t)((a.g.V - r0) < 64 ? (a.g.V - r0) : 64);
+    const bool act = lane() < nr;
+    int64_t rs = 0, rend = 0;
+    if (!cached_read<int64_t>(c, q, act, a.g.rp_off + 8 * (r0 + lane()), rs)) goto done;
+    if (!cached_read<int64_t>(c, q, lane() == 0, a.g.rp_off + 8 * (r0 + nr), rend)) goto done;
+    rend = (int64_t)rdlane64((uint64_t)rend, 0);
+    int64_t re = (int64_t)shfl64((uint64_t)rs, (lane() + 1) & 63);
+    if (lane() == nr - 1) re = rend;
+    float acc = 0.0f;
+    const uint64_t E0 = rdlane64((uint64_t)rs, 0), E1 = (uint64_t)rend;
+    for (uint64_t w0 = E0; w0 < E1; w0 += 2048) {
+      const uint64_t w1 = (w0 + 2048 < E1) ? w0 + 2048 : E1;
+      const uint64_t cb0 = a.g.col_off + 4 * w0, cb1 = a.g.col_off + 4 * w1 - 1;
+      const uint64_t vb0 = a.g.val_off + 4 * w0, vb1 = a.g.val_off + 4 * w1 - 1;
+      const uint32_t lc0 = (uint32_t)(cb0 >> c.line_shift), nc = (uint32_t)(cb1 >> c.line_shift) - lc0 + 1;
+      const uint32_t lv0 = (uint32_t)(vb0 >> c.line_shift), nv = (uint32_t)(vb1 >> c.line_shift) - lv0 + 1;
+      // pin the window's lines (col lines in lanes [0, nc), val lines in [8, 8 + nv))
+      bool todo = lane() < nc || (lane() >= 8 && lane() < 8 + nv);
+      const uint32_t want = lane() < 8 ? lc0 + lane() : lv0 + (lane() - 8);
+      chunk_t ch;
+      spin_t sp;
+      bool held = false;
+      for (;;) {
+        ch.act = todo;
+        ch.line_id = want;
+        ch.off = 0;
+        if (!chunk_issue(c, ch, q, true, PIN_LINE)) goto done;
+        if (ballot(ch.act && ch.st == A_EAGAIN)) {
+          chunk_release(c, ch, false);
+          if (!sp.step(c, 0xF5000000ull)) goto done;
+          continue;
+        }
+        if (!chunk_wait(c, ch, true)) goto done;
+        held = true;
+        break;
+      }
+      if (todo) win[wv][lane() < 8 ? lane() : 8 + (lane() - 8)] = ch.idx;
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+      __builtin_amdgcn_wave_barrier();
+      if (act) {
+        const uint64_t k0 = (uint64_t)rs > w0 ? (uint64_t)rs : w0;
+        const uint64_t k1 = (uint64_t)re < w1 ? (uint64_t)re : w1;
+        for (uint64_t k = k0; k < k1; ++k) {
+          const uint64_t cb = a.g.col_off + 4 * k, vb = a.g.val_off + 4 * k;
+          const uint32_t ci = win[wv][(uint32_t)(cb >> c.line_shift) - lc0];
+          const uint32_t vi = win[wv][8 + (uint32_t)(vb >> c.line_shift) - lv0];
+          const int32_t col = *reinterpret_cast<const int32_t*>(line_ptr(c, ci) + (cb & lmask));
+          const float val = *reinterpret_cast<const float*>(line_ptr(c, vi) + (vb & lmask));
+          const float xv = ((uint64_t)col < a.g.V) ? a.x[col] : 0.0f;
+          acc = __builtin_fmaf(val, xv, acc);
+        }
+      }
+      __builtin_amdgcn_wave_barrier();
+      if (held) chunk_release(c, ch, false);
+    }
+    if (act) a.y[r0 + lane()] = acc;
+  }
+done:
+  user_wave_done(c);
+}
+
 // Roofline probe: waves copy 4 KiB blocks from `src` (pinned host or HBM) to `dst`
 // (HBM), `per` blocks in flight per wave, with the same wave-cooperative copy the emulated
 // controller uses.  Block i is src block `list[i]` (or i when list is NULL) and lands in
@@ -721,7 +1067,8 @@ struct agile_ctx_s {
 namespace {
 
 constexpr int KIND_EMBBAG1 = 0, KIND_EMBBAG2 = 1, KIND_EMBBAG4 = 2, KIND_READ = 3, KIND_FLUSH = 4,
-              KIND_TRACE = 5, KIND_BWD1 = 6, KIND_BWD2 = 7, KIND_BWD4 = 8, KIND_N = 9;
+              KIND_TRACE = 5, KIND_BWD1 = 6, KIND_BWD2 = 7, KIND_BWD4 = 8, KIND_SERVE1 = 9,
+              KIND_SERVE2 = 10, KIND_SERVE4 = 11, KIND_N = 12;
 
 agile_status fail(agile_ctx ctx, agile_status s, const std::string& msg) {
   if (ctx) ctx->last_error = msg;
@@ -769,6 +1116,9 @@ int occupancy(agile_ctx ctx, int kind) {
     case KIND_BWD1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_bwd_sgd<1>, WG, 0); break;
     case KIND_BWD2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_bwd_sgd<2>, WG, 0); break;
     case KIND_BWD4: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_bwd_sgd<4>, WG, 0); break;
+    case KIND_SERVE1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_serve<1>, WG, 0); break;
+    case KIND_SERVE2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_serve<2>, WG, 0); break;
+    case KIND_SERVE4: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_serve<4>, WG, 0); break;
     default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_trace, WG, 0); break;
   }
   if (e != hipSuccess || nb <= 0) nb = 1;
@@ -1286,6 +1636,141 @@ agile_status agile_embbag_forward(agile_ctx ctx, agile_store store, const agile_
   return embbag_launch(ctx, store, tb, d_idx, d_off, B, 0, K, mode, d_out, stream, false);
 }
 
+static agile_status ensure_scratch(agile_ctx ctx, size_t need, hipStream_t hs) {
+  if (need <= ctx->scratch_bytes) return AGILE_OK;
+  HIPCHK(ctx, hipStreamSynchronize(hs));
+  if (ctx->scratch) HIPCHK(ctx, hipFree(ctx->scratch));
+  ctx->scratch = nullptr;
+  ctx->scratch_bytes = 0;
+  if (hipMalloc(&ctx->scratch, need) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(ctx, AGILE_ENOMEM, "scratch allocation failed");
+  }
+  ctx->scratch_bytes = need;
+  return AGILE_OK;
+}
+
+static agile_status check_csr(agile_ctx ctx, agile_store store, const agile_csr* g, bool need_val) {
+  if (!g) return fail(ctx, AGILE_EINVAL, "graph: null csr");
+  if (g->num_vertices == 0 || g->num_vertices >= (1ull << 31))
+    return fail(ctx, AGILE_EINVAL, "graph: vertex count must be 1..2^31-1");
+  if (g->row_ptr_offset % 8 || g->col_offset % 4 || g->val_offset % 4)
+    return fail(ctx, AGILE_EINVAL, "graph: misaligned arrays");
+  if (g->row_ptr_offset + 8 * (g->num_vertices + 1) > store->bytes || g->col_offset + 4 * g->num_edges > store->bytes ||
+      (need_val && g->val_offset + 4 * g->num_edges > store->bytes))
+    return fail(ctx, AGILE_EINVAL, "graph: arrays exceed the store");
+  return AGILE_OK;
+}
+
+static csr_t to_csr(const agile_csr* g) {
+  csr_t c;
+  c.V = g->num_vertices;
+  c.E = g->num_edges;
+  c.rp_off = g->row_ptr_offset;
+  c.col_off = g->col_offset;
+  c.val_off = g->val_offset;
+  return c;
+}
+
+__global__ void k_bfs_init(int32_t* level, uint64_t V, uint64_t src, int32_t* F) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < V) level[i] = (i == src) ? 0 : -1;
+  if (i == 0) F[0] = (int32_t)src;
+}
+
+agile_status agile_bfs(agile_ctx ctx, agile_store store, const agile_csr* g, uint64_t src, int32_t* d_level,
+                       uint32_t* out_levels, void* stream) {
+  agile_status s = check_usable(ctx);
+  if (s) return s;
+  if (store != ctx->store) return fail(ctx, AGILE_EINVAL, "bfs: store is not open on this context");
+  if ((s = check_csr(ctx, store, g, false)) != AGILE_OK) return s;
+  if (!d_level || src >= g->num_vertices) return fail(ctx, AGILE_EINVAL, "bfs: bad level array or source");
+  hipStream_t hs = (hipStream_t)stream;
+  const uint64_t V = g->num_vertices;
+  size_t scan_bytes = 0;
+  HIPCHK(ctx, hipcub::DeviceScan::ExclusiveSum(nullptr, scan_bytes, (uint64_t*)nullptr, (uint64_t*)nullptr,
+                                               (int)V, hs));
+  auto al = [](size_t v) { return (v + 255) & ~(size_t)255; };
+  const size_t oF = 0, oN = oF + al(4 * V), ocs = oN + al(4 * V), ocd = ocs + al(8 * V), oco = ocd + al(8 * V),
+               octr = oco + al(8 * (V + 1)), osc = octr + 256, need = osc + al(scan_bytes);
+  if ((s = ensure_scratch(ctx, need, hs)) != AGILE_OK) return s;
+  uint8_t* sb = (uint8_t*)ctx->scratch;
+  bfs_args a{};
+  a.g = to_csr(g);
+  a.cs = (uint64_t*)(sb + ocs);
+  a.cd = (uint64_t*)(sb + ocd);
+  a.co = (uint64_t*)(sb + oco);
+  a.ctr = (uint32_t*)(sb + octr);
+  a.level = d_level;
+  int32_t* F = (int32_t*)(sb + oF);
+  int32_t* N = (int32_t*)(sb + oN);
+  hipLaunchKernelGGL(k_bfs_init, dim3((uint32_t)((V + 255) / 256)), dim3(256), 0, hs, d_level, V, src, F);
+  HIPCHK(ctx, hipGetLastError());
+  uint32_t nF = 1;
+  int32_t L = 0;
+  const uint64_t by_cache = std::max<uint64_t>(1, ctx->d.num_lines / 128);
+  while (nF > 0) {
+    a.F = F;
+    a.N = N;
+    a.nF = nF;
+    a.L = L;
+    HIPCHK(ctx, hipMemsetAsync(a.ctr, 0, 256, hs));
+    uint32_t uw = (uint32_t)std::min<uint64_t>({(nF + 63) / 64, (uint64_t)user_wave_cap(ctx, KIND_READ), by_cache});
+    uw = (uw + WPB - 1) / WPB * WPB;
+    launch_t li = make_launch(ctx, uw, true, 0);
+    hipLaunchKernelGGL(k_bfs_front, dim3(li.service_blocks + uw / WPB), dim3(WG), 0, hs, ctx->d, li, a);
+    HIPCHK(ctx, hipGetLastError());
+    uint32_t nC = 0;
+    HIPCHK(ctx, hipMemcpyAsync(&nC, a.ctr, 4, hipMemcpyDeviceToHost, hs));
+    if ((s = sync_stream(ctx, hs)) != AGILE_OK) return s;
+    if (nC == 0) break;
+    HIPCHK(ctx, hipcub::DeviceScan::ExclusiveSum(sb + osc, scan_bytes, a.cd, a.co, (int)nC, hs));
+    uint64_t last[2] = {0, 0};
+    HIPCHK(ctx, hipMemcpyAsync(&last[0], a.co + nC - 1, 8, hipMemcpyDeviceToHost, hs));
+    HIPCHK(ctx, hipMemcpyAsync(&last[1], a.cd + nC - 1, 8, hipMemcpyDeviceToHost, hs));
+    HIPCHK(ctx, hipStreamSynchronize(hs));
+    a.nC = nC;
+    a.Et = last[0] + last[1];
+    uw = (uint32_t)std::min<uint64_t>({(a.Et + 1023) / 1024, (uint64_t)user_wave_cap(ctx, KIND_READ), by_cache});
+    uw = (uw + WPB - 1) / WPB * WPB;
+    li = make_launch(ctx, uw, true, 0);
+    hipLaunchKernelGGL(k_bfs_edges, dim3(li.service_blocks + uw / WPB), dim3(WG), 0, hs, ctx->d, li, a);
+    HIPCHK(ctx, hipGetLastError());
+    HIPCHK(ctx, hipMemcpyAsync(&nF, a.ctr + 1, 4, hipMemcpyDeviceToHost, hs));
+    if ((s = sync_stream(ctx, hs)) != AGILE_OK) return s;
+    std::swap(F, N);
+    ++L;
+  }
+  if (out_levels) *out_levels = (uint32_t)(L + 1);
+  return AGILE_OK;
+}
+
+agile_status agile_spmv(agile_ctx ctx, agile_store store, const agile_csr* g, const float* d_x, float* d_y,
+                        void* stream) {
+  agile_status s = check_usable(ctx);
+  if (s) return s;
+  if (store != ctx->store) return fail(ctx, AGILE_EINVAL, "spmv: store is not open on this context");
+  if ((s = check_csr(ctx, store, g, true)) != AGILE_OK) return s;
+  if (!d_x || !d_y) return fail(ctx, AGILE_EINVAL, "spmv: null vector");
+  if (ctx->cfg.line_bytes < 4096) return fail(ctx, AGILE_EINVAL, "spmv: line too small");
+  hipStream_t hs = (hipStream_t)stream;
+  if ((s = ensure_scratch(ctx, 256, hs)) != AGILE_OK) return s;
+  spmv_args a{};
+  a.g = to_csr(g);
+  a.x = d_x;
+  a.y = d_y;
+  a.ctr = (uint32_t*)ctx->scratch;
+  HIPCHK(ctx, hipMemsetAsync(a.ctr, 0, 4, hs));
+  const uint64_t by_cache = std::max<uint64_t>(1, ctx->d.num_lines / 32);
+  uint32_t uw = (uint32_t)std::min<uint64_t>({(g->num_vertices + 63) / 64, (uint64_t)user_wave_cap(ctx, KIND_READ),
+                                              by_cache});
+  uw = (uw + WPB - 1) / WPB * WPB;
+  launch_t li = make_launch(ctx, uw, true, 0);
+  hipLaunchKernelGGL(k_spmv, dim3(li.service_blocks + uw / WPB), dim3(WG), 0, hs, ctx->d, li, a);
+  HIPCHK(ctx, hipGetLastError());
+  return AGILE_OK;
+}
+
 agile_status agile_embbag_backward_sgd(agile_ctx ctx, agile_store store, const agile_tables* tb,
                                        const int64_t* d_idx, const int64_t* d_off, uint64_t B, uint64_t n,
                                        const float* d_grad, float lr, void* stream) {
@@ -1377,6 +1862,189 @@ agile_status agile_probe_copy(const void* src, const uint64_t* d_list, uint64_t 
   hipLaunchKernelGGL(k_probe_copy, dim3(blocks), dim3(WG), 0, (hipStream_t)stream, s, d_list, n, (uint8_t*)d_dst,
                      dst_blocks, per_wave);
   return hipGetLastError() == hipSuccess ? AGILE_OK : AGILE_EHIP;
+}
+
+agile_status agile_serve(agile_ctx ctx, agile_store store, const agile_tables* tb, uint32_t K, uint32_t mode,
+                         uint64_t nreq, const double* arrival_s, const int64_t* req_bag0, const int64_t* bag_off,
+                         const int64_t* idx, float* out, double* latency_s, const agile_serve_opts* opts,
+                         agile_serve_report* report) {
+  agile_status s = check_usable(ctx);
+  if (s) return s;
+  if (store != ctx->store) return fail(ctx, AGILE_EINVAL, "serve: store is not open on this context");
+  if (!tb || !arrival_s || !req_bag0 || !bag_off || !out || !latency_s)
+    return fail(ctx, AGILE_EINVAL, "serve: null pointer");
+  if (nreq == 0) return AGILE_OK;
+  if (tb->dim == 0 || tb->dim > 256 || 4096 % (tb->dim * 4) || tb->num_tables == 0 || tb->rows == 0)
+    return fail(ctx, AGILE_EINVAL, "serve: bad tables");
+  const uint64_t row_bytes = (uint64_t)tb->dim * 4, table_bytes = tb->rows * row_bytes;
+  if (tb->base_offset % row_bytes || tb->base_offset + table_bytes * tb->num_tables > store->bytes)
+    return fail(ctx, AGILE_EINVAL, "serve: tables exceed the store");
+  const uint64_t nbags = (uint64_t)req_bag0[nreq];
+  const uint64_t nlook = (uint64_t)bag_off[nbags];
+  if (nbags == 0 || nbags >= (1ull << 32) || nreq >= (1ull << 32)) return fail(ctx, AGILE_EINVAL, "serve: sizes");
+  for (uint64_t r = 0; r < nreq; ++r)
+    if (req_bag0[r + 1] <= req_bag0[r] || (r && arrival_s[r] < arrival_s[r - 1]))
+      return fail(ctx, AGILE_EINVAL, "serve: every request needs >= 1 bag; arrivals must not decrease");
+  // ---- per-bag and per-request tables in HBM (copied before the session starts)
+  std::vector<uint32_t> bag_req(nbags), bag_tab(nbags), req_nb(nreq);
+  uint64_t max_req_look = 0;
+  for (uint64_t r = 0; r < nreq; ++r) {
+    req_nb[r] = (uint32_t)(req_bag0[r + 1] - req_bag0[r]);
+    for (int64_t b = req_bag0[r]; b < req_bag0[r + 1]; ++b) {
+      bag_req[b] = (uint32_t)r;
+      bag_tab[b] = (uint32_t)((b - req_bag0[r]) % tb->num_tables);
+    }
+    max_req_look = std::max<uint64_t>(max_req_look, (uint64_t)(bag_off[req_bag0[r + 1]] - bag_off[req_bag0[r]]));
+  }
+  auto al = [](size_t v) { return (v + 255) & ~(size_t)255; };
+  const size_t o_idx = 0, o_off = o_idx + al(8 * std::max<uint64_t>(nlook, 1)), o_breq = o_off + al(8 * (nbags + 1)),
+               o_btab = o_breq + al(4 * nbags), o_rnb = o_btab + al(4 * nbags), o_rcnt = o_rnb + al(4 * nreq),
+               o_pub = o_rcnt + al(4 * nreq), need = o_pub + 256;
+  hipStream_t hs = nullptr;
+  HIPCHK(ctx, hipStreamCreateWithFlags(&hs, hipStreamNonBlocking));
+  struct stream_guard {
+    hipStream_t h;
+    ~stream_guard() { (void)hipStreamDestroy(h); }
+  } sg{hs};
+  if ((s = ensure_scratch(ctx, need, hs)) != AGILE_OK) return s;
+  uint8_t* sb = (uint8_t*)ctx->scratch;
+  if (nlook) HIPCHK(ctx, hipMemcpy(sb + o_idx, idx, 8 * nlook, hipMemcpyHostToDevice));
+  HIPCHK(ctx, hipMemcpy(sb + o_off, bag_off, 8 * (nbags + 1), hipMemcpyHostToDevice));
+  HIPCHK(ctx, hipMemcpy(sb + o_breq, bag_req.data(), 4 * nbags, hipMemcpyHostToDevice));
+  HIPCHK(ctx, hipMemcpy(sb + o_btab, bag_tab.data(), 4 * nbags, hipMemcpyHostToDevice));
+  HIPCHK(ctx, hipMemcpy(sb + o_rnb, req_nb.data(), 4 * nreq, hipMemcpyHostToDevice));
+  HIPCHK(ctx, hipMemset(sb + o_rcnt, 0, 4 * nreq));
+  HIPCHK(ctx, hipMemset(sb + o_pub, 0, 256));
+  // ---- pinned, coherent host memory: publication count + stop, done flags, outputs
+  void* hp = nullptr;
+  const size_t hbytes = al(8) + al(4 * nreq) + al(4 * nbags * tb->dim);
+  if (hipHostMalloc(&hp, hbytes, hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(ctx, AGILE_ENOMEM, "serve: pinned allocation failed");
+  }
+  struct host_guard {
+    void* p;
+    ~host_guard() { (void)hipHostFree(p); }
+  } hg{hp};
+  memset(hp, 0, hbytes);
+  volatile uint32_t* pub = (volatile uint32_t*)hp;
+  volatile uint32_t* done = (volatile uint32_t*)((uint8_t*)hp + al(8));
+  float* hout = (float*)((uint8_t*)hp + al(8) + al(4 * nreq));
+  void *d_pub = nullptr, *d_done = nullptr, *d_out = nullptr;
+  HIPCHK(ctx, hipHostGetDevicePointer(&d_pub, (void*)pub, 0));
+  HIPCHK(ctx, hipHostGetDevicePointer(&d_done, (void*)done, 0));
+  HIPCHK(ctx, hipHostGetDevicePointer(&d_out, (void*)hout, 0));
+  // ---- kernel
+  embbag_args a{};
+  a.idx = (const int64_t*)(sb + o_idx);
+  a.off = (const int64_t*)(sb + o_off);
+  a.out = (float*)d_out;
+  a.nbags = nbags;
+  a.n = nlook;
+  a.rows = tb->rows;
+  a.base_off = tb->base_offset;
+  a.table_bytes = table_bytes;
+  a.T = tb->num_tables;
+  a.dim = tb->dim;
+  a.row_bytes = (uint32_t)row_bytes;
+  a.K = K;
+  a.mode = mode;
+  a.gather = 0;
+  a.serve = 1;
+  a.bag_req = (const uint32_t*)(sb + o_breq);
+  a.bag_tab = (const uint32_t*)(sb + o_btab);
+  a.req_nbags = (const uint32_t*)(sb + o_rnb);
+  a.req_cnt = (uint32_t*)(sb + o_rcnt);
+  a.pub_dev = (const uint32_t*)(sb + o_pub);
+  a.pub_host = (const uint32_t*)d_pub;
+  a.done = (uint32_t*)d_done;
+  const int kind = tb->dim <= 64 ? KIND_SERVE1 : (tb->dim <= 128 ? KIND_SERVE2 : KIND_SERVE4);
+  const uint64_t by_cache = std::max<uint64_t>(1, ctx->d.num_lines / 16);
+  uint64_t want = opts && opts->user_waves ? opts->user_waves : user_wave_cap(ctx, kind);
+  const uint32_t active = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>({want, (uint64_t)user_wave_cap(ctx, kind), by_cache}));
+  const uint32_t uw = (active + WPB - 1) / WPB * WPB;
+  a.active_waves = active;
+  launch_t li = make_launch(ctx, uw, true, nbags + active);
+  li.service_blocks = (ctx->n_ctrl + ctx->n_cq + 1 + WPB - 1) / WPB;  // + the publication mirror
+  const dim3 grid(li.service_blocks + uw / WPB);
+  if (kind == KIND_SERVE1)
+    hipLaunchKernelGGL(k_serve<1>, grid, dim3(WG), 0, hs, ctx->d, li, a, (uint32_t)nreq, (uint32_t*)(sb + o_pub));
+  else if (kind == KIND_SERVE2)
+    hipLaunchKernelGGL(k_serve<2>, grid, dim3(WG), 0, hs, ctx->d, li, a, (uint32_t)nreq, (uint32_t*)(sb + o_pub));
+  else
+    hipLaunchKernelGGL(k_serve<4>, grid, dim3(WG), 0, hs, ctx->d, li, a, (uint32_t)nreq, (uint32_t*)(sb + o_pub));
+  HIPCHK(ctx, hipGetLastError());
+  // ---- host loop: publish arrivals in real time, admit by queue and cache budget, and
+  //      record when each request's outputs become visible
+  const uint64_t sq_slots = (uint64_t)ctx->d.num_qp * ctx->d.depth;
+  const uint64_t cap_look = opts && opts->max_inflight_lookups ? opts->max_inflight_lookups
+                                                               : std::max<uint64_t>(sq_slots, max_req_look);
+  const uint64_t cap_lines = std::max<uint64_t>(1, ctx->d.num_lines);
+  const uint64_t cap_req = opts && opts->max_inflight_requests ? opts->max_inflight_requests : 4096;
+  std::vector<uint64_t> inflight;
+  std::vector<double> t_pub(nreq, 0.0);
+  uint64_t next = 0, completed = 0, in_look = 0, in_lines = 0, max_in = 0;
+  auto look_of = [&](uint64_t r) { return (uint64_t)(bag_off[req_bag0[r + 1]] - bag_off[req_bag0[r]]); };
+  auto lines_of = [&](uint64_t r) { return std::min<uint64_t>(look_of(r), cap_lines / 2); };
+  const auto t0 = std::chrono::steady_clock::now();
+  auto since = [&]() { return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count(); };
+  double last_progress = 0.0;
+  const double limit_s = 4.0 * (double)ctx->cfg.timeout_ns * 1e-9 + 30.0;
+  agile_status st_loop = AGILE_OK;
+  while (completed < nreq) {
+    const double now = since();
+    bool moved = false;
+    while (next < nreq && arrival_s[next] <= now) {
+      const uint64_t L = look_of(next), Ln = lines_of(next);
+      const bool empty = inflight.empty();
+      if (!empty && (in_look + L > cap_look || in_lines + Ln > cap_lines || inflight.size() >= cap_req)) break;
+      in_look += L;
+      in_lines += Ln;
+      inflight.push_back(next);
+      max_in = std::max<uint64_t>(max_in, inflight.size());
+      t_pub[next] = now;
+      ++next;
+      __atomic_store_n((uint32_t*)&pub[0], (uint32_t)next, __ATOMIC_RELEASE);
+      moved = true;
+    }
+    for (size_t i = 0; i < inflight.size();) {
+      const uint64_t r = inflight[i];
+      if (__atomic_load_n((uint32_t*)&done[r], __ATOMIC_ACQUIRE)) {
+        const double tn = since();
+        latency_s[r] = tn - arrival_s[r];
+        in_look -= look_of(r);
+        in_lines -= lines_of(r);
+        inflight[i] = inflight.back();
+        inflight.pop_back();
+        ++completed;
+        moved = true;
+      } else {
+        ++i;
+      }
+    }
+    if (moved) {
+      last_progress = now;
+    } else if (now - last_progress > limit_s || *ctx->abort_host) {
+      __atomic_store_n((uint32_t*)&pub[1], 1u, __ATOMIC_RELEASE);
+      __atomic_store_n(ctx->abort_host, 1u, __ATOMIC_SEQ_CST);
+      st_loop = fail(ctx, AGILE_ETIMEDOUT, "serve: no progress");
+      break;
+    }
+  }
+  const double elapsed = since();
+  s = sync_stream(ctx, hs);
+  if (st_loop != AGILE_OK) return st_loop;
+  if (s != AGILE_OK) return s;
+  memcpy(out, hout, 4 * nbags * tb->dim);
+  if (report) {
+    report->elapsed_s = elapsed;
+    report->requests = nreq;
+    report->bags = nbags;
+    report->lookups = nlook;
+    report->max_inflight_requests = max_in;
+    report->user_waves = active;
+  }
+  return AGILE_OK;
 }
 
 // ---- diagnostics used by tests (declared in agile.h)

@@ -162,3 +162,60 @@ def requests(seed: int, count: int, rate: float, max_log2: int = 12):
 
 def num_threads() -> int:
     return int(lib().gen_num_threads())
+
+
+def rmat_layout(scale: int, edge_factor: int, a: float, b: float, c: float, seed: int):
+    """Pass 1 of the RMAT generator and the store layout of the CSR arrays:
+    [row_ptr int64 (V+1)] [pad to 4 KiB] [col int32 E] [pad] [val fp32 E] [pad].
+    Returns (row_ptr numpy int64, dict of byte offsets and total size)."""
+    deg = rmat_degrees(scale, edge_factor, a, b, c, seed)
+    V = 1 << scale
+    row_ptr = np.zeros(V + 1, dtype=np.int64)
+    np.cumsum(deg, out=row_ptr[1:])
+    del deg
+    E = int(row_ptr[-1])
+    up = lambda v: (v + 4095) // 4096 * 4096  # noqa: E731
+    rp_off = 0
+    col_off = up(8 * (V + 1))
+    val_off = up(col_off + 4 * E)
+    total = up(val_off + 4 * E)
+    return row_ptr, dict(V=V, E=E, row_ptr_offset=rp_off, col_offset=col_off, val_offset=val_off,
+                         total=total)
+
+
+def rmat_fill_store(base_ptr: int, row_ptr: np.ndarray, lay: dict, scale: int, edge_factor: int,
+                    a: float, b: float, c: float, seed: int) -> None:
+    """Pass 2: writes row_ptr, col and val into the store image at base_ptr."""
+    import ctypes as _C
+    V = lay["V"]
+    _C.memmove(base_ptr + lay["row_ptr_offset"], row_ptr.ctypes.data, 8 * (V + 1))
+    rmat_fill(scale, edge_factor, a, b, c, seed, base_ptr + lay["row_ptr_offset"],
+              base_ptr + lay["col_offset"], base_ptr + lay["val_offset"])
+
+
+def serve_stream(count: int, rate: float, rows: int, alpha: float, seed: int,
+                 max_log2: int = 12, bag_hi: int = 80):
+    """Request stream for the serving workload: Poisson arrivals (mean gap 1/rate),
+    request sizes n = clamp(round(2^(max_log2 * u)), 1, 2^max_log2), each request split
+    into consecutive bags of length uniform [1, bag_hi] (the last one truncated), rows
+    Zipf(alpha).  Returns (arrival_s, req_bag0[count+1], bag_off[nbags+1], idx)."""
+    arrival, size = requests(seed, count, rate, max_log2)
+    total = int(size.sum())
+    lens = uniform_int(seed, S_BAGLEN, total, 1, bag_hi)  # more than enough draws
+    req_bag0 = np.zeros(count + 1, dtype=np.int64)
+    bag_lens = []
+    k = 0
+    for r in range(count):
+        left = int(size[r])
+        nb = 0
+        while left > 0:
+            L = min(int(lens[k]), left)
+            k += 1
+            bag_lens.append(L)
+            left -= L
+            nb += 1
+        req_bag0[r + 1] = req_bag0[r] + nb
+    bag_off = np.zeros(len(bag_lens) + 1, dtype=np.int64)
+    np.cumsum(np.asarray(bag_lens, dtype=np.int64), out=bag_off[1:])
+    idx = zipf_rows(zipf_cum(rows, alpha), seed, total)
+    return arrival, req_bag0, bag_off, idx
