@@ -45,7 +45,154 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--profile-only", action="store_true",
                     help="run warmup + timed steps only (for profilers)")
+    ap.add_argument("--extras", default="serve",
+                    help="comma list of extra measurements: serve, bwd, graph ('' = none)")
+    ap.add_argument("--serve-seconds", type=float, default=1.0)
+    ap.add_argument("--graph-scale", type=int, default=22)
     return ap.parse_args()
+
+
+def measure_serve(agile, gen, seconds: float, log):
+    """Continuous batching over the tiny table: Poisson 20k req/s, requests of 1..4096
+    lookups (log-uniform), bags U[1,80], 1 MiB cache; throughput and latency."""
+    rows, dim = 65536, 64
+    buf = agile.PinnedBuffer(rows * dim * 4)
+    gen.fill_table(buf.ptr, 0, rows, dim, 0)
+    nreq = max(100, int(20000 * seconds))
+    arrival, req_bag0, bag_off, idx = gen.serve_stream(nreq, 20000.0, rows, 1.05, seed=40)
+    res = {}
+    for label, geom in (("default", dict(line_bytes=4096, assoc=8, num_qp=16, qp_depth=1024)),):
+        ctx = agile.Context(cache_bytes=1 << 20, timeout_ns=int(20e9), **geom)
+        ctx.open_store(buf)
+        tb = ctx.tables(rows, dim, 1)
+        _, lat, rep = ctx.serve(tb, 0, arrival, req_bag0, bag_off, idx)
+        st = ctx.stats()
+        ctx.close_store()
+        ctx.shutdown()
+        res[label] = {"geometry": geom, "requests": nreq, "offered_req_per_s": 20000.0,
+                      "req_per_s": round(nreq / rep["elapsed_s"], 1),
+                      "lookups_per_s": round(rep["lookups"] / rep["elapsed_s"], 1),
+                      "p50_ms": round(float(np.median(lat)) * 1e3, 3),
+                      "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 3),
+                      "max_inflight_requests": rep["max_inflight_requests"],
+                      "hit_rate": round(st["hits"] / max(st["requests"], 1), 4)}
+        log(f"serve {label}: {res[label]}")
+    buf.free()
+    return res
+
+
+def measure_bwd(agile, gen, log, steps: int = 4):
+    """Write path at the differentiation configuration: 4 tables of 8,388,608 x 64 fp32
+    (8 GiB store), 1 GiB 16-way cache; batch 4096 x 4 bags, len U[1,40], Zipf(1.1);
+    forward + backward (fused SGD, lr 0.01) per step, then a flush."""
+    import torch
+    rows, dim, T, B = 8388608, 64, 4, 4096
+    tbytes = rows * dim * 4
+    buf = agile.PinnedBuffer(T * tbytes)
+    for t in range(T):
+        gen.fill_table(buf.ptr + t * tbytes, 0, rows, dim, 20 + t)
+    ctx = agile.Context(cache_bytes=1 << 30, line_bytes=4096, assoc=16, num_qp=16, qp_depth=1024,
+                        latency_ns=80_000, iops_cap=1_500_000, timeout_ns=int(20e9))
+    ctx.open_store(buf)
+    tb = ctx.tables(rows, dim, T)
+    cum = gen.zipf_cum(rows, 1.1)
+    bs = []
+    for n in range(steps + 1):
+        off, idx = gen.embbag_batch(cum, B, T, 1, 40, seed=30 + n)
+        g = gen.normal_f32(31 + n, B * T * dim)
+        bs.append((torch.from_numpy(off).cuda(), torch.from_numpy(idx).cuda(),
+                   torch.from_numpy(g).cuda().view(B * T, dim)))
+    out = torch.empty((B * T, dim), device="cuda")
+
+    def step(i):
+        off, idx, g = bs[i]
+        ctx.embbag_forward(tb, idx, off, B, 0, out)
+        ctx.embbag_backward_sgd(tb, idx, off, B, g, 0.01)
+
+    step(0)
+    ctx.sync()
+    ctx.stats(reset=True)
+    t0 = time.perf_counter()
+    for i in range(1, steps + 1):
+        step(i)
+    ctx.sync()
+    el = time.perf_counter() - t0
+    st = ctx.stats()
+    t1 = time.perf_counter()
+    ctx.flush()
+    fl = time.perf_counter() - t1
+    st2 = ctx.stats()
+    looked = sum(int(bs[i][1].numel()) for i in range(1, steps + 1))
+    res = {"steps": steps, "ms_per_step": round(el / steps * 1e3, 3),
+           "lookups_per_s": round(looked / el, 1), "rows_updated": st["rows_updated"],
+           "wb_evict": st["wb_evict"], "flush_lines": st2["wb_flush"], "flush_s": round(fl, 4),
+           "flush_gbs": round(st2["wb_flush"] * 4096 / max(fl, 1e-9) / 1e9, 3)}
+    log(f"bwd: {res}")
+    ctx.close_store()
+    ctx.shutdown()
+    buf.free()
+    return res
+
+
+def measure_graph(agile, gen, oracle, scale: int, log):
+    """Out-of-HBM graph: RMAT(0.57, 0.19, 0.19) with 2^scale vertices and 16 edges per
+    vertex held in the store, 4 GiB cache; BFS levels validated (Graph500 rules) and
+    SpMV sampled rows against the oracle."""
+    import torch
+    abc = (0.57, 0.19, 0.19)
+    t0 = time.perf_counter()
+    row_ptr, lay = gen.rmat_layout(scale, 16, *abc, 0)
+    buf = agile.PinnedBuffer(lay["total"])
+    gen.rmat_fill_store(buf.ptr, row_ptr, lay, scale, 16, *abc, 0)
+    log(f"graph scale {scale}: {lay['E']} edges, store {lay['total'] / 2**30:.2f} GiB, "
+        f"built in {time.perf_counter() - t0:.1f}s")
+    V, E = lay["V"], lay["E"]
+    ctx = agile.Context(cache_bytes=4 << 30, line_bytes=4096, assoc=16, num_qp=16, qp_depth=1024,
+                        timeout_ns=int(30e9))
+    ctx.open_store(buf)
+    g = agile.CSR(V, E, lay["row_ptr_offset"], lay["col_offset"], lay["val_offset"])
+    src = gen.bfs_source(0, row_ptr)
+    level = torch.empty(V, dtype=torch.int32, device="cuda")
+    ctx.invalidate()
+    ctx.stats(reset=True)
+    t1 = time.perf_counter()
+    nl = ctx.bfs(g, src, level)
+    bfs_s = time.perf_counter() - t1
+    bst = ctx.stats()
+    lev = level.cpu().numpy()
+    col = buf.array[lay["col_offset"]:lay["col_offset"] + 4 * E].view(np.int32)
+    val = buf.array[lay["val_offset"]:lay["val_offset"] + 4 * E].view(np.float32)
+    ok_bfs = oracle.bfs_validate(row_ptr, col, src, lev) == 0
+    x = gen.uniform_f32(1, gen.S_X, V, -1.0, 1.0)
+    xd = torch.from_numpy(x).cuda()
+    y = torch.empty(V, dtype=torch.float32, device="cuda")
+    ctx.invalidate()
+    ctx.stats(reset=True)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    ctx.spmv(g, xd, y)
+    ctx.sync()
+    spmv_s = time.perf_counter() - t2
+    sst = ctx.stats()
+    yh = y.cpu().numpy()
+    rng = np.random.default_rng(3)
+    rows_s = np.sort(rng.choice(V, 2048, replace=False))
+    ok_spmv = True
+    for r in rows_s:
+        if yh[r].view(np.uint32) != oracle.spmv(row_ptr, col, val, x, int(r), int(r) + 1)[0].view(np.uint32):
+            ok_spmv = False
+            break
+    store_bytes = 8 * (V + 1) + 8 * E
+    res = {"scale": scale, "V": V, "E": E, "bfs_s": round(bfs_s, 4), "bfs_levels": nl,
+           "bfs_valid": ok_bfs, "bfs_reached": int((lev >= 0).sum()),
+           "bfs_read_cmds": bst["read_cmds"], "spmv_s": round(spmv_s, 4),
+           "spmv_gbs": round(store_bytes / spmv_s / 1e9, 3), "spmv_read_cmds": sst["read_cmds"],
+           "spmv_sampled_rows_bit_exact": ok_spmv}
+    log(f"graph: {res}")
+    ctx.close_store()
+    ctx.shutdown()
+    buf.free()
+    return res
 
 
 def main():
@@ -250,6 +397,20 @@ def main():
                          f"pinned image directly ({el:.1f} s)"}
         log(f"cpu oracle: {cpu['value']} rows/s on {nbags} bags")
 
+    extras = {}
+    wanted = [e for e in args.extras.split(",") if e]
+    if wanted:
+        ctx.close_store()
+        ctx.shutdown()
+        buf.free()
+        ctx = None
+        if "serve" in wanted:
+            extras["serving"] = measure_serve(agile, gen, args.serve_seconds, log)
+        if "bwd" in wanted:
+            extras["write_path"] = measure_bwd(agile, gen, log)
+        if "graph" in wanted:
+            extras["graph"] = measure_graph(agile, gen, oracle, args.graph_scale, log)
+
     ms_step = float(np.mean(ms_async))
     rows_per_s = lookups_timed / (sum(ms_async) * 1e-3)
     iops = reads / (sum(ms_async) * 1e-3)
@@ -294,13 +455,15 @@ def main():
                      "kernel": "k_embbag<2>",
                      "note": "the step is bounded by the emulated store (see store_roofline)"},
         "cpu_baseline": cpu,
+        **extras,
         "device": {"cus": info["cu_count"], "wallclock_hz": info["wallclock_hz"],
                    "user_waves": info["max_user_waves"]},
     }
     print(json.dumps(rec), flush=True)
-    ctx.close_store()
-    ctx.shutdown()
-    buf.free()
+    if ctx is not None:
+        ctx.close_store()
+        ctx.shutdown()
+        buf.free()
 
 
 if __name__ == "__main__":

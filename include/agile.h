@@ -69,7 +69,7 @@ typedef struct agile_config {
   uint32_t assoc;        /* ways per set; (cache_bytes / line_bytes) % assoc == 0 */
   uint32_t num_qp;       /* queue pairs, 1..1024 */
   uint32_t qp_depth;     /* entries per SQ and per CQ: power of two in [64, 65536] */
-  uint32_t ctrl_waves;   /* emulated-controller wavefronts (0 = num_qp) */
+  uint32_t ctrl_waves;   /* emulated-controller wavefronts (0 = max(num_qp, 64)) */
   uint32_t cq_waves;     /* completion-service wavefronts (0 = min(num_qp, 64)) */
   uint32_t max_user_waves; /* cap on user wavefronts per launch (0 = fill the GPU) */
   uint64_t latency_ns;   /* emulated per-command latency, fetch to completion */

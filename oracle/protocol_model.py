@@ -29,6 +29,15 @@ the submission loop rings while it still waits for slots.
 commands at once or none of them.  It deadlocks: the completion queue's room frees only
 when the polling window is full, and the window may need some of the very entries the
 controller holds back.  The controller therefore posts as many as fit.
+
+``explore_fetch`` models several controller wavefronts that share one submission
+queue: each claims a run of issued commands by reading the queue's fetch pointer and
+its doorbell and then advancing the fetch pointer with a compare-and-swap, while
+submitters keep ringing the doorbell.  With the doorbell read first, a controller can
+pair a stale doorbell with a fetch pointer that others have already moved past it; the
+unsigned difference wraps and the claim reaches beyond the doorbell.  Reading the fetch
+pointer first (the doorbell can only have grown since), or rejecting differences larger
+than the queue, keeps every claim behind the doorbell.
 """
 from __future__ import annotations
 
@@ -200,6 +209,59 @@ def explore(model: str, depth: int, reqs, window: int = None, limit: int = 2_000
         nxt = succ(s)
         if not nxt and not fin(s):
             return len(seen), s
+        for n in nxt:
+            if n not in seen:
+                seen.add(n)
+                if len(seen) > limit:
+                    raise RuntimeError("state limit exceeded")
+                q.append(n)
+    return len(seen), None
+
+
+def explore_fetch(order: str, controllers: int = 2, total: int = 4, depth: int = 2,
+                  nfree: int = 2, guard: bool = False, limit: int = 2_000_000):
+    """Shared fetch of one SQ by several controllers (32-bit pointers).
+
+    order: "db_first" or "fetch_first".  guard: skip a claim whose difference exceeds the
+    depth.  Returns (states, violating state or None); a violation is a successful claim
+    whose end lies beyond the doorbell at the moment of the claim."""
+    M = 1 << 32
+    first_db = order == "db_first"
+    if order not in ("db_first", "fetch_first"):
+        raise ValueError(order)
+    start = (0, 0, tuple((0, 0, 0) for _ in range(controllers)))  # db, fetch, (pc, r1, r2)
+    seen = {start}
+    q = deque([start])
+    while q:
+        st = q.popleft()
+        db, fetch, cs = st
+        nxt = []
+        # submitters ring one more command while the queue has a free slot (fetched
+        # commands complete at once, so the slots behind the fetch pointer are free)
+        if db < total and db - fetch < depth:
+            nxt.append((db + 1, fetch, cs))
+        for i, (pc, r1, r2) in enumerate(cs):
+            c = list(cs)
+            if pc == 0:
+                c[i] = (1, db if first_db else fetch, 0)
+                nxt.append((db, fetch, tuple(c)))
+            elif pc == 1:
+                c[i] = (2, r1, fetch if first_db else db)
+                nxt.append((db, fetch, tuple(c)))
+            else:
+                r_db, r_f = (r1, r2) if first_db else (r2, r1)
+                avail = (r_db - r_f) % M
+                c[i] = (0, 0, 0)
+                if avail == 0 or (guard and avail > depth):
+                    nxt.append((db, fetch, tuple(c)))
+                    continue
+                k = min(avail, nfree)
+                if fetch == r_f:
+                    if r_f + k > db:
+                        return len(seen), (db, fetch, cs, i)
+                    nxt.append((db, r_f + k, tuple(c)))
+                else:
+                    nxt.append((db, fetch, tuple(c)))
         for n in nxt:
             if n not in seen:
                 seen.add(n)

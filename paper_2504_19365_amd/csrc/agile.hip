@@ -106,7 +106,7 @@ __device__ bool wait_published(const dev_ctx& c, const embbag_args& a, uint32_t 
   while (uni(ld_rlx(a.pub_dev)) <= r) {
     if ((++n & 63) == 0) {
       if (aborted(c)) return false;
-      if (uni(__hip_atomic_load(a.pub_host + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM))) return false;
+      if (uni(ld_rlx(a.pub_dev + 1))) return false;  // stop, mirrored from the host
     }
     __builtin_amdgcn_s_sleep(32);
   }
@@ -117,7 +117,7 @@ __device__ bool wait_published(const dev_ctx& c, const embbag_args& a, uint32_t 
 // Next chunk after `d` (or the first one when !d.valid): continues the bag or grabs the
 // next non-empty bag; empty bags get their zero output on the way.
 template <int VPL>
-__device__ desc_t next_desc(const dev_ctx& c, const launch_t& li, const embbag_args& a,
+__device__ __forceinline__ desc_t next_desc(const dev_ctx& c, const launch_t& li, const embbag_args& a,
                             const desc_t& d, src_state& ss, bool may_wait) {
   desc_t r;
   r.valid = false;
@@ -220,7 +220,7 @@ __device__ __forceinline__ void ld_row(const float* p, float (&v)[VPL]) {
 // tenant while it was read (seqlock-style: the metadata is re-read after the data loads
 // have completed).  Returns the number of rows consumed.
 template <int VPL>
-__device__ uint32_t consume(const dev_ctx& c, const embbag_args& a, const desc_t& d,
+__device__ __forceinline__ uint32_t consume(const dev_ctx& c, const embbag_args& a, const desc_t& d,
                             const chunk_t& ch, float (&acc)[VPL], bool validate) {
   const uint64_t okm = ballot(ch.act && st_ok(ch.st));
   const uint32_t nok = (~okm == 0ull) ? 64u : ffs64(~okm);
@@ -272,7 +272,7 @@ __device__ uint32_t consume(const dev_ctx& c, const embbag_args& a, const desc_t
 
 // One user wavefront of the embedding-bag / gather workload.
 template <int VPL>
-__device__ void embbag_wave(const dev_ctx& c, const launch_t& li, const embbag_args& a, uint32_t uw) {
+__device__ __forceinline__ void embbag_wave(const dev_ctx& c, const launch_t& li, const embbag_args& a, uint32_t uw) {
   const uint32_t q = uw % c.num_qp;
   const bool async = a.mode == AGILE_MODE_ASYNC;
   float acc[VPL];
@@ -405,8 +405,9 @@ __global__ __launch_bounds__(WG) void k_embbag(dev_ctx c, launch_t li, embbag_ar
 }
 
 // Serving kernel: the embedding-bag wave loop over a stream of requests.  One extra
-// service wavefront mirrors the host's count of published requests into device memory,
-// so that waiting waves poll HBM instead of sending PCIe reads.
+// service wavefront mirrors the host's count of published requests, its stop flag and
+// its abort flag into device memory, so that waiting waves poll HBM instead of sending
+// PCIe reads.
 __device__ void mirror_published(const dev_ctx& c, const embbag_args& a, uint32_t nreq, uint32_t* pub_dev) {
   uint32_t last = 0;
   for (;;) {
@@ -415,8 +416,11 @@ __device__ void mirror_published(const dev_ctx& c, const embbag_args& a, uint32_
       last = v;
       if (lane() == 0) st_rlx(pub_dev, v);
     }
-    if (last >= nreq || aborted(c)) break;
-    if (uni(__hip_atomic_load(a.pub_host + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM))) break;
+    if (last >= nreq || aborted(c) || host_abort_poll(c)) break;
+    if (uni(__hip_atomic_load(a.pub_host + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM))) {
+      if (lane() == 0) st_rlx(pub_dev + 1, 1u);
+      break;
+    }
     __builtin_amdgcn_s_sleep(16);
   }
 }
@@ -1062,6 +1066,7 @@ struct agile_ctx_s {
   std::vector<int> occ_cache;  // resident workgroups per CU, per kernel kind
   void* scratch = nullptr;     // backward-pass work arrays, grown on demand
   size_t scratch_bytes = 0;
+  uint32_t iso_lds = 0;        // dynamic LDS that makes one workgroup fill a CU
 };
 
 namespace {
@@ -1107,19 +1112,20 @@ int occupancy(agile_ctx ctx, int kind) {
   if (v > 0) return v;
   int nb = 0;
   hipError_t e = hipSuccess;
+  const size_t L = ctx->iso_lds;
   switch (kind) {
-    case KIND_EMBBAG1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_embbag<1>, WG, 0); break;
-    case KIND_EMBBAG2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_embbag<2>, WG, 0); break;
-    case KIND_EMBBAG4: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_embbag<4>, WG, 0); break;
-    case KIND_READ: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_async_read, WG, 0); break;
-    case KIND_FLUSH: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_flush, WG, 0); break;
-    case KIND_BWD1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_bwd_sgd<1>, WG, 0); break;
-    case KIND_BWD2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_bwd_sgd<2>, WG, 0); break;
-    case KIND_BWD4: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_bwd_sgd<4>, WG, 0); break;
-    case KIND_SERVE1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_serve<1>, WG, 0); break;
-    case KIND_SERVE2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_serve<2>, WG, 0); break;
-    case KIND_SERVE4: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_serve<4>, WG, 0); break;
-    default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_trace, WG, 0); break;
+    case KIND_EMBBAG1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_embbag<1>, WG, L); break;
+    case KIND_EMBBAG2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_embbag<2>, WG, L); break;
+    case KIND_EMBBAG4: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_embbag<4>, WG, L); break;
+    case KIND_READ: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_async_read, WG, L); break;
+    case KIND_FLUSH: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_flush, WG, L); break;
+    case KIND_BWD1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_bwd_sgd<1>, WG, L); break;
+    case KIND_BWD2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_bwd_sgd<2>, WG, L); break;
+    case KIND_BWD4: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_bwd_sgd<4>, WG, L); break;
+    case KIND_SERVE1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_serve<1>, WG, L); break;
+    case KIND_SERVE2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_serve<2>, WG, L); break;
+    case KIND_SERVE4: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_serve<4>, WG, L); break;
+    default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_trace, WG, L); break;
   }
   if (e != hipSuccess || nb <= 0) nb = 1;
   v = nb;
@@ -1261,7 +1267,8 @@ agile_status agile_init(const agile_config* cfg_in, agile_ctx* out) {
   if (lines > 0xFFFFFFFFull) return AGILE_EINVAL;
   if (cfg.num_qp == 0 || cfg.num_qp > 1024) return AGILE_EINVAL;
   if (cfg.qp_depth < 64 || cfg.qp_depth > 65536 || !is_pow2(cfg.qp_depth)) return AGILE_EINVAL;
-  uint32_t n_ctrl = cfg.ctrl_waves ? cfg.ctrl_waves : cfg.num_qp;
+  // by default enough controller wavefronts that their PCIe copies are not the limit
+  uint32_t n_ctrl = cfg.ctrl_waves ? cfg.ctrl_waves : std::max<uint32_t>(cfg.num_qp, 64);
   uint32_t n_cq = cfg.cq_waves ? cfg.cq_waves : std::min<uint32_t>(cfg.num_qp, 64);
   if (n_ctrl > 4096 || n_cq > 1024) return AGILE_EINVAL;
   if ((uint64_t)n_cq * 64 < cfg.num_qp) return AGILE_EINVAL;  // <= 64 CQs per polling wave
@@ -1287,6 +1294,24 @@ agile_status agile_init(const agile_config* cfg_in, agile_ctx* out) {
   }
   ctx->cu_count = (uint32_t)cus;
   ctx->clock_hz = (uint64_t)wclk_khz * 1000ull;
+  {
+    // more than half a CU's LDS per workgroup: one workgroup per CU for service kernels
+    int lds_cu = 0;
+    if (hipDeviceGetAttribute(&lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, cfg.device) != hipSuccess)
+      lds_cu = 0;
+    uint32_t iso = lds_cu > 0 ? (uint32_t)((lds_cu / 2 + 1024 + 255) & ~255) : 0u;
+    const void* fns[] = {(const void*)k_async_read, (const void*)k_flush, (const void*)k_embbag<1>,
+                         (const void*)k_embbag<2>, (const void*)k_embbag<4>, (const void*)k_bfs_front,
+                         (const void*)k_bfs_edges, (const void*)k_spmv, (const void*)k_bwd_sgd<1>,
+                         (const void*)k_bwd_sgd<2>, (const void*)k_bwd_sgd<4>, (const void*)k_serve<1>,
+                         (const void*)k_serve<2>, (const void*)k_serve<4>, (const void*)k_trace};
+    for (const void* f : fns)
+      if (iso && hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)iso) != hipSuccess) {
+        (void)hipGetLastError();
+        iso = 0;
+      }
+    ctx->iso_lds = iso;
+  }
   ctx->n_ctrl = n_ctrl;
   ctx->n_cq = n_cq;
   ctx->service_blocks = (n_ctrl + n_cq + WPB - 1) / WPB;
@@ -1303,7 +1328,7 @@ agile_status agile_init(const agile_config* cfg_in, agile_ctx* out) {
   d.depth = cfg.qp_depth;
   d.depth_shift = log2u(cfg.qp_depth);
   d.lat_ticks = (uint64_t)((double)cfg.latency_ns * 1e-9 * (double)ctx->clock_hz + 0.5);
-  d.tok_fp = cfg.iops_cap ? (uint64_t)((double)ctx->clock_hz / (double)cfg.iops_cap * 4294967296.0) : 0;
+  d.tok_fp = cfg.iops_cap ? (uint64_t)((double)ctx->clock_hz / (double)cfg.iops_cap * (double)(1ull << TOK_FRAC)) : 0;
   d.timeout_ticks = (uint64_t)((double)cfg.timeout_ns * 1e-9 * (double)ctx->clock_hz);
   d.flags = cfg.flags;
 
@@ -1321,6 +1346,7 @@ agile_status agile_init(const agile_config* cfg_in, agile_ctx* out) {
   if ((s = dalloc(ctx, &d.cnt, (uint64_t)C_COUNT * CSTRIDE * 8)) != AGILE_OK) return bail(s);
   if ((s = dalloc(ctx, &d.err, 128)) != AGILE_OK) return bail(s);
   if ((s = dalloc(ctx, &d.err_info, 128)) != AGILE_OK) return bail(s);
+  if ((s = dalloc(ctx, &d.abort_dev, 128)) != AGILE_OK) return bail(s);
   void* ab = nullptr;
   if (hipHostMalloc(&ab, 4096, hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess) {
     (void)hipGetLastError();
@@ -1338,7 +1364,7 @@ agile_status agile_init(const agile_config* cfg_in, agile_ctx* out) {
       hipMemset(d.sq, 0, nq * sizeof(sqe_t)) != hipSuccess || hipMemset(d.cq, 0, nq * sizeof(cqe_t)) != hipSuccess ||
       hipMemset(d.qp, 0, (uint64_t)cfg.num_qp * sizeof(qp_t)) != hipSuccess || hipMemset(d.next_tok, 0, 128) != hipSuccess ||
       hipMemset(d.cnt, 0, (uint64_t)C_COUNT * CSTRIDE * 8) != hipSuccess || hipMemset(d.err, 0, 128) != hipSuccess ||
-      hipMemset(d.err_info, 0, 128) != hipSuccess)
+      hipMemset(d.err_info, 0, 128) != hipSuccess || hipMemset(d.abort_dev, 0, 128) != hipSuccess)
     return bail(AGILE_EHIP);
   std::vector<uint32_t> slots(nq);
   for (uint64_t i = 0; i < nq; ++i) slots[i] = (uint32_t)((i % cfg.qp_depth) << 2) | SLOT_EMPTY;
@@ -1454,7 +1480,7 @@ agile_status agile_async_read(agile_ctx ctx, agile_store store, const uint64_t* 
   uint32_t uw = std::min<uint32_t>((n + 63) / 64, user_wave_cap(ctx, KIND_READ));
   uw = (uw + WPB - 1) / WPB * WPB;
   launch_t li = make_launch(ctx, uw, true, 0);
-  hipLaunchKernelGGL(k_async_read, dim3(li.service_blocks + uw / WPB), dim3(WG), 0, (hipStream_t)stream,
+  hipLaunchKernelGGL(k_async_read, dim3(li.service_blocks + uw / WPB), dim3(WG), ctx->iso_lds, (hipStream_t)stream,
                      ctx->d, li, d_blocks, n, d_tickets);
   HIPCHK(ctx, hipGetLastError());
   return AGILE_OK;
@@ -1502,7 +1528,7 @@ agile_status agile_flush(agile_ctx ctx, agile_store store, void* stream) {
   uint32_t uw = std::min<uint32_t>((ctx->d.num_lines + 63) / 64, user_wave_cap(ctx, KIND_FLUSH));
   uw = (uw + WPB - 1) / WPB * WPB;
   launch_t li = make_launch(ctx, uw, true, 0);
-  hipLaunchKernelGGL(k_flush, dim3(li.service_blocks + uw / WPB), dim3(WG), 0, hs, ctx->d, li);
+  hipLaunchKernelGGL(k_flush, dim3(li.service_blocks + uw / WPB), dim3(WG), ctx->iso_lds, hs, ctx->d, li);
   HIPCHK(ctx, hipGetLastError());
   return sync_stream(ctx, hs);
 }
@@ -1614,11 +1640,11 @@ static agile_status embbag_launch(agile_ctx ctx, agile_store store, const agile_
   const dim3 grid(li.service_blocks + uw / WPB);
   hipStream_t hs = (hipStream_t)stream;
   if (kind == KIND_EMBBAG1)
-    hipLaunchKernelGGL(k_embbag<1>, grid, dim3(WG), 0, hs, ctx->d, li, a);
+    hipLaunchKernelGGL(k_embbag<1>, grid, dim3(WG), ctx->iso_lds, hs, ctx->d, li, a);
   else if (kind == KIND_EMBBAG2)
-    hipLaunchKernelGGL(k_embbag<2>, grid, dim3(WG), 0, hs, ctx->d, li, a);
+    hipLaunchKernelGGL(k_embbag<2>, grid, dim3(WG), ctx->iso_lds, hs, ctx->d, li, a);
   else
-    hipLaunchKernelGGL(k_embbag<4>, grid, dim3(WG), 0, hs, ctx->d, li, a);
+    hipLaunchKernelGGL(k_embbag<4>, grid, dim3(WG), ctx->iso_lds, hs, ctx->d, li, a);
   HIPCHK(ctx, hipGetLastError());
   return AGILE_OK;
 }
@@ -1708,6 +1734,7 @@ agile_status agile_bfs(agile_ctx ctx, agile_store store, const agile_csr* g, uin
   HIPCHK(ctx, hipGetLastError());
   uint32_t nF = 1;
   int32_t L = 0;
+  uint32_t levels = 1;  // levels that hold at least one vertex
   const uint64_t by_cache = std::max<uint64_t>(1, ctx->d.num_lines / 128);
   while (nF > 0) {
     a.F = F;
@@ -1718,7 +1745,7 @@ agile_status agile_bfs(agile_ctx ctx, agile_store store, const agile_csr* g, uin
     uint32_t uw = (uint32_t)std::min<uint64_t>({(nF + 63) / 64, (uint64_t)user_wave_cap(ctx, KIND_READ), by_cache});
     uw = (uw + WPB - 1) / WPB * WPB;
     launch_t li = make_launch(ctx, uw, true, 0);
-    hipLaunchKernelGGL(k_bfs_front, dim3(li.service_blocks + uw / WPB), dim3(WG), 0, hs, ctx->d, li, a);
+    hipLaunchKernelGGL(k_bfs_front, dim3(li.service_blocks + uw / WPB), dim3(WG), ctx->iso_lds, hs, ctx->d, li, a);
     HIPCHK(ctx, hipGetLastError());
     uint32_t nC = 0;
     HIPCHK(ctx, hipMemcpyAsync(&nC, a.ctr, 4, hipMemcpyDeviceToHost, hs));
@@ -1734,14 +1761,15 @@ agile_status agile_bfs(agile_ctx ctx, agile_store store, const agile_csr* g, uin
     uw = (uint32_t)std::min<uint64_t>({(a.Et + 1023) / 1024, (uint64_t)user_wave_cap(ctx, KIND_READ), by_cache});
     uw = (uw + WPB - 1) / WPB * WPB;
     li = make_launch(ctx, uw, true, 0);
-    hipLaunchKernelGGL(k_bfs_edges, dim3(li.service_blocks + uw / WPB), dim3(WG), 0, hs, ctx->d, li, a);
+    hipLaunchKernelGGL(k_bfs_edges, dim3(li.service_blocks + uw / WPB), dim3(WG), ctx->iso_lds, hs, ctx->d, li, a);
     HIPCHK(ctx, hipGetLastError());
     HIPCHK(ctx, hipMemcpyAsync(&nF, a.ctr + 1, 4, hipMemcpyDeviceToHost, hs));
     if ((s = sync_stream(ctx, hs)) != AGILE_OK) return s;
+    if (nF) ++levels;
     std::swap(F, N);
     ++L;
   }
-  if (out_levels) *out_levels = (uint32_t)(L + 1);
+  if (out_levels) *out_levels = levels;
   return AGILE_OK;
 }
 
@@ -1766,7 +1794,7 @@ agile_status agile_spmv(agile_ctx ctx, agile_store store, const agile_csr* g, co
                                               by_cache});
   uw = (uw + WPB - 1) / WPB * WPB;
   launch_t li = make_launch(ctx, uw, true, 0);
-  hipLaunchKernelGGL(k_spmv, dim3(li.service_blocks + uw / WPB), dim3(WG), 0, hs, ctx->d, li, a);
+  hipLaunchKernelGGL(k_spmv, dim3(li.service_blocks + uw / WPB), dim3(WG), ctx->iso_lds, hs, ctx->d, li, a);
   HIPCHK(ctx, hipGetLastError());
   return AGILE_OK;
 }
@@ -1839,11 +1867,11 @@ agile_status agile_embbag_backward_sgd(agile_ctx ctx, agile_store store, const a
   launch_t li = make_launch(ctx, uw, true, 0);
   const dim3 grid(li.service_blocks + uw / WPB);
   if (kind == KIND_BWD1)
-    hipLaunchKernelGGL(k_bwd_sgd<1>, grid, dim3(WG), 0, hs, ctx->d, li, a);
+    hipLaunchKernelGGL(k_bwd_sgd<1>, grid, dim3(WG), ctx->iso_lds, hs, ctx->d, li, a);
   else if (kind == KIND_BWD2)
-    hipLaunchKernelGGL(k_bwd_sgd<2>, grid, dim3(WG), 0, hs, ctx->d, li, a);
+    hipLaunchKernelGGL(k_bwd_sgd<2>, grid, dim3(WG), ctx->iso_lds, hs, ctx->d, li, a);
   else
-    hipLaunchKernelGGL(k_bwd_sgd<4>, grid, dim3(WG), 0, hs, ctx->d, li, a);
+    hipLaunchKernelGGL(k_bwd_sgd<4>, grid, dim3(WG), ctx->iso_lds, hs, ctx->d, li, a);
   HIPCHK(ctx, hipGetLastError());
   return AGILE_OK;
 }
@@ -1968,11 +1996,11 @@ agile_status agile_serve(agile_ctx ctx, agile_store store, const agile_tables* t
   li.service_blocks = (ctx->n_ctrl + ctx->n_cq + 1 + WPB - 1) / WPB;  // + the publication mirror
   const dim3 grid(li.service_blocks + uw / WPB);
   if (kind == KIND_SERVE1)
-    hipLaunchKernelGGL(k_serve<1>, grid, dim3(WG), 0, hs, ctx->d, li, a, (uint32_t)nreq, (uint32_t*)(sb + o_pub));
+    hipLaunchKernelGGL(k_serve<1>, grid, dim3(WG), ctx->iso_lds, hs, ctx->d, li, a, (uint32_t)nreq, (uint32_t*)(sb + o_pub));
   else if (kind == KIND_SERVE2)
-    hipLaunchKernelGGL(k_serve<2>, grid, dim3(WG), 0, hs, ctx->d, li, a, (uint32_t)nreq, (uint32_t*)(sb + o_pub));
+    hipLaunchKernelGGL(k_serve<2>, grid, dim3(WG), ctx->iso_lds, hs, ctx->d, li, a, (uint32_t)nreq, (uint32_t*)(sb + o_pub));
   else
-    hipLaunchKernelGGL(k_serve<4>, grid, dim3(WG), 0, hs, ctx->d, li, a, (uint32_t)nreq, (uint32_t*)(sb + o_pub));
+    hipLaunchKernelGGL(k_serve<4>, grid, dim3(WG), ctx->iso_lds, hs, ctx->d, li, a, (uint32_t)nreq, (uint32_t*)(sb + o_pub));
   HIPCHK(ctx, hipGetLastError());
   // ---- host loop: publish arrivals in real time, admit by queue and cache budget, and
   //      record when each request's outputs become visible
@@ -2056,7 +2084,7 @@ agile_status agile_debug_trace(agile_ctx ctx, agile_store store, const uint64_t*
   if (n == 0) return AGILE_OK;
   if (!d_lines || !d_hit || !d_way) return fail(ctx, AGILE_EINVAL, "trace: null pointer");
   launch_t li = make_launch(ctx, WPB, true, 0);
-  hipLaunchKernelGGL(k_trace, dim3(li.service_blocks + 1), dim3(WG), 0, (hipStream_t)stream, ctx->d, li, d_lines,
+  hipLaunchKernelGGL(k_trace, dim3(li.service_blocks + 1), dim3(WG), ctx->iso_lds, (hipStream_t)stream, ctx->d, li, d_lines,
                      d_writes, n, d_hit, d_way);
   HIPCHK(ctx, hipGetLastError());
   return sync_stream(ctx, (hipStream_t)stream);

@@ -178,12 +178,13 @@ struct dev_ctx {
   uint64_t store_blocks;
   // emulator
   uint64_t lat_ticks;
-  uint64_t tok_fp;  // ticks per command, 32.32 fixed point; 0 = no cap
+  uint64_t tok_fp;  // ticks per command in TOK_FRAC-bit fixed point; 0 = no cap
   uint64_t* next_tok;
   // control
   uint64_t* cnt;
   uint32_t* err;
-  uint32_t* abort_flag;
+  uint32_t* abort_flag;  // pinned host word: the host watchdog raises it
+  uint32_t* abort_dev;   // device word that every wait polls
   uint64_t* err_info;
   uint64_t timeout_ticks;
   uint32_t flags;
@@ -200,8 +201,16 @@ struct launch_t {
   uint32_t _l0;
 };
 
-constexpr uint32_t WG = 256;  // threads per workgroup: 4 wavefronts
+// Threads per workgroup: 16 wavefronts.  Kernels that carry service wavefronts also
+// reserve more than half of a CU's LDS, so that exactly one workgroup fits per CU: the
+// leading service workgroups then own whole CUs and no user wave shares a SIMD or a
+// memory pipeline with the emulated controller or the completion service.
+constexpr uint32_t WG = 1024;
 constexpr uint32_t FLAG_PROFILE = 0x4;
+// Token times of the IOPS cap are kept in 44.20 fixed point of the wall clock, modulo
+// 2^64: the 44-bit integer part wraps after about two days of 100 MHz ticks, so they are
+// only ever compared through signed differences.
+constexpr uint32_t TOK_FRAC = 20;
 constexpr uint32_t WPB = WG / 64;
 
 __device__ __forceinline__ uint64_t* counter(const dev_ctx& c, uint32_t i) {
@@ -210,8 +219,6 @@ __device__ __forceinline__ uint64_t* counter(const dev_ctx& c, uint32_t i) {
 __device__ __forceinline__ void count(const dev_ctx& c, uint32_t i, uint64_t v) {
   if (v) add_rlx(counter(c, i), v);
 }
-// The abort flag lives in pinned host memory so that the host can also raise it while
-// kernels run (host-side watchdog); it is read with system scope.
 __device__ __forceinline__ bool profiling(const dev_ctx& c) { return (c.flags & FLAG_PROFILE) != 0; }
 // Adds now() - t to timer i (lane 0 only, profile flag only); returns now().
 __device__ __forceinline__ uint64_t ptick(const dev_ctx& c, uint32_t i, uint64_t t) {
@@ -220,30 +227,39 @@ __device__ __forceinline__ uint64_t ptick(const dev_ctx& c, uint32_t i, uint64_t
   if (lane() == 0) add_rlx(c.cnt + (size_t)i * CSTRIDE, n - t);
   return n;
 }
-__device__ __forceinline__ bool aborted(const dev_ctx& c) {
-  return uni(__hip_atomic_load(c.abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM)) != 0;
+// Abort has two words.  The host watchdog can only raise the one in pinned host memory;
+// waits poll the device word, since thousands of waves reading host memory in their
+// spin loops would flood the PCIe link that the controller's copies use.  A few waves
+// (one controller wavefront, the serving mirror, and every spinning wave at a low rate)
+// look at the host word and copy a raised flag into the device word.
+__device__ __forceinline__ bool aborted(const dev_ctx& c) { return uni(ld_rlx(c.abort_dev)) != 0; }
+__device__ __forceinline__ bool host_abort_poll(const dev_ctx& c) {
+  if (!uni(__hip_atomic_load(c.abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM))) return false;
+  if (lane() == 0) st_rlx(c.abort_dev, 1u);
+  return true;
 }
 __device__ __noinline__ void raise_error(const dev_ctx& c, uint32_t code, uint64_t info) {
   uint32_t z = 0;
   if (cas(c.err, z, code)) st_rlx(c.err_info, info);
+  st_rlx(c.abort_dev, 1u);
   __hip_atomic_store(c.abort_flag, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
 // Bounded spin helper: returns false (and raises E_TIMEDOUT) when the deadline passes or
 // the context is aborted.
+// Exponential backoff (about 0.1 us doubling to about 7 us): thousands of waiting waves
+// must not flood the memory system that the controller's copies share.
 struct spin_t {
   uint64_t t0;
   uint32_t n;
   __device__ spin_t() : t0(now()), n(0) {}
   __device__ __forceinline__ bool step(const dev_ctx& c, uint64_t info) {
     ++n;
-    if (n < 8) {
-      __builtin_amdgcn_s_sleep(1);
-    } else {
-      __builtin_amdgcn_s_sleep(8);
-    }
-    if ((n & 15) == 0) {
+    const uint32_t reps = n < 7 ? (1u << (n - 1)) : 64u;
+    for (uint32_t r = 0; r < reps; ++r) __builtin_amdgcn_s_sleep(4);
+    if (n >= 7 || (n & 3) == 0) {
       if (aborted(c)) return false;
+      if ((n & 255) == 0 && host_abort_poll(c)) return false;  // about every 2 ms
       if (now() - t0 > c.timeout_ticks) {
         if (lane() == ffs64(ballot(true))) raise_error(c, E_TIMEDOUT, info);
         return false;
@@ -268,7 +284,7 @@ __device__ __forceinline__ uint8_t* line_ptr(const dev_ctx& c, uint32_t idx) {
 // turning UPDATED slots of the expected lap into ISSUED until the first slot that is not
 // (an unwritten or empty entry), then stores the new tail into the doorbell.  The wave
 // returns once its last ticket is behind the doorbell.  Returns false on abort/timeout.
-__device__ bool submit(const dev_ctx& c, uint32_t q, bool want, uint32_t opc, uint32_t line_idx,
+__device__ __forceinline__ bool submit(const dev_ctx& c, uint32_t q, bool want, uint32_t opc, uint32_t line_idx,
                        uint64_t slba, uint32_t nblk) {
   const uint64_t m = ballot(want);
   if (!m) return true;
@@ -391,7 +407,7 @@ __device__ __forceinline__ void copy_blocks(uint8_t* const* dst, const uint8_t* 
 // Copies the blocks of the commands in `ready`, up to four 4 KiB blocks in flight per
 // wave (the store-side memory-level parallelism comes from the number of controller
 // wavefronts).
-__device__ void copy_cmds(const dev_ctx& c, uint64_t ready, uint32_t p_opc, uint32_t p_nblk,
+__device__ __forceinline__ void copy_cmds(const dev_ctx& c, uint64_t ready, uint32_t p_opc, uint32_t p_nblk,
                           uint32_t p_status, uint64_t p_slba, uint64_t p_prp) {
   uint8_t* dst[4];
   const uint8_t* src[4];
@@ -422,7 +438,7 @@ __device__ void copy_cmds(const dev_ctx& c, uint64_t ready, uint32_t p_opc, uint
 // bucket when an IOPS cap is set, and completes a command once
 // now >= max(fetch + latency, token time): the block(s) are copied across PCIe between
 // the pinned image and the HBM line, then a phase-tagged CQE is posted.
-__device__ void controller(const dev_ctx& c, const launch_t& li, uint32_t cw) {
+__device__ __forceinline__ void controller(const dev_ctx& c, const launch_t& li, uint32_t cw) {
   const uint32_t dmask = c.depth - 1;
   const bool shared = li.n_ctrl > c.num_qp;
   const uint32_t qstep = li.n_ctrl < c.num_qp ? li.n_ctrl : c.num_qp;
@@ -433,20 +449,27 @@ __device__ void controller(const dev_ctx& c, const launch_t& li, uint32_t cw) {
   uint64_t p_slba = 0, p_prp = 0, p_deadline = 0;
   uint64_t idle_since = now();
   uint64_t busy = 0;
-  uint32_t loops = 0;
+  uint32_t loops = 0, idle_rounds = 0;
+  uint64_t host_seen = idle_since;
   for (;;) {
     if (((++loops) & 1023) == 0 && lane() == 0) count(c, C_CTRL_LOOPS, 1);
     const uint64_t t = now();
+    if (cw == 0 && t - host_seen > 2000) {  // mirror the host's abort flag every 20 us
+      host_seen = t;
+      if (host_abort_poll(c)) break;
+    }
     uint64_t tp = t;
     bool progress = false;
     // 1. fetch into free lanes
     uint64_t freem = ballot(!pend);
     for (uint32_t q = q0; q < c.num_qp && freem; q += qstep) {
       qp_t* qs = c.qp + q;
+      // the fetch pointer first: a doorbell read before it may be older than a fetch
+      // pointer that other controllers have since advanced, and the difference would wrap
+      const uint32_t f = uni(ld_acq(&qs->fetch));
       const uint32_t db = uni(ld_rlx(&qs->db));
-      const uint32_t f = uni(ld_rlx(&qs->fetch));
       uint32_t avail = db - f;
-      if (avail == 0) continue;
+      if (avail == 0 || avail > c.depth) continue;
       fence_acq();  // the entries behind the doorbell are visible from here on
       const uint32_t nfree = __popcll(freem);
       const uint32_t k = avail < nfree ? avail : nfree;
@@ -463,17 +486,19 @@ __device__ void controller(const dev_ctx& c, const launch_t& li, uint32_t cw) {
       if (lane() == 0) count(c, C_CTRL_FETCH, k);
       const uint32_t r = mbcnt(freem);
       const bool take = ((freem >> lane()) & 1ull) && r < k;
+      // token bucket for the IOPS cap: reserve k consecutive release times; tok0 is the
+      // first one, relative to t
       uint64_t tok0 = 0;
       if (c.tok_fp) {
         if (lane() == 0) {
+          const uint64_t tn = t << TOK_FRAC;  // wraps; only differences are used
           uint64_t old = ld_rlx(c.next_tok);
           for (;;) {
-            const uint64_t tn = t << 32;
-            const uint64_t first = old > tn ? old : tn;
+            const uint64_t first = (int64_t)(old - tn) > 0 ? old : tn;
             if (cas(c.next_tok, old, first + (uint64_t)k * c.tok_fp)) {
-              tok0 = first;
+              tok0 = first - tn;
               if (profiling(c)) {
-                count(c, P_TOK_LEAD, (first - tn) >> 32);
+                count(c, P_TOK_LEAD, tok0 >> TOK_FRAC);
                 count(c, P_TOK_N, 1);
               }
               break;
@@ -508,7 +533,7 @@ __device__ void controller(const dev_ctx& c, const launch_t& li, uint32_t cw) {
         }
         uint64_t dl = t + c.lat_ticks;
         if (c.tok_fp) {
-          const uint64_t tk = (tok0 + (uint64_t)r * c.tok_fp) >> 32;
+          const uint64_t tk = t + ((tok0 + (uint64_t)r * c.tok_fp) >> TOK_FRAC);
           if (tk > dl) dl = tk;
         }
         p_deadline = dl;
@@ -594,13 +619,29 @@ __device__ void controller(const dev_ctx& c, const launch_t& li, uint32_t cw) {
     }
     if (progress) {
       idle_since = now();
+      idle_rounds = 0;
       continue;
     }
     if (!ballot(pend)) {
       if (service_should_exit(c, li)) break;
-      __builtin_amdgcn_s_sleep(2);
+      // idle: back off (about 0.1 us doubling to about 3 us) between doorbell polls
+      const uint32_t reps = idle_rounds < 5 ? (1u << idle_rounds) : 32u;
+      ++idle_rounds;
+      for (uint32_t r = 0; r < reps; ++r) __builtin_amdgcn_s_sleep(4);
     } else {
-      __builtin_amdgcn_s_sleep(1);
+      // holding commands: wait on the clock alone (no memory traffic) until the earliest
+      // deadline, at most about 2 us, then look at the doorbells again
+      uint64_t first = ~0ull;
+      if (pend && !p_copied) first = p_deadline;
+      for (uint32_t o = 32; o; o >>= 1) {
+        const uint64_t x = ((uint64_t)shfl32((uint32_t)(first >> 32), lane() ^ o) << 32) |
+                           shfl32((uint32_t)first, lane() ^ o);
+        first = x < first ? x : first;
+      }
+      first = uni64(first);
+      const uint64_t until = now() + 200;
+      const uint64_t stop = first < until ? first : until;
+      while (now() < stop) __builtin_amdgcn_s_sleep(2);
     }
     if (aborted(c)) break;
     if (now() - idle_since > c.timeout_ticks) {
@@ -620,7 +661,7 @@ __device__ void controller(const dev_ctx& c, const launch_t& li, uint32_t cw) {
 // the slot's next lap, moves its line from FETCHING to READY (or WRITEBACK to READY), and
 // sets its mask bit.  When the mask is full the window advances by 64 and the CQ head
 // doorbell is written.
-__device__ void completion(const dev_ctx& c, const launch_t& li, uint32_t w) {
+__device__ __forceinline__ void completion(const dev_ctx& c, const launch_t& li, uint32_t w) {
   const uint32_t dmask = c.depth - 1;
   const uint32_t nmy = (c.num_qp > w) ? (c.num_qp - w + li.n_cq - 1) / li.n_cq : 0;
   if (nmy == 0) return;
@@ -633,7 +674,7 @@ __device__ void completion(const dev_ctx& c, const launch_t& li, uint32_t w) {
     mask = ((uint64_t)ld_rlx(&qs->cq_mask_hi) << 32) | ld_rlx(&qs->cq_mask_lo);
   }
   uint64_t idle_since = now();
-  uint32_t loops = 0;
+  uint32_t loops = 0, idle_rounds = 0;
   for (;;) {
     if (((++loops) & 1023) == 0 && lane() == 0) count(c, C_CQ_LOOPS, 1);
     const uint64_t tl = now();
@@ -644,7 +685,11 @@ __device__ void completion(const dev_ctx& c, const launch_t& li, uint32_t w) {
       uint64_t mk = rdlane64(mask, k);
       const uint32_t pos = o + lane();
       bool fresh = false;
-      if (!((mk >> lane()) & 1ull)) {
+      // hint: nothing can be new while the controller's posting counter has not passed
+      // the entries this window already consumed
+      const uint32_t tail = uni(ld_rlx(&c.qp[q].cq_tail));
+      const uint32_t seen = o + (uint32_t)__popcll(mk);
+      if (tail != seen && !((mk >> lane()) & 1ull)) {
         cqe_t* e = c.cq + (size_t)q * c.depth + (pos & dmask);
         const uint32_t dw3 = ld_rlx(&e->dw3);
         const uint32_t expect = ((pos >> c.depth_shift) & 1u) ^ 1u;
@@ -700,10 +745,16 @@ __device__ void completion(const dev_ctx& c, const launch_t& li, uint32_t w) {
     ptick(c, any ? P_CQ_BUSY : P_CQ_IDLE, tl);
     if (any) {
       idle_since = now();
+      idle_rounds = 0;
       continue;
     }
     if (service_should_exit(c, li)) break;
-    __builtin_amdgcn_s_sleep(1);
+    {
+      // idle: back off from about 25 ns to about 0.8 us between polls
+      const uint32_t reps = idle_rounds < 5 ? (1u << idle_rounds) : 32u;
+      ++idle_rounds;
+      for (uint32_t r = 0; r < reps; ++r) __builtin_amdgcn_s_sleep(1);
+    }
     if (now() - idle_since > 4 * c.timeout_ticks) {
       raise_error(c, E_TIMEDOUT, 0xC2000000ull | w);
       break;
@@ -716,7 +767,7 @@ __device__ void completion(const dev_ctx& c, const launch_t& li, uint32_t w) {
   }
 }
 
-__device__ void run_service(const dev_ctx& c, const launch_t& li) {
+__device__ __forceinline__ void run_service(const dev_ctx& c, const launch_t& li) {
   const uint32_t sw = blockIdx.x * WPB + threadIdx.x / 64;
   if (li.prio) __builtin_amdgcn_s_setprio(3);
   if (lane() == 0 && sw < li.n_ctrl + li.n_cq) count(c, C_SVC_START, 1);
@@ -793,7 +844,7 @@ __device__ __forceinline__ int probe_set(const dev_ctx& c, uint32_t base, uint32
 // `cnt` == 0 asks for an unpinned hit: a resident or in-flight line is reported with its
 // generation and not pinned (the caller validates after reading); a miss still pins its
 // claim with one reference.
-__device__ acq_t acquire_try(const dev_ctx& c, uint32_t line_id, uint32_t cnt, int retake) {
+__device__ __forceinline__ acq_t acquire_try(const dev_ctx& c, uint32_t line_id, uint32_t cnt, int retake) {
   acq_t r{A_NONE, 0, 0};
   const uint32_t set = set_of(c, line_id);
   const uint32_t base = set * c.assoc;
@@ -945,7 +996,7 @@ __device__ __forceinline__ void dedup(chunk_t& ch) {
 
 // Acquire + submit for the leaders of `ch`.  On return every active lane has st in
 // {A_HIT, A_JOIN, A_MISS, A_EAGAIN} (or the context aborted).  Counts stats.
-__device__ bool chunk_issue(const dev_ctx& c, chunk_t& ch, uint32_t q, bool count_stats,
+__device__ __forceinline__ bool chunk_issue(const dev_ctx& c, chunk_t& ch, uint32_t q, bool count_stats,
                             uint32_t pin_mode = PIN_LINE) {
   const uint64_t t_issue = now();
   dedup(ch);
@@ -1036,9 +1087,10 @@ __device__ bool chunk_issue(const dev_ctx& c, chunk_t& ch, uint32_t q, bool coun
 // still carries its tag and generation in the FETCHING state.  With `acquire`, one
 // acquire fence follows (plain loads of the line data are then safe); without it the
 // caller reads the data with device-coherent loads.
-__device__ bool chunk_wait(const dev_ctx& c, const chunk_t& ch, bool acquire = true) {
+__device__ __forceinline__ bool chunk_wait(const dev_ctx& c, const chunk_t& ch, bool acquire = true) {
   const uint64_t t_wait = now();
-  bool waiting = ch.act && (ch.st == A_JOIN || ch.st == A_MISS);
+  // one poller per distinct line (the dedup leader); followers share its line
+  bool waiting = ch.act && ch.leader == lane() && (ch.st == A_JOIN || ch.st == A_MISS);
   spin_t sp;
   while (true) {
     if (waiting) {

@@ -1,0 +1,110 @@
+"""Autotuner for the block-I/O path's geometry.
+
+Staged coordinate descent over line size, associativity, queue-pair count, queue depth and
+the number of emulated-controller wavefronts.  Each trial builds a context with the candidate
+geometry over the same store, runs a short closed-loop serving session (every request
+available at once, so the session measures sustainable throughput) and scores it in
+lookups per second.  Points the library rejects (for example fewer lines than ways) are
+skipped.  The result is a JSON-serialisable dict: the chosen geometry and every trial.
+"""
+from __future__ import annotations
+
+import json
+import time
+
+import numpy as np
+
+from . import agile, gen
+
+SPACE = {
+    "line_bytes": [4096, 8192, 16384, 32768, 65536],
+    "assoc": [4, 8, 16, 32],
+    "num_qp": [4, 8, 16, 32, 64],
+    "qp_depth": [256, 512, 1024, 2048, 4096],
+    "ctrl_waves": [16, 32, 64, 128],
+}
+START = {"line_bytes": 4096, "assoc": 8, "num_qp": 16, "qp_depth": 1024, "ctrl_waves": 64}
+
+
+def _config(point: dict, cache_bytes: int, latency_ns: int, iops_cap: int) -> dict:
+    return dict(cache_bytes=cache_bytes, line_bytes=point["line_bytes"], assoc=point["assoc"],
+                num_qp=point["num_qp"], qp_depth=point["qp_depth"],
+                ctrl_waves=point["ctrl_waves"], latency_ns=latency_ns,
+                iops_cap=iops_cap, timeout_ns=int(20e9))
+
+
+def feasible(point: dict, cache_bytes: int) -> bool:
+    lines = cache_bytes // point["line_bytes"]
+    return lines >= point["assoc"] and lines % point["assoc"] == 0
+
+
+def serve_trial(image, rows: int, dim: int, point: dict, stream, cache_bytes: int, K: int = 0,
+                latency_ns: int = 0, iops_cap: int = 0, mode: int = agile.MODE_ASYNC) -> dict:
+    """One closed-loop serving session; returns lookups/s and latency percentiles."""
+    arrival, req_bag0, bag_off, idx = stream
+    ctx = agile.Context(**_config(point, cache_bytes, latency_ns, iops_cap))
+    try:
+        ctx.open_store(image)
+        tb = ctx.tables(rows, dim, 1)
+        _, lat, rep = ctx.serve(tb, K, np.zeros_like(arrival), req_bag0, bag_off, idx, mode=mode)
+        ctx.close_store()
+    finally:
+        ctx.shutdown()
+    return {"lookups_per_s": rep["lookups"] / rep["elapsed_s"], "p50_s": float(np.median(lat)),
+            "p99_s": float(np.percentile(lat, 99)), "elapsed_s": rep["elapsed_s"]}
+
+
+def tune(image, rows: int, dim: int, cache_bytes: int = 1 << 20, requests: int = 2000,
+         seed: int = 40, rounds: int = 2, K: int = 0, latency_ns: int = 0, iops_cap: int = 0,
+         space: dict | None = None, start: dict | None = None, log=print) -> dict:
+    space = space or SPACE
+    point = dict(start or START)
+    stream = gen.serve_stream(requests, 20000.0, rows, 1.05, seed)
+    trials = []
+    cache = {}
+
+    def score(p):
+        key = tuple(sorted(p.items()))
+        if key in cache:
+            return cache[key]
+        if not feasible(p, cache_bytes):
+            cache[key] = None
+            return None
+        t0 = time.perf_counter()
+        try:
+            r = serve_trial(image, rows, dim, p, stream, cache_bytes, K, latency_ns, iops_cap)
+        except agile.AgileError as e:  # rejected configuration
+            log(f"  skip {p}: {e}")
+            cache[key] = None
+            return None
+        r["trial_s"] = time.perf_counter() - t0
+        trials.append({"point": dict(p), **r})
+        log(f"  {p} -> {r['lookups_per_s'] / 1e6:.3f} M lookups/s p99 {r['p99_s'] * 1e3:.2f} ms")
+        cache[key] = r["lookups_per_s"]
+        return cache[key]
+
+    best = score(point)
+    for _ in range(rounds):
+        improved = False
+        for axis, values in space.items():
+            for v in values:
+                if v == point[axis]:
+                    continue
+                cand = dict(point)
+                cand[axis] = v
+                sc = score(cand)
+                if sc is not None and (best is None or sc > best * 1.02):
+                    best, point, improved = sc, cand, True
+        if not improved:
+            break
+    return {"best": point, "best_lookups_per_s": best, "trials": trials,
+            "cache_bytes": cache_bytes}
+
+
+if __name__ == "__main__":
+    import sys
+    rows, dim = 65536, 64
+    buf = agile.PinnedBuffer(rows * dim * 4)
+    gen.fill_table(buf.ptr, 0, rows, dim, 0)
+    res = tune(buf, rows, dim, requests=int(sys.argv[1]) if len(sys.argv) > 1 else 2000)
+    print(json.dumps({k: v for k, v in res.items() if k != "trials"}))

@@ -280,3 +280,15 @@ def test_protocol_model_naive_deadlocks_as_in_fig1():
     # with enough room for everyone the naive design completes
     n, dead = pm.explore("naive", 4, (2, 2))
     assert dead is None
+
+
+@pytest.mark.parametrize("controllers,total", [(2, 4), (3, 5)])
+def test_protocol_model_shared_fetch_reads_fetch_pointer_first(controllers, total):
+    # several controller wavefronts claim runs of one SQ with a compare-and-swap on its
+    # fetch pointer; a doorbell read before the fetch pointer can be stale by then
+    n, bad = pm.explore_fetch("db_first", controllers=controllers, total=total)
+    assert bad is not None
+    for order, guard in (("fetch_first", False), ("fetch_first", True), ("db_first", True)):
+        n, bad = pm.explore_fetch(order, controllers=controllers, total=total, guard=guard)
+        assert bad is None, (order, guard, bad)
+        assert n > 100
