@@ -101,7 +101,7 @@ __device__ __forceinline__ void write_bag(const dev_ctx& c, const embbag_args& a
 // Serving: waits until request r is published (the device mirror holds the count).
 // Returns false when the session is stopped or aborted.  No device deadline: requests
 // may arrive seconds apart; the host watchdog bounds the session.
-__device__ bool wait_published(const dev_ctx& c, const embbag_args& a, uint32_t r) {
+__device__ __forceinline__ bool wait_published(const dev_ctx& c, const embbag_args& a, uint32_t r) {
   uint32_t n = 0;
   while (uni(ld_rlx(a.pub_dev)) <= r) {
     if ((++n & 63) == 0) {
@@ -215,10 +215,78 @@ __device__ __forceinline__ void ld_row(const float* p, float (&v)[VPL]) {
   }
 }
 
-// Consumes rows of the chunk in order, eight rows' loads in flight at a time, until the
-// first row whose lane has no line or (with `validate`) whose unpinned line changed
-// tenant while it was read (seqlock-style: the metadata is re-read after the data loads
-// have completed).  Returns the number of rows consumed.
+// Rows per round of the consume loop (two rounds of row values are live at once).
+template <int VPL>
+constexpr uint32_t rows_per_round() { return VPL >= 4 ? 4u : 8u; }
+
+// Loads rows [j, j + g) of the chunk (g <= R) into v; lanes past the row width read 0.
+template <int VPL>
+__device__ __forceinline__ void load_rows(const dev_ctx& c, const chunk_t& ch, uint32_t j, uint32_t g,
+                                          uint32_t d0, bool mine, float (&v)[rows_per_round<VPL>()][VPL]) {
+#pragma unroll
+  for (uint32_t u = 0; u < rows_per_round<VPL>(); ++u) {
+    if (u < g) {
+      const uint32_t idx = rdlane(ch.idx, j + u);
+      const uint32_t off = rdlane(ch.off, j + u);
+      const float* p = reinterpret_cast<const float*>(line_ptr(c, idx) + off) + d0;
+      if (mine) {
+        ld_row<VPL>(p, v[u]);
+      } else {
+#pragma unroll
+        for (int e = 0; e < VPL; ++e) v[u][e] = 0.0f;
+      }
+    }
+  }
+}
+
+template <int VPL>
+__device__ __forceinline__ void use_rows(const embbag_args& a, const desc_t& d, uint32_t j, uint32_t good,
+                                         uint32_t d0, bool mine, const float (&v)[rows_per_round<VPL>()][VPL],
+                                         float (&acc)[VPL]) {
+#pragma unroll
+  for (uint32_t u = 0; u < rows_per_round<VPL>(); ++u) {
+    if (u < good && mine) {
+      if (a.gather) {
+        float* o = a.out + (uint64_t)(d.j + j + u) * a.dim + d0;
+#pragma unroll
+        for (int e = 0; e < VPL; ++e) o[e] = v[u][e];
+      } else {
+#pragma unroll
+        for (int e = 0; e < VPL; ++e) acc[e] = acc[e] + fK(v[u][e], a.K);
+      }
+    }
+  }
+}
+
+// Seqlock check of rows [j, j + g) of the chunk, issued only once the loads in `v` have
+// returned: lane u re-reads the metadata of row j + u (unless the chunk pins it).  Returns
+// the number of leading rows that are still valid.
+template <int VPL>
+__device__ __forceinline__ uint32_t validate_rows(const dev_ctx& c, const chunk_t& ch, uint32_t j, uint32_t g,
+                                                  const float (&v)[rows_per_round<VPL>()][VPL]) {
+  uint32_t dep = 0;
+#pragma unroll
+  for (uint32_t u = 0; u < rows_per_round<VPL>(); ++u)
+    if (u < g) dep ^= __float_as_uint(v[u][0]);
+  const uint32_t r = (j + lane()) & 63;
+  uint32_t ridx = shfl32(ch.idx, r);
+  const uint32_t rtag = shfl32(ch.line_id, r);
+  const uint32_t rgen = shfl32(ch.gen, r);
+  const uint32_t rpin = shfl32(ch.pinned ? 1u : 0u, r);
+  // the metadata address depends on every row value of the round, so these loads are
+  // issued after the row loads have completed (the seqlock order), and not before
+  asm volatile("" : "+v"(ridx) : "v"(dep));
+  bool bad = false;
+  if (lane() < g && !rpin) bad = !line_still_valid(c, ridx, rtag, rgen);
+  const uint64_t bm = ballot(bad);
+  return bm ? ffs64(bm) : g;
+}
+
+// Consumes rows of the chunk in order until the first row whose lane has no line or
+// (with `validate`) whose unpinned line changed tenant while it was read.  Returns the
+// number of rows consumed.  Rows go in rounds; with validation the rounds are
+// software-pipelined: the next round's row loads are in flight together with this
+// round's metadata re-reads, so each round costs one memory round trip.
 template <int VPL>
 __device__ __forceinline__ uint32_t consume(const dev_ctx& c, const embbag_args& a, const desc_t& d,
                             const chunk_t& ch, float (&acc)[VPL], bool validate) {
@@ -227,45 +295,39 @@ __device__ __forceinline__ uint32_t consume(const dev_ctx& c, const embbag_args&
   const uint32_t n = nok < d.n ? nok : d.n;
   const uint32_t d0 = lane() * VPL;
   const bool mine = d0 < a.dim;
-  for (uint32_t j = 0; j < n; j += 8) {
-    const uint32_t g = (n - j) < 8 ? (n - j) : 8;
-    float v[8][VPL];
-#pragma unroll
-    for (uint32_t u = 0; u < 8; ++u) {
-      if (u < g) {
-        const uint32_t idx = rdlane(ch.idx, j + u);
-        const uint32_t off = rdlane(ch.off, j + u);
-        const float* p = reinterpret_cast<const float*>(line_ptr(c, idx) + off) + d0;
-        if (mine) ld_row<VPL>(p, v[u]);
-      }
+  constexpr uint32_t R = rows_per_round<VPL>();
+  if (!validate) {
+    for (uint32_t j = 0; j < n; j += R) {
+      const uint32_t g = (n - j) < R ? (n - j) : R;
+      float v[R][VPL];
+      load_rows<VPL>(c, ch, j, g, d0, mine, v);
+      use_rows<VPL>(a, d, j, g, d0, mine, v, acc);
     }
-    uint32_t good = g;
-    if (validate) {
-      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");  // data loads have completed
-      const uint32_t r = (j + lane()) & 63;
-      const uint32_t ridx = shfl32(ch.idx, r);
-      const uint32_t rtag = shfl32(ch.line_id, r);
-      const uint32_t rgen = shfl32(ch.gen, r);
-      const uint32_t rpin = shfl32(ch.pinned ? 1u : 0u, r);
-      bool bad = false;
-      if (lane() < g && !rpin) bad = !line_still_valid(c, ridx, rtag, rgen);
-      const uint64_t bm = ballot(bad);
-      if (bm) good = ffs64(bm);
-    }
-#pragma unroll
-    for (uint32_t u = 0; u < 8; ++u) {
-      if (u < good && mine) {
-        if (a.gather) {
-          float* o = a.out + (uint64_t)(d.j + j + u) * a.dim + d0;
-#pragma unroll
-          for (int e = 0; e < VPL; ++e) o[e] = v[u][e];
-        } else {
-#pragma unroll
-          for (int e = 0; e < VPL; ++e) acc[e] = acc[e] + fK(v[u][e], a.K);
-        }
-      }
-    }
+    return n;
+  }
+  float va[R][VPL], vb[R][VPL];
+  uint32_t j = 0;
+  if (n) load_rows<VPL>(c, ch, 0, n < R ? n : R, d0, mine, va);
+  while (j < n) {
+    // round in va, next round into vb
+    uint32_t g = (n - j) < R ? (n - j) : R;
+    uint32_t jn = j + g;
+    uint32_t gn = jn < n ? ((n - jn) < R ? (n - jn) : R) : 0;
+    if (gn) load_rows<VPL>(c, ch, jn, gn, d0, mine, vb);
+    uint32_t good = validate_rows<VPL>(c, ch, j, g, va);
+    use_rows<VPL>(a, d, j, good, d0, mine, va, acc);
     if (good < g) return j + good;
+    j = jn;
+    if (j >= n) break;
+    // round in vb, next round into va
+    g = gn;
+    jn = j + g;
+    gn = jn < n ? ((n - jn) < R ? (n - jn) : R) : 0;
+    if (gn) load_rows<VPL>(c, ch, jn, gn, d0, mine, va);
+    good = validate_rows<VPL>(c, ch, j, g, vb);
+    use_rows<VPL>(a, d, j, good, d0, mine, vb, acc);
+    if (good < g) return j + good;
+    j = jn;
   }
   return n;
 }
@@ -304,7 +366,7 @@ __device__ __forceinline__ void embbag_wave(const dev_ctx& c, const launch_t& li
     const uint32_t k = consume<VPL>(c, a, dc, cc, acc, true);
     chunk_release(c, cc, false);
     ptick(c, P_U_CONSUME, t_cons);
-    if (lane() == 0) count(c, C_AUX1, k);
+    if (lane() == 0) wcount(WS_AUX1, k);
     if (k < dc.n) {
       // EAGAIN: drop every pin this wave holds (including the prefetched chunk), then
       // drain the rest of the chunk one row at a time, acquiring each row while holding
@@ -329,7 +391,7 @@ __device__ __forceinline__ void embbag_wave(const dev_ctx& c, const launch_t& li
         if (!chunk_wait(c, cc, false)) return;
         consume<VPL>(c, a, one, cc, acc, false);
         chunk_release(c, cc, false);
-        if (lane() == 0) count(c, C_AUX1, 1);
+        if (lane() == 0) wcount(WS_AUX1, 1);
         dc.j += 1;
         dc.n -= 1;
       }
@@ -354,7 +416,7 @@ __device__ __forceinline__ void embbag_wave(const dev_ctx& c, const launch_t& li
 // Serialized mode: lane 0 of a single wave handles one lookup at a time in program order
 // (issue, wait, compute, release), so the cache sees exactly the request sequence.
 template <int VPL>
-__device__ void embbag_serial(const dev_ctx& c, const launch_t& li, const embbag_args& a) {
+__device__ __forceinline__ void embbag_serial(const dev_ctx& c, const launch_t& li, const embbag_args& a) {
   float acc[VPL];
   const uint64_t nb = a.nbags;
   for (uint64_t g = 0; g < nb; ++g) {
@@ -379,7 +441,7 @@ __device__ void embbag_serial(const dev_ctx& c, const launch_t& li, const embbag
         const uint32_t k = consume<VPL>(c, a, d, ch, acc, false);
         chunk_release(c, ch, false);
         if (k == 1) {
-          if (lane() == 0) count(c, C_AUX1, 1);
+          if (lane() == 0) wcount(WS_AUX1, 1);
           break;
         }
         if (!sp.step(c, 0xF1000000ull)) return;
@@ -395,6 +457,7 @@ __global__ __launch_bounds__(WG) void k_embbag(dev_ctx c, launch_t li, embbag_ar
     run_service(c, li);
     return;
   }
+  user_wave_begin();
   const uint32_t uw = (blockIdx.x - li.service_blocks) * WPB + threadIdx.x / 64;
   if (c.flags & AGILE_F_SERIALIZED) {
     if (uw == 0) embbag_serial<VPL>(c, li, a);
@@ -408,7 +471,7 @@ __global__ __launch_bounds__(WG) void k_embbag(dev_ctx c, launch_t li, embbag_ar
 // service wavefront mirrors the host's count of published requests, its stop flag and
 // its abort flag into device memory, so that waiting waves poll HBM instead of sending
 // PCIe reads.
-__device__ void mirror_published(const dev_ctx& c, const embbag_args& a, uint32_t nreq, uint32_t* pub_dev) {
+__device__ __forceinline__ void mirror_published(const dev_ctx& c, const embbag_args& a, uint32_t nreq, uint32_t* pub_dev) {
   uint32_t last = 0;
   for (;;) {
     const uint32_t v = uni(__hip_atomic_load(a.pub_host, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM));
@@ -437,6 +500,7 @@ __global__ __launch_bounds__(WG) void k_serve(dev_ctx c, launch_t li, embbag_arg
     run_service(c, li);
     return;
   }
+  user_wave_begin();
   const uint32_t uw = (blockIdx.x - li.service_blocks) * WPB + threadIdx.x / 64;
   if (uw < a.active_waves) embbag_wave<VPL>(c, li, a, uw);
   user_wave_done(c);
@@ -449,6 +513,7 @@ __global__ __launch_bounds__(WG) void k_async_read(dev_ctx c, launch_t li, const
     run_service(c, li);
     return;
   }
+  user_wave_begin();
   const uint32_t uw = (blockIdx.x - li.service_blocks) * WPB + threadIdx.x / 64;
   const uint32_t q = uw % c.num_qp;
   for (uint64_t base = (uint64_t)uw * 64; base < n; base += (uint64_t)li.user_waves * 64) {
@@ -477,6 +542,7 @@ __global__ __launch_bounds__(WG) void k_async_read(dev_ctx c, launch_t li, const
 
 __global__ __launch_bounds__(WG) void k_wait(dev_ctx c, launch_t li, const agile_ticket* tickets,
                                              uint32_t n, void** ptrs) {
+  user_wave_begin();
   const uint32_t uw = blockIdx.x * WPB + threadIdx.x / 64;
   const uint64_t i = (uint64_t)uw * 64 + lane();
   bool waiting = false;
@@ -521,6 +587,7 @@ __global__ __launch_bounds__(WG) void k_wait(dev_ctx c, launch_t li, const agile
 
 __global__ __launch_bounds__(WG) void k_release(dev_ctx c, launch_t li, const agile_ticket* tickets,
                                                 uint32_t n) {
+  user_wave_begin();
   const uint32_t uw = blockIdx.x * WPB + threadIdx.x / 64;
   const uint64_t i = (uint64_t)uw * 64 + lane();
   if (i < n) {
@@ -538,6 +605,7 @@ __global__ __launch_bounds__(WG) void k_flush(dev_ctx c, launch_t li) {
     run_service(c, li);
     return;
   }
+  user_wave_begin();
   const uint32_t uw = (blockIdx.x - li.service_blocks) * WPB + threadIdx.x / 64;
   const uint32_t q = uw % c.num_qp;
   for (uint64_t base = (uint64_t)uw * 64; base < c.num_lines; base += (uint64_t)li.user_waves * 64) {
@@ -567,6 +635,7 @@ __global__ __launch_bounds__(WG) void k_flush(dev_ctx c, launch_t li) {
 }
 
 __global__ __launch_bounds__(WG) void k_invalidate(dev_ctx c, launch_t li) {
+  user_wave_begin();
   const uint32_t uw = blockIdx.x * WPB + threadIdx.x / 64;
   const uint64_t i = (uint64_t)uw * 64 + lane();
   if (i < c.num_lines) {
@@ -592,6 +661,7 @@ __global__ __launch_bounds__(WG) void k_trace(dev_ctx c, launch_t li, const uint
     run_service(c, li);
     return;
   }
+  user_wave_begin();
   const uint32_t uw = (blockIdx.x - li.service_blocks) * WPB + threadIdx.x / 64;
   if (uw == 0) {
     for (uint64_t i = 0; i < n; ++i) {
@@ -663,7 +733,7 @@ __global__ void k_bwd_heads(bwd_args a) {
 // unpins it with release ordering.  A MODIFIED line is written back when the clock evicts
 // it or at flush (Sec. 3.4, case d).
 template <int VPL>
-__device__ void bwd_wave(const dev_ctx& c, const bwd_args& a, uint32_t uw) {
+__device__ __forceinline__ void bwd_wave(const dev_ctx& c, const bwd_args& a, uint32_t uw) {
   const uint32_t q = uw % c.num_qp;
   const uint32_t nheads = ld_rlx(a.ctr);
   const uint32_t d0 = lane() * VPL;
@@ -741,7 +811,7 @@ __device__ void bwd_wave(const dev_ctx& c, const bwd_args& a, uint32_t uw) {
           if (cas(c.meta + ch.idx, mv, mv + 1ull)) break;  // READY -> DIRTY
         }
       }
-      if (lane() == 0) count(c, C_WROWS, __popcll(okm));
+      if (lane() == 0) wcount(WS_WROWS, __popcll(okm));
       chunk_release(c, ch, true);
       if (okm && ((okm >> lane()) & 1ull)) todo = false;
       if (ballot(todo) && !okm) {
@@ -757,6 +827,7 @@ __global__ __launch_bounds__(WG) void k_bwd_sgd(dev_ctx c, launch_t li, bwd_args
     run_service(c, li);
     return;
   }
+  user_wave_begin();
   const uint32_t uw = (blockIdx.x - li.service_blocks) * WPB + threadIdx.x / 64;
   bwd_wave<VPL>(c, a, uw);
   user_wave_done(c);
@@ -772,7 +843,7 @@ struct csr_t {
 // line's tag and generation are re-checked after the load.  Lanes whose line changed, or
 // whose set had no evictable way, retry while holding nothing.
 template <typename T>
-__device__ bool cached_read(const dev_ctx& c, uint32_t q, bool act, uint64_t byte, T& out) {
+__device__ __forceinline__ bool cached_read(const dev_ctx& c, uint32_t q, bool act, uint64_t byte, T& out) {
   bool todo = act;
   spin_t sp;
   while (ballot(todo)) {
@@ -822,6 +893,7 @@ __global__ __launch_bounds__(WG) void k_bfs_front(dev_ctx c, launch_t li, bfs_ar
     run_service(c, li);
     return;
   }
+  user_wave_begin();
   const uint32_t uw = (blockIdx.x - li.service_blocks) * WPB + threadIdx.x / 64;
   const uint32_t q = uw % c.num_qp;
   for (uint64_t base = (uint64_t)uw * 64; base < a.nF; base += (uint64_t)li.user_waves * 64) {
@@ -852,6 +924,7 @@ __global__ __launch_bounds__(WG) void k_bfs_edges(dev_ctx c, launch_t li, bfs_ar
     run_service(c, li);
     return;
   }
+  user_wave_begin();
   const uint32_t uw = (blockIdx.x - li.service_blocks) * WPB + threadIdx.x / 64;
   const uint32_t q = uw % c.num_qp;
   for (;;) {
@@ -935,6 +1008,7 @@ __global__ __launch_bounds__(WG) void k_spmv(dev_ctx c, launch_t li, spmv_args a
     run_service(c, li);
     return;
   }
+  user_wave_begin();
   const uint32_t wv = threadIdx.x / 64;
   const uint32_t uw = (blockIdx.x - li.service_blocks) * WPB + wv;
   const uint32_t q = uw % c.num_qp;
@@ -1329,6 +1403,11 @@ agile_status agile_init(const agile_config* cfg_in, agile_ctx* out) {
   d.depth_shift = log2u(cfg.qp_depth);
   d.lat_ticks = (uint64_t)((double)cfg.latency_ns * 1e-9 * (double)ctx->clock_hz + 0.5);
   d.tok_fp = cfg.iops_cap ? (uint64_t)((double)ctx->clock_hz / (double)cfg.iops_cap * (double)(1ull << TOK_FRAC)) : 0;
+  {
+    // every command that can be queued or held by a controller lane, one period each
+    const double lim = ((double)cfg.num_qp * cfg.qp_depth + 64.0 * n_ctrl) * (double)d.tok_fp;
+    d.tok_max = lim < 4.0e18 ? (uint64_t)lim : 4000000000000000000ull;
+  }
   d.timeout_ticks = (uint64_t)((double)cfg.timeout_ns * 1e-9 * (double)ctx->clock_hz);
   d.flags = cfg.flags;
 

@@ -179,6 +179,7 @@ struct dev_ctx {
   // emulator
   uint64_t lat_ticks;
   uint64_t tok_fp;  // ticks per command in TOK_FRAC-bit fixed point; 0 = no cap
+  uint64_t tok_max; // largest lead a reservation can legitimately have (same units)
   uint64_t* next_tok;
   // control
   uint64_t* cnt;
@@ -208,8 +209,10 @@ struct launch_t {
 constexpr uint32_t WG = 1024;
 constexpr uint32_t FLAG_PROFILE = 0x4;
 // Token times of the IOPS cap are kept in 44.20 fixed point of the wall clock, modulo
-// 2^64: the 44-bit integer part wraps after about two days of 100 MHz ticks, so they are
-// only ever compared through signed differences.
+// 2^64: the integer part wraps after about two days of 100 MHz ticks, so a stored token
+// time is only used through its difference to now, and only while that lead is positive
+// and no larger than the queues can account for (an idle or never-used bucket can sit at
+// any distance, with either sign).
 constexpr uint32_t TOK_FRAC = 20;
 constexpr uint32_t WPB = WG / 64;
 
@@ -238,11 +241,17 @@ __device__ __forceinline__ bool host_abort_poll(const dev_ctx& c) {
   if (lane() == 0) st_rlx(c.abort_dev, 1u);
   return true;
 }
-__device__ __noinline__ void raise_error(const dev_ctx& c, uint32_t code, uint64_t info) {
+// Kept out of line (a cold path) with plain pointer arguments: a reference to the whole
+// context would force the kernel to keep a copy of it in scratch memory.
+__device__ __noinline__ void raise_error_at(uint32_t* err, uint64_t* err_info, uint32_t* abort_dev,
+                                            uint32_t* abort_flag, uint32_t code, uint64_t info) {
   uint32_t z = 0;
-  if (cas(c.err, z, code)) st_rlx(c.err_info, info);
-  st_rlx(c.abort_dev, 1u);
-  __hip_atomic_store(c.abort_flag, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+  if (cas(err, z, code)) st_rlx(err_info, info);
+  st_rlx(abort_dev, 1u);
+  __hip_atomic_store(abort_flag, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+__device__ __forceinline__ void raise_error(const dev_ctx& c, uint32_t code, uint64_t info) {
+  raise_error_at(c.err, c.err_info, c.abort_dev, c.abort_flag, code, info);
 }
 
 // Bounded spin helper: returns false (and raises E_TIMEDOUT) when the deadline passes or
@@ -386,31 +395,41 @@ __device__ __forceinline__ uint64_t shfl64(uint64_t v, uint32_t src) {
 // Copies one 4 KiB block with the whole wave: 16-byte lanes, 1 KiB per instruction, so
 // that each instruction touches a single page of the pinned image.  `nb` (1..4) blocks
 // are copied together with all their loads issued before the stores.
-__device__ __forceinline__ void copy_blocks(uint8_t* const* dst, const uint8_t* const* src, uint32_t nb) {
-  uint4 v[4][4];
-#pragma unroll
-  for (uint32_t b = 0; b < 4; ++b)
-    if (b < nb) {
-      const uint4* s = reinterpret_cast<const uint4*>(src[b]);
-#pragma unroll
-      for (uint32_t i = 0; i < 4; ++i) v[b][i] = s[i * 64 + lane()];
-    }
-#pragma unroll
-  for (uint32_t b = 0; b < 4; ++b)
-    if (b < nb) {
-      uint4* d = reinterpret_cast<uint4*>(dst[b]);
-#pragma unroll
-      for (uint32_t i = 0; i < 4; ++i) d[i * 64 + lane()] = v[b][i];
-    }
-}
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(1))) u32x4 gmem_u32x4;
 
-// Copies the blocks of the commands in `ready`, up to four 4 KiB blocks in flight per
-// wave (the store-side memory-level parallelism comes from the number of controller
-// wavefronts).
+// Copies NB 4 KiB blocks with one wavefront: every lane moves 16 bytes of each quarter of
+// each block, all NB * 4 loads in flight before the first store (PCIe reads are latency-
+// bound, so bytes in flight per wave set the copy rate).
+template <uint32_t NB>
+__device__ __forceinline__ void copy_n(uint8_t* const (&dst)[4], const uint8_t* const (&src)[4]) {
+  u32x4 v[NB][4];
+#pragma unroll
+  for (uint32_t b = 0; b < NB; ++b) {
+    const gmem_u32x4* s = (const gmem_u32x4*)src[b];
+#pragma unroll
+    for (uint32_t i = 0; i < 4; ++i) v[b][i] = s[i * 64 + lane()];
+  }
+#pragma unroll
+  for (uint32_t b = 0; b < NB; ++b) {
+    gmem_u32x4* d = (gmem_u32x4*)dst[b];
+#pragma unroll
+    for (uint32_t i = 0; i < 4; ++i) d[i * 64 + lane()] = v[b][i];
+  }
+}
+__device__ __forceinline__ void copy_blocks(uint8_t* const (&dst)[4], const uint8_t* const (&src)[4], uint32_t nb) {
+  switch (nb) {
+    case 1: copy_n<1>(dst, src); break;
+    case 2: copy_n<2>(dst, src); break;
+    case 3: copy_n<3>(dst, src); break;
+    default: copy_n<4>(dst, src); break;
+  }
+}
 __device__ __forceinline__ void copy_cmds(const dev_ctx& c, uint64_t ready, uint32_t p_opc, uint32_t p_nblk,
                           uint32_t p_status, uint64_t p_slba, uint64_t p_prp) {
-  uint8_t* dst[4];
-  const uint8_t* src[4];
+  // the block pointers are written at constant indices only, so they stay in registers
+  uint8_t* dst[4] = {nullptr, nullptr, nullptr, nullptr};
+  const uint8_t* src[4] = {nullptr, nullptr, nullptr, nullptr};
   uint32_t k = 0;
   for (uint64_t rem = ready; rem; rem &= rem - 1) {
     const uint32_t l = ffs64(rem);
@@ -421,8 +440,12 @@ __device__ __forceinline__ void copy_cmds(const dev_ctx& c, uint64_t ready, uint
     uint8_t* img = c.image + (rdlane64(p_slba, l) << 12);
     for (uint32_t b = 0; b < nblk; ++b) {
       const uint64_t o = (uint64_t)b << 12;
-      src[k] = rd ? img + o : hbm + o;
-      dst[k] = rd ? hbm + o : img + o;
+#pragma unroll
+      for (uint32_t i = 0; i < 4; ++i)
+        if (i == k) {
+          src[i] = rd ? img + o : hbm + o;
+          dst[i] = rd ? hbm + o : img + o;
+        }
       if (++k == 4) {
         copy_blocks(dst, src, 4);
         k = 0;
@@ -494,7 +517,10 @@ __device__ __forceinline__ void controller(const dev_ctx& c, const launch_t& li,
           const uint64_t tn = t << TOK_FRAC;  // wraps; only differences are used
           uint64_t old = ld_rlx(c.next_tok);
           for (;;) {
-            const uint64_t first = (int64_t)(old - tn) > 0 ? old : tn;
+            // a lead beyond what every queued command could account for is a bucket
+            // that went idle (or was never used): it restarts at now
+            const uint64_t lead = old - tn;
+            const uint64_t first = ((int64_t)lead > 0 && lead <= c.tok_max) ? old : tn;
             if (cas(c.next_tok, old, first + (uint64_t)k * c.tok_fp)) {
               tok0 = first - tn;
               if (profiling(c)) {
@@ -777,8 +803,33 @@ __device__ __forceinline__ void run_service(const dev_ctx& c, const launch_t& li
     completion(c, li, sw - li.n_ctrl);
 }
 
+// Per-wavefront statistics.  The counters that user waves bump on every chunk are summed
+// in the wave's own LDS slots and added to the device counters once, when the wave ends:
+// thousands of waves adding to a handful of device-scope addresses would serialise there.
+enum : uint32_t { WS_REQUESTS = 0, WS_HITS, WS_MISSES, WS_EAGAIN, WS_AUX1, WS_WROWS, WS_COUNT };
+__device__ __forceinline__ uint32_t ws_counter(uint32_t k) {
+  return k == WS_REQUESTS ? C_REQUESTS : k == WS_HITS ? C_HITS : k == WS_MISSES ? C_MISSES
+       : k == WS_EAGAIN ? C_EAGAIN : k == WS_AUX1 ? C_AUX1 : C_WROWS;
+}
+__device__ __forceinline__ uint64_t* wave_stats() {
+  __shared__ uint64_t ws[WPB][WS_COUNT];
+  return ws[threadIdx.x / 64];
+}
+// Called by every user wavefront before its first chunk.
+__device__ __forceinline__ void user_wave_begin() {
+  if (lane() < WS_COUNT) wave_stats()[lane()] = 0;
+}
+// Lane 0 only.
+__device__ __forceinline__ void wcount(uint32_t k, uint64_t v) {
+  if (v) wave_stats()[k] += v;
+}
+
 // Called by every user wavefront when it is done with this launch.
 __device__ __forceinline__ void user_wave_done(const dev_ctx& c) {
+  if (lane() < WS_COUNT) {
+    const uint64_t v = wave_stats()[lane()];
+    if (v) add_rlx(counter(c, ws_counter(lane())), v);
+  }
   if (lane() == 0) add_rel(counter(c, C_USER_DONE), 1ull);
 }
 
@@ -1074,10 +1125,10 @@ __device__ __forceinline__ bool chunk_issue(const dev_ctx& c, chunk_t& ch, uint3
     const uint64_t nmiss = __popcll(ballot(ch.act && ch.st == A_MISS));
     const uint64_t nea = __popcll(ballot(lead && st == A_EAGAIN));
     if (lane() == 0) {
-      count(c, C_REQUESTS, nreq);
-      count(c, C_MISSES, nmiss);
-      count(c, C_HITS, nreq - nmiss);
-      count(c, C_EAGAIN, nea);
+      wcount(WS_REQUESTS, nreq);
+      wcount(WS_MISSES, nmiss);
+      wcount(WS_HITS, nreq - nmiss);
+      wcount(WS_EAGAIN, nea);
     }
   }
   return true;
