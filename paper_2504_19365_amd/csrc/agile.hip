@@ -48,12 +48,27 @@ struct embbag_args {
   uint32_t* done;             // pinned: done[r] = 1 once request r's outputs are visible
 };
 
-// Per-wave state of the bag source: a bag grabbed before its request was published is
-// kept for later; after the first failed grab the wave grabs no more.
+// Per-wave state of the bag source.  Bags [0, 2A) of a launch with A active waves are
+// dealt out statically (wave u gets bags u and u + A), so that no wave starts behind a
+// queue of thousands of same-address atomics; the rest are grabbed one at a time from
+// the work counter.  The wave holds the next bag it will work on, taken (and its lookup
+// range loaded) as soon as the previous one was taken, so that the grab's atomic and the
+// offset loads travel while the current bag is processed (except for the last bags of a
+// launch).  A held bag whose request is not yet published stays held.  After the first
+// failed grab the wave grabs no more, so every wave makes exactly one failed grab per
+// launch: the counter advances by (bags - min(2A, bags)) + A.
 struct src_state {
-  int64_t stash;
+  int64_t g;       // held bag, or -1
+  int64_t j0, j1;  // its lookups [j0, j1)
   bool exhausted;
+  uint32_t uw;     // this wave's index among the active waves
+  uint32_t dealt;  // static bags looked at so far (0..2)
 };
+// Work-counter increments of one launch over `nbags` bags with `active` waves.
+__host__ __device__ inline uint64_t launch_grabs(uint64_t nbags, uint64_t active) {
+  const uint64_t dealt = 2 * active < nbags ? 2 * active : nbags;
+  return nbags - dealt + active;
+}
 
 __device__ __forceinline__ float fK(float v, uint32_t K) {
   for (uint32_t k = 0; k < K; ++k) v = __builtin_fmaf(v, 0.999f, 0.001f);
@@ -116,6 +131,45 @@ __device__ __forceinline__ bool wait_published(const dev_ctx& c, const embbag_ar
 
 // Next chunk after `d` (or the first one when !d.valid): continues the bag or grabs the
 // next non-empty bag; empty bags get their zero output on the way.
+// Takes the next bag into the held slot (or marks the source exhausted).
+__device__ __forceinline__ void hold_next(const dev_ctx& c, const launch_t& li, const embbag_args& a,
+                                          src_state& ss) {
+  const int64_t A = (int64_t)a.active_waves, nb = (int64_t)a.nbags;
+  const int64_t dealt = 2 * A < nb ? 2 * A : nb;
+  int64_t g = -1;
+  while (ss.dealt < 2) {
+    const int64_t s = (int64_t)ss.uw + (int64_t)ss.dealt * A;
+    ++ss.dealt;
+    if (s < dealt) {
+      g = s;
+      break;
+    }
+  }
+  if (g < 0) {
+    const int64_t v = grab(c, li);
+    if (v < 0 || dealt + v >= nb) {
+      // below zero: the work counter is behind this launch's base (never in a healthy
+      // context); report it instead of indexing with it
+      if (v < 0 && lane() == 0) raise_error(c, E_STATE, 0xE0000000ull);
+      ss.exhausted = true;
+      ss.g = -1;
+      return;
+    }
+    g = dealt + v;
+  }
+  ss.g = g;
+  if (a.gather) {
+    ss.j0 = g * 64;
+    ss.j1 = ((int64_t)a.n < ss.j0 + 64) ? (int64_t)a.n : ss.j0 + 64;
+  } else {
+    ss.j0 = a.off[g];
+    ss.j1 = a.off[g + 1];
+  }
+}
+
+// Next chunk after `d` (or the first one when !d.valid): continues the bag or takes the
+// held bag; empty bags get their zero output on the way.  With !may_wait, a held bag of
+// an unpublished request ends the search (the wave first finishes what it has).
 template <int VPL>
 __device__ __forceinline__ desc_t next_desc(const dev_ctx& c, const launch_t& li, const embbag_args& a,
                             const desc_t& d, src_state& ss, bool may_wait) {
@@ -127,39 +181,30 @@ __device__ __forceinline__ desc_t next_desc(const dev_ctx& c, const launch_t& li
     r.end = d.end;
   } else {
     for (;;) {
-      if (ss.exhausted) return r;
-      int64_t g = ss.stash;
-      if (g < 0) g = grab(c, li);
-      if (g >= (int64_t)a.nbags) {
-        ss.exhausted = true;
-        ss.stash = -1;
-        return r;
+      if (ss.g < 0) {
+        if (ss.exhausted) return r;
+        hold_next(c, li, a, ss);
+        if (ss.g < 0) return r;
       }
+      const int64_t g = ss.g;
       if (a.serve) {
         const uint32_t rq = a.bag_req[g];
         if (uni(ld_rlx(a.pub_dev)) <= rq) {
-          if (!may_wait) {
-            ss.stash = g;  // consume what the wave holds first
-            return r;
-          }
+          if (!may_wait) return r;  // keep holding it
           if (!wait_published(c, a, rq)) {
             ss.exhausted = true;
-            ss.stash = -1;
+            ss.g = -1;
             return r;
           }
         } else {
           fence_acq();
         }
       }
-      ss.stash = -1;
-      int64_t j0, j1;
-      if (a.gather) {
-        j0 = g * 64;
-        j1 = ((int64_t)a.n < j0 + 64) ? (int64_t)a.n : j0 + 64;
-      } else {
-        j0 = a.off[g];
-        j1 = a.off[g + 1];
-      }
+      const int64_t j0 = ss.j0, j1 = ss.j1;
+      // hold the next bag now, except near the end of the work: a held bag cannot go to
+      // a wave that runs out, so the last bags are taken only when needed
+      ss.g = -1;
+      if (g + 2 * (int64_t)a.active_waves < (int64_t)a.nbags) hold_next(c, li, a, ss);
       if (j1 > j0) {
         r.g = g;
         r.j = j0;
@@ -342,7 +387,7 @@ __device__ __forceinline__ void embbag_wave(const dev_ctx& c, const launch_t& li
   for (int v = 0; v < VPL; ++v) acc[v] = 0.0f;
   desc_t none;
   none.valid = false;
-  src_state ss{-1, false};
+  src_state ss{-1, 0, 0, false, uw, 0};
   desc_t dc = next_desc<VPL>(c, li, a, none, ss, true);
   if (!dc.valid) return;
   chunk_t cc, cn;
@@ -353,11 +398,15 @@ __device__ __forceinline__ void embbag_wave(const dev_ctx& c, const launch_t& li
     bool n_issued = false;
     dn.valid = false;
     if (async) {
+      const uint64_t t_desc = now();
       dn = next_desc<VPL>(c, li, a, dc, ss, false);
       if (dn.valid) {
         make_chunk(c, a, dn, cn);
+        wtick(c, WS_T_DESC, t_desc);
         if (!chunk_issue(c, cn, q, true, PIN_NONE)) return;
         n_issued = true;
+      } else {
+        wtick(c, WS_T_DESC, t_desc);
       }
     }
     // consume the current chunk in order up to its first row without a line
@@ -365,7 +414,7 @@ __device__ __forceinline__ void embbag_wave(const dev_ctx& c, const launch_t& li
     const uint64_t t_cons = now();
     const uint32_t k = consume<VPL>(c, a, dc, cc, acc, true);
     chunk_release(c, cc, false);
-    ptick(c, P_U_CONSUME, t_cons);
+    wtick(c, WS_T_CONSUME, t_cons);
     if (lane() == 0) wcount(WS_AUX1, k);
     if (k < dc.n) {
       // EAGAIN: drop every pin this wave holds (including the prefetched chunk), then
@@ -401,13 +450,16 @@ __device__ __forceinline__ void embbag_wave(const dev_ctx& c, const launch_t& li
 #pragma unroll
       for (int v = 0; v < VPL; ++v) acc[v] = 0.0f;
     }
-    if (!async || (!dn.valid && ss.stash >= 0)) dn = next_desc<VPL>(c, li, a, dc, ss, true);
+    const uint64_t t_desc = now();
+    if (!async || (!dn.valid && ss.g >= 0)) dn = next_desc<VPL>(c, li, a, dc, ss, true);
     dc = dn;
     if (!dc.valid) break;
     if (n_issued) {
       cc = cn;
+      wtick(c, WS_T_DESC, t_desc);
     } else {
       make_chunk(c, a, dc, cc);
+      wtick(c, WS_T_DESC, t_desc);
       if (!chunk_issue(c, cc, q, true, PIN_NONE)) return;
     }
   }
@@ -1715,7 +1767,7 @@ static agile_status embbag_launch(agile_ctx ctx, agile_store store, const agile_
   }
   a.active_waves = active;
   const bool serial = (ctx->cfg.flags & AGILE_F_SERIALIZED) != 0;
-  launch_t li = make_launch(ctx, uw, true, serial ? 0 : a.nbags + active);
+  launch_t li = make_launch(ctx, uw, true, serial ? 0 : launch_grabs(a.nbags, active));
   const dim3 grid(li.service_blocks + uw / WPB);
   hipStream_t hs = (hipStream_t)stream;
   if (kind == KIND_EMBBAG1)
@@ -2071,7 +2123,7 @@ agile_status agile_serve(agile_ctx ctx, agile_store store, const agile_tables* t
   const uint32_t active = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>({want, (uint64_t)user_wave_cap(ctx, kind), by_cache}));
   const uint32_t uw = (active + WPB - 1) / WPB * WPB;
   a.active_waves = active;
-  launch_t li = make_launch(ctx, uw, true, nbags + active);
+  launch_t li = make_launch(ctx, uw, true, launch_grabs(nbags, active));
   li.service_blocks = (ctx->n_ctrl + ctx->n_cq + 1 + WPB - 1) / WPB;  // + the publication mirror
   const dim3 grid(li.service_blocks + uw / WPB);
   if (kind == KIND_SERVE1)

@@ -152,7 +152,8 @@ enum : uint32_t {
   C_AUX1, C_SVC_START, C_CTRL_FETCH, C_CTRL_LOOPS, C_CQ_LOOPS, C_WROWS,
   // stage timers (ticks of s_memrealtime, summed over wavefronts; profile flag only)
   P_CTRL_FETCH, P_CTRL_COPY, P_CTRL_POST, P_CTRL_HOLD, P_CTRL_IDLE, P_CTRL_NOROOM, P_CQ_BUSY,
-  P_CQ_IDLE, P_U_ISSUE, P_U_SUBMIT, P_U_WAIT, P_U_CONSUME, P_TOK_LEAD, P_TOK_N, C_COUNT
+  P_CQ_IDLE, P_U_ISSUE, P_U_SUBMIT, P_U_WAIT, P_U_CONSUME, P_TOK_LEAD, P_TOK_N, P_U_DESC,
+  P_U_LIFE, C_COUNT
 };
 constexpr uint32_t CSTRIDE = 16;  // u64 per counter
 
@@ -806,10 +807,15 @@ __device__ __forceinline__ void run_service(const dev_ctx& c, const launch_t& li
 // Per-wavefront statistics.  The counters that user waves bump on every chunk are summed
 // in the wave's own LDS slots and added to the device counters once, when the wave ends:
 // thousands of waves adding to a handful of device-scope addresses would serialise there.
-enum : uint32_t { WS_REQUESTS = 0, WS_HITS, WS_MISSES, WS_EAGAIN, WS_AUX1, WS_WROWS, WS_COUNT };
+// The user-wave stage timers (profile flag only) are kept the same way.
+enum : uint32_t {
+  WS_REQUESTS = 0, WS_HITS, WS_MISSES, WS_EAGAIN, WS_AUX1, WS_WROWS,
+  WS_T_ISSUE, WS_T_SUBMIT, WS_T_WAIT, WS_T_CONSUME, WS_T_DESC, WS_T_LIFE, WS_COUNT
+};
 __device__ __forceinline__ uint32_t ws_counter(uint32_t k) {
-  return k == WS_REQUESTS ? C_REQUESTS : k == WS_HITS ? C_HITS : k == WS_MISSES ? C_MISSES
-       : k == WS_EAGAIN ? C_EAGAIN : k == WS_AUX1 ? C_AUX1 : C_WROWS;
+  constexpr uint32_t map[WS_COUNT] = {C_REQUESTS, C_HITS, C_MISSES, C_EAGAIN, C_AUX1, C_WROWS,
+                                      P_U_ISSUE, P_U_SUBMIT, P_U_WAIT, P_U_CONSUME, P_U_DESC, P_U_LIFE};
+  return map[k];
 }
 __device__ __forceinline__ uint64_t* wave_stats() {
   __shared__ uint64_t ws[WPB][WS_COUNT];
@@ -817,17 +823,25 @@ __device__ __forceinline__ uint64_t* wave_stats() {
 }
 // Called by every user wavefront before its first chunk.
 __device__ __forceinline__ void user_wave_begin() {
-  if (lane() < WS_COUNT) wave_stats()[lane()] = 0;
+  if (lane() < WS_COUNT) wave_stats()[lane()] = lane() == WS_T_LIFE ? (uint64_t)0 - now() : 0;
 }
 // Lane 0 only.
 __device__ __forceinline__ void wcount(uint32_t k, uint64_t v) {
   if (v) wave_stats()[k] += v;
 }
+// User-wave stage timer k (profile flag only): adds now() - t, returns now().
+__device__ __forceinline__ uint64_t wtick(const dev_ctx& c, uint32_t k, uint64_t t) {
+  if (!profiling(c)) return 0;
+  const uint64_t n = now();
+  if (lane() == 0) wave_stats()[k] += n - t;
+  return n;
+}
 
 // Called by every user wavefront when it is done with this launch.
 __device__ __forceinline__ void user_wave_done(const dev_ctx& c) {
   if (lane() < WS_COUNT) {
-    const uint64_t v = wave_stats()[lane()];
+    uint64_t v = wave_stats()[lane()];
+    if (lane() == WS_T_LIFE) v = profiling(c) ? v + now() : 0;
     if (v) add_rlx(counter(c, ws_counter(lane())), v);
   }
   if (lane() == 0) add_rel(counter(c, C_USER_DONE), 1ull);
@@ -1007,7 +1021,9 @@ __device__ __forceinline__ acq_t acquire_try(const dev_ctx& c, uint32_t line_id,
 // A chunk is up to 64 lookups, one per lane.  issue() coalesces duplicate lines within the
 // wave (level-1 coalescing, Sec. 3.3.2: one leader lane per distinct line), acquires the
 // leaders' lines (level-2 coalescing in the cache), submits the wave's READs with one
-// reservation, and broadcasts each leader's line to its followers.
+// reservation, and broadcasts each leader's line to its followers.  Optimistic readers
+// probe first and coalesce only the lanes whose line is neither resident nor in flight:
+// a hit needs no leader, since it issues nothing.
 // Pinning modes of a chunk.
 enum : uint32_t {
   PIN_LINE = 0,  // one pin per distinct line (writers, serialized traces)
@@ -1031,14 +1047,15 @@ __device__ __forceinline__ bool st_ok(uint32_t st) {
   return st == A_HIT || st == A_JOIN || st == A_MISS;
 }
 
-__device__ __forceinline__ void dedup(chunk_t& ch) {
-  uint64_t todo = ballot(ch.act);
+// Leader election among the lanes with `part` (the others lead themselves).
+__device__ __forceinline__ void dedup(chunk_t& ch, bool part) {
+  uint64_t todo = ballot(part);
   ch.leader = lane();
   ch.cnt = 0;
   while (todo) {
     const uint32_t l = ffs64(todo);
     const uint32_t v = rdlane(ch.line_id, l);
-    const uint64_t same = ballot(ch.act && ch.line_id == v);
+    const uint64_t same = ballot(part && ch.line_id == v);
     if ((same >> lane()) & 1ull) ch.leader = l;
     if (lane() == l) ch.cnt = __popcll(same);
     todo &= ~same;
@@ -1050,10 +1067,27 @@ __device__ __forceinline__ void dedup(chunk_t& ch) {
 __device__ __forceinline__ bool chunk_issue(const dev_ctx& c, chunk_t& ch, uint32_t q, bool count_stats,
                             uint32_t pin_mode = PIN_LINE) {
   const uint64_t t_issue = now();
-  dedup(ch);
-  const bool lead = ch.act && ch.leader == lane();
-  const uint32_t npin = pin_mode == PIN_EACH ? ch.cnt : (pin_mode == PIN_LINE ? 1u : 0u);
   uint32_t st = A_NONE, idx = 0, gen = 0;
+  bool part = ch.act;  // lanes that go through dedup and the acquire loop
+  if (pin_mode == PIN_NONE) {
+    // optimistic readers: every lane first probes its own set; a resident or in-flight
+    // line is taken unpinned on the spot, and only the lanes left over elect leaders
+    if (ch.act) {
+      const uint32_t base = set_of(c, ch.line_id) * c.assoc;
+      uint64_t m = 0;
+      const int w = probe_set(c, base, ch.line_id, m);
+      if (w >= 0) {
+        st = (m_state(m) == ST_FETCHING) ? A_JOIN : A_HIT;
+        idx = base + (uint32_t)w;
+        gen = m_gen(m);
+        if (!(m & M_REF)) or_rlx(c.meta + idx, M_REF);
+        part = false;
+      }
+    }
+  }
+  dedup(ch, part);
+  const bool lead = part && ch.leader == lane();
+  const uint32_t npin = pin_mode == PIN_EACH ? ch.cnt : (pin_mode == PIN_LINE ? 1u : 0u);
   int retake = -1;
   bool pending = lead;
   spin_t sp;
@@ -1087,7 +1121,7 @@ __device__ __forceinline__ bool chunk_issue(const dev_ctx& c, chunk_t& ch, uint3
     const uint64_t ts = now();
     if (!submit(c, q, rd, OPC_READ, idx, slba, nblk)) return false;
     if (!submit(c, q, wb, OPC_WRITE, idx, slba, nblk)) return false;
-    ptick(c, P_U_SUBMIT, ts);
+    wtick(c, WS_T_SUBMIT, ts);
     if (ballot(wb)) {
       const uint64_t nwb = __popcll(ballot(wb));
       if (lane() == 0) count(c, C_WB_EVICT, nwb);
@@ -1119,7 +1153,7 @@ __device__ __forceinline__ bool chunk_issue(const dev_ctx& c, chunk_t& ch, uint3
     ch.st = A_NONE;
     ch.pinned = false;
   }
-  ptick(c, P_U_ISSUE, t_issue);
+  wtick(c, WS_T_ISSUE, t_issue);
   if (count_stats) {
     const uint64_t nreq = __popcll(ballot(ch.act && ch.st != A_EAGAIN));
     const uint64_t nmiss = __popcll(ballot(ch.act && ch.st == A_MISS));
@@ -1152,7 +1186,7 @@ __device__ __forceinline__ bool chunk_wait(const dev_ctx& c, const chunk_t& ch, 
     if (!sp.step(c, 0xD0000000ull | ch.idx)) return false;
   }
   if (acquire) fence_acq();
-  ptick(c, P_U_WAIT, t_wait);
+  wtick(c, WS_T_WAIT, t_wait);
   return true;
 }
 
