@@ -30,6 +30,32 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+ROOT = os.path.dirname(os.path.abspath(__file__))
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_embbag_dlrm_16GiB_traffic.md")
+KERNEL_SOURCES = ("paper_2504_19365_amd/csrc/agile.hip", "paper_2504_19365_amd/csrc/agile_dev.hpp",
+                  "include/agile.h")
+
+
+def committed_traffic():
+    """Measured HBM traffic per launch of the timed kernel (rocprofv3 FETCH_SIZE and
+    WRITE_SIZE, scaled by a plain copy of known size) from the committed profile, or None
+    when the kernel sources changed since the counters were taken."""
+    import hashlib
+    try:
+        text = open(TRAFFIC_PROFILE).read()
+    except OSError:
+        return None
+    vals = dict(line.split(": ", 1) for line in text.splitlines()
+                if line.startswith(("traffic_bytes_per_launch: ", "source_sha256_16: ")))
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    if vals.get("source_sha256_16") != h.hexdigest()[:16]:
+        return None
+    return int(vals["traffic_bytes_per_launch"])
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -40,7 +66,14 @@ def parse():
     ap.add_argument("--tables", type=int, default=8)
     ap.add_argument("--batch", type=int, default=2048)
     ap.add_argument("--cache-gib", type=float, default=2.0)
-    ap.add_argument("--sweep", default="0,512", help="K values for async/sync; '' = skip")
+    ap.add_argument("--sweep", default="0,64,512,bal",
+                    help="K values for async/sync at full occupancy ('bal' = calibrated so "
+                         "that compute is 0.9x the I/O time); '' = skip")
+    ap.add_argument("--hit-cache-gib", type=float, default=8.0,
+                    help="cache of the hit-path replay: large enough that no set overflows")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="with --profile-only: one device copy of this size first (the "
+                         "reference kernel that scales the HBM traffic counters)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--profile-only", action="store_true",
@@ -257,6 +290,18 @@ def main():
     timed_ids = list(range(args.warmup, nb))
     lookups_timed = sum(batches[i][2] for i in timed_ids)
 
+    if args.profile_only and args.calib_copy_mib:
+        # a plain copy of known size: its FETCH_SIZE / WRITE_SIZE readings scale the
+        # counters of the workload kernel to bytes
+        nb_c = args.calib_copy_mib << 20
+        src_c = torch.empty(nb_c, dtype=torch.uint8, device="cuda")
+        dst_c = torch.empty_like(src_c)
+        src_c.fill_(1)
+        torch.cuda.synchronize()
+        dst_c.copy_(src_c)
+        torch.cuda.synchronize()
+        del src_c, dst_c
+
     # ---- timed step: asynchronous mode
     cold()
     run(agile.MODE_ASYNC, args.K, warm_ids)
@@ -293,25 +338,47 @@ def main():
                                  ref.view(np.uint32)))
     log(f"oracle parity on 256 sampled bags: {parity}")
 
-    # ---- hit path: replay the last batch right after itself (working set fits the cache)
-    ctx.stats(reset=True)
-    run(agile.MODE_ASYNC, 0, [last], time_each=False)
-    s4 = ctx.stats()
-    ms_hit, _ = run(agile.MODE_ASYNC, 0, [last, last, last])
-    s5 = ctx.stats()
-    hit_misses = s5["misses"] - s4["misses"]
+    # ---- hit path: a second context over the same store whose cache holds the batch's
+    # working set with no set overflowing; a warm pass, then replays (misses must be 0)
+    last = timed_ids[-1]
     n_last = batches[last][2]
+    hctx = agile.Context(**{**cfg, "cache_bytes": int(args.hit_cache_gib * 2**30)})
+    hctx.open_store(buf)
+    htb = hctx.tables(rows, dim, T)
+    hout = torch.empty((B * T, dim), dtype=torch.float32, device="cuda")
+
+    def hit_run(K, reps, waves=0, bi=last):
+        off_b, idx_b, _ = batches[bi]
+        hctx.set_max_user_waves(waves)
+        hctx.embbag_forward(htb, idx_b, off_b, B, K, hout)
+        hctx.sync()
+        ms = []
+        for _ in range(reps):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            hctx.embbag_forward(htb, idx_b, off_b, B, K, hout)
+            e1.record(stream)
+            hctx.sync()
+            ms.append(e0.elapsed_time(e1))
+        hctx.set_max_user_waves(0)
+        return float(np.median(ms))
+
+    hit_run(0, 1)
+    h0 = hctx.stats()
+    ms_hit = hit_run(0, 5)
+    h1 = hctx.stats()
+    hit_misses = h1["misses"] - h0["misses"]
+    hit_same = bool(torch.equal(hout, outs[last])) if args.K == 0 else None
     hit_bytes = n_last * (dim * 4 + 8) + B * T * (dim * 4 + 8)
-    hit_gbs = hit_bytes / (np.median(ms_hit) * 1e-3) / 1e9
-    log(f"hit replay: {np.median(ms_hit):.3f} ms, misses {hit_misses}, {hit_gbs:.0f} GB/s")
+    hit_gbs = hit_bytes / (ms_hit * 1e-3) / 1e9
+    log(f"hit replay ({args.hit_cache_gib} GiB cache): {ms_hit:.3f} ms, misses {hit_misses}, "
+        f"{hit_gbs:.0f} GB/s, same output as the timed step: {hit_same}")
 
     # ---- compute sweep at full occupancy: async vs sync at identical outputs
     def t_hit(K, ids=(last,), waves=0):
-        ctx.set_max_user_waves(waves)
-        run(agile.MODE_ASYNC, K, list(ids), time_each=False)  # warm these lines
-        ms, _ = run(agile.MODE_ASYNC, K, list(ids) * 2)
-        ctx.set_max_user_waves(0)
-        return float(np.median(ms))
+        """Compute-inclusive time of a batch (mean over `ids`) with every row a hit."""
+        return float(np.mean([hit_run(K, 3, waves, bi) for bi in ids]))
 
     def pair(K, ids, warm, waves=0):
         res = {}
@@ -327,11 +394,23 @@ def main():
         return res
 
     sweep = []
+    k_bal = None
     if args.sweep:
         ids3 = timed_ids[:3]
         t_io = None
-        for k in [k for k in args.sweep.split(",") if k and k != "bal"]:
-            K = int(k)
+        ks = [k for k in args.sweep.split(",") if k]
+        if "bal" in ks and "0" not in ks:
+            ks = ["0"] + ks
+        for k in ks:
+            if k == "bal":
+                # K with compute = 0.9 x the synchronous I/O time of a batch at K = 0
+                c_lo, c_hi = t_hit(0), t_hit(512)
+                per_k = max((c_hi - c_lo) / 512.0, 1e-9)
+                K = int(round(0.9 * t_io / per_k))
+                k_bal = K
+                log(f"K_bal = {K} (I/O {t_io:.2f} ms, {per_k * 1e3:.3f} us per unit of K)")
+            else:
+                K = int(k)
             res = pair(K, ids3, warm_ids[:1])
             if K == 0:
                 t_io = res["sync"]
@@ -339,7 +418,8 @@ def main():
             io = t_io or res["sync"]
             ctc = comp / io
             bound = 1 + ctc if ctc <= 1 else 1 + 1 / ctc
-            sweep.append({"K": K, "sync_ms": round(res["sync"], 3), "async_ms": round(res["async"], 3),
+            sweep.append({"K": K, "balanced": k == "bal", "sync_ms": round(res["sync"], 3),
+                          "async_ms": round(res["async"], 3),
                           "speedup": round(res["sync"] / res["async"], 3), "ctc": round(ctc, 4),
                           "eq1_bound": round(bound, 3), "identical": res["identical"]})
             log(f"full GPU K={K}: sync {res['sync']:.2f} async {res['async']:.2f} "
@@ -375,28 +455,26 @@ def main():
                 f"speedup {res['sync'] / res['async']:.3f} bound {bound:.3f} "
                 f"identical {res['identical']}")
 
-    # ---- CPU baseline: the oracle on a bounded sample of the same workload
+    # ---- CPU baseline: the oracle on a bounded sample of the same workload (whole
+    # batches of the same generator, seeds 1000, 1001, ..., until the time budget is spent)
     cpu = None
     if not args.no_cpu:
-        first = timed_ids[0]
-        off0 = batches[first][0].cpu().numpy()
-        idx0 = batches[first][1].cpu().numpy()
-        nbags = 256
-        while True:
-            bags = np.arange(nbags, dtype=np.int64)
+        looked, el, nbat = 0, 0.0, 0
+        while el < args.cpu_seconds and nbat < 200:
+            off_c, idx_c = gen.embbag_batch(cum, B, T, 1, 80, seed=1000 + nbat)
             c0 = time.perf_counter()
-            oracle.embbag_forward(buf.array, rows, dim, T, idx0, off0, B, args.K, bags=bags)
-            el = time.perf_counter() - c0
-            if el > args.cpu_seconds * 0.5 or nbags >= B * T:
-                break
-            nbags = min(B * T, int(nbags * max(2.0, args.cpu_seconds / max(el, 1e-3))))
-        looked = int(off0[nbags] - off0[0])
+            oracle.embbag_forward(buf.array, rows, dim, T, idx_c, off_c, B, args.K)
+            el += time.perf_counter() - c0
+            looked += idx_c.size
+            nbat += 1
         cpu = {"value": round(looked / el, 1), "unit": "rows/s", "cores": 1, "kind": "oracle",
-               "sample": f"first {nbags} bags ({looked} lookups) of step batch seed "
-                         f"{1000 + first}, K={args.K}, single-threaded C oracle reading the "
-                         f"pinned image directly ({el:.1f} s)"}
-        log(f"cpu oracle: {cpu['value']} rows/s on {nbags} bags")
+               "sample": f"{nbat} whole batches (seeds 1000..{999 + nbat}, {looked} lookups, "
+                         f"K={args.K}) through the single-threaded C oracle reading the pinned "
+                         f"image directly, {el:.1f} s"}
+        log(f"cpu oracle: {cpu['value']} rows/s over {nbat} batches")
 
+    hctx.close_store()
+    hctx.shutdown()
     extras = {}
     wanted = [e for e in args.extras.split(",") if e]
     if wanted:
@@ -412,6 +490,9 @@ def main():
             extras["graph"] = measure_graph(agile, gen, oracle, args.graph_scale, log)
 
     ms_step = float(np.mean(ms_async))
+    default_workload = (args.K == 0 and rows == 4194304 and T == 8 and B == 2048
+                        and args.cache_gib == 2.0)
+    traffic = committed_traffic() if default_workload else None
     rows_per_s = lookups_timed / (sum(ms_async) * 1e-3)
     iops = reads / (sum(ms_async) * 1e-3)
     store_roof = min(1.5e6, 1e30)
@@ -446,14 +527,19 @@ def main():
                            "miss_gbs": round(iops * 4096 / 1e9, 3),
                            "read_cmds": reads, "hits": hits, "misses": misses},
         "hit_path": {"gbs": round(hit_gbs, 1), "frac_hbm_peak": round(hit_gbs / HBM_PEAK_GBS, 4),
-                     "ms": round(float(np.median(ms_hit)), 4), "misses_in_replay": hit_misses,
-                     "lookups": n_last},
+                     "ms": round(ms_hit, 4), "misses_in_replay": hit_misses, "lookups": n_last,
+                     "cache_gib": args.hit_cache_gib, "same_output_as_step": hit_same},
+        "k_bal": k_bal,
         "compute_sweep_full_gpu": sweep,
         "overlap_1024_threads": overlap,
         "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 6), "traffic": None,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 6),
+                     "traffic": traffic,
+                     "traffic_unit": "bytes per launch (FETCH_SIZE + WRITE_SIZE, scaled)",
+                     "algorithmic_bytes_per_launch": int(algo_bytes / len(timed_ids)),
                      "kernel": "k_embbag<2>",
-                     "note": "the step is bounded by the emulated store (see store_roofline)"},
+                     "note": "the step is bounded by the emulated store (see store_roofline); "
+                             "traffic includes the 4 KiB block fills of the misses"},
         "cpu_baseline": cpu,
         **extras,
         "device": {"cus": info["cu_count"], "wallclock_hz": info["wallclock_hz"],
