@@ -285,7 +285,9 @@ agile_status agile_spmv(agile_ctx ctx, agile_store store, const agile_csr* g, co
 typedef struct agile_serve_opts {
   uint64_t max_inflight_lookups;  /* queue budget (0 = the SQ slots, or the largest request) */
   uint64_t max_inflight_requests; /* 0 = 4096 */
-  uint64_t user_waves;            /* 0 = fill the GPU */
+  uint64_t user_waves;            /* 0 = num_lines / 16; else this many (up to what fits) */
+  uint64_t max_inflight_lines;    /* cache budget (0 = num_lines); a request reserves
+                                     min(its lookups, 64, budget / 2) lines */
 } agile_serve_opts;
 
 typedef struct agile_serve_report {
@@ -301,7 +303,7 @@ typedef struct agile_serve_report {
  * up and their I/O overlaps on the device.  The host publishes request r once
  * arrival_s[r] (seconds from the start, non-decreasing) has passed and the requests in
  * flight leave room in the queue budget (lookups in flight, every lookup may miss) and
- * the cache budget (lines in flight, at most half the cache per request); a request that
+ * the cache budget (lines one chunk of each request in flight can pin); a request that
  * does not fit waits, and so do the ones behind it.  Request r owns bags
  * [req_bag0[r], req_bag0[r+1]); bag b owns lookups [bag_off[b], bag_off[b+1]) of idx and
  * reads table (b - req_bag0[r]) % num_tables.  Outputs (pooled, K as in

@@ -63,7 +63,7 @@ class CSR(C.Structure):
 
 class ServeOpts(C.Structure):
     _fields_ = [("max_inflight_lookups", C.c_uint64), ("max_inflight_requests", C.c_uint64),
-                ("user_waves", C.c_uint64)]
+                ("user_waves", C.c_uint64), ("max_inflight_lines", C.c_uint64)]
 
 
 class ServeReport(C.Structure):
@@ -342,7 +342,8 @@ class Context:
 
     def serve(self, tb: Tables, K: int, arrival, req_bag0, bag_off, idx,
               mode: int = MODE_ASYNC, max_inflight_lookups: int = 0,
-              max_inflight_requests: int = 0, user_waves: int = 0, store=None):
+              max_inflight_requests: int = 0, user_waves: int = 0,
+              max_inflight_lines: int = 0, store=None):
         """Continuous-batching session; returns (out [nbags, dim], latency_s, report)."""
         store = store or self.store
         arrival = np.ascontiguousarray(arrival, dtype=np.float64)
@@ -353,7 +354,8 @@ class Context:
         nbags = int(req_bag0[-1])
         out = np.empty((nbags, tb.dim), dtype=np.float32)
         lat = np.zeros(nreq, dtype=np.float64)
-        opts = ServeOpts(max_inflight_lookups, max_inflight_requests, user_waves)
+        opts = ServeOpts(max_inflight_lookups, max_inflight_requests, user_waves,
+                         max_inflight_lines)
         rep = ServeReport()
         self._check(lib().agile_serve(self.h, store.handle, C.byref(tb), K, mode, nreq,
                                       _ptr(arrival), _ptr(req_bag0), _ptr(bag_off),

@@ -409,13 +409,27 @@ __device__ __forceinline__ void embbag_wave(const dev_ctx& c, const launch_t& li
         wtick(c, WS_T_DESC, t_desc);
       }
     }
-    // consume the current chunk in order up to its first row without a line
-    if (!chunk_wait(c, cc, false)) return;
-    const uint64_t t_cons = now();
-    const uint32_t k = consume<VPL>(c, a, dc, cc, acc, true);
-    chunk_release(c, cc, false);
-    wtick(c, WS_T_CONSUME, t_cons);
-    if (lane() == 0) wcount(WS_AUX1, k);
+    // Consume the current chunk in order up to its first row without a line.  A row
+    // whose line changed tenant while it was read (the seqlock check failed) is presented
+    // again optimistically, with the rest of the chunk, up to twice: waiting for the lines
+    // of a fresh claim is safe while this wave holds pins, since a claimed line always
+    // fills.  A row that met a full set, or keeps losing its line, is drained below.
+    uint32_t k = 0;
+    for (uint32_t attempt = 0;; ++attempt) {
+      if (attempt) {
+        dc.j += k;
+        dc.n -= k;
+        make_chunk(c, a, dc, cc);
+        if (!chunk_issue(c, cc, q, true, PIN_NONE)) return;
+      }
+      if (!chunk_wait(c, cc, false)) return;
+      const uint64_t t_cons = now();
+      k = consume<VPL>(c, a, dc, cc, acc, true);
+      chunk_release(c, cc, false);
+      wtick(c, WS_T_CONSUME, t_cons);
+      if (lane() == 0) wcount(WS_AUX1, k);
+      if (k == dc.n || attempt == 2 || !st_ok(rdlane(cc.st, k))) break;
+    }
     if (k < dc.n) {
       // EAGAIN: drop every pin this wave holds (including the prefetched chunk), then
       // drain the rest of the chunk one row at a time, acquiring each row while holding
@@ -2118,9 +2132,11 @@ agile_status agile_serve(agile_ctx ctx, agile_store store, const agile_tables* t
   a.pub_host = (const uint32_t*)d_pub;
   a.done = (uint32_t*)d_done;
   const int kind = tb->dim <= 64 ? KIND_SERVE1 : (tb->dim <= 128 ? KIND_SERVE2 : KIND_SERVE4);
+  // default: a sixteenth of the lines in waves; an explicit count overrides that (the
+  // EAGAIN drain keeps an over-subscribed cache deadlock-free, only slower)
   const uint64_t by_cache = std::max<uint64_t>(1, ctx->d.num_lines / 16);
-  uint64_t want = opts && opts->user_waves ? opts->user_waves : user_wave_cap(ctx, kind);
-  const uint32_t active = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>({want, (uint64_t)user_wave_cap(ctx, kind), by_cache}));
+  const uint64_t want = opts && opts->user_waves ? opts->user_waves : by_cache;
+  const uint32_t active = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(want, (uint64_t)user_wave_cap(ctx, kind)));
   const uint32_t uw = (active + WPB - 1) / WPB * WPB;
   a.active_waves = active;
   launch_t li = make_launch(ctx, uw, true, launch_grabs(nbags, active));
@@ -2138,13 +2154,18 @@ agile_status agile_serve(agile_ctx ctx, agile_store store, const agile_tables* t
   const uint64_t sq_slots = (uint64_t)ctx->d.num_qp * ctx->d.depth;
   const uint64_t cap_look = opts && opts->max_inflight_lookups ? opts->max_inflight_lookups
                                                                : std::max<uint64_t>(sq_slots, max_req_look);
-  const uint64_t cap_lines = std::max<uint64_t>(1, ctx->d.num_lines);
+  const uint64_t cap_lines = opts && opts->max_inflight_lines ? opts->max_inflight_lines
+                                                             : std::max<uint64_t>(1, ctx->d.num_lines);
   const uint64_t cap_req = opts && opts->max_inflight_requests ? opts->max_inflight_requests : 4096;
   std::vector<uint64_t> inflight;
   std::vector<double> t_pub(nreq, 0.0);
   uint64_t next = 0, completed = 0, in_look = 0, in_lines = 0, max_in = 0;
   auto look_of = [&](uint64_t r) { return (uint64_t)(bag_off[req_bag0[r + 1]] - bag_off[req_bag0[r]]); };
-  auto lines_of = [&](uint64_t r) { return std::min<uint64_t>(look_of(r), cap_lines / 2); };
+  // a request's cache reservation: the lines one chunk of it can pin (a wave holds at
+  // most one chunk's misses of a bag while it waits), never more than half the budget
+  auto lines_of = [&](uint64_t r) {
+    return std::min<uint64_t>({look_of(r), (uint64_t)64, std::max<uint64_t>(1, cap_lines / 2)});
+  };
   const auto t0 = std::chrono::steady_clock::now();
   auto since = [&]() { return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count(); };
   double last_progress = 0.0;

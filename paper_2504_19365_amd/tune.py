@@ -1,7 +1,8 @@
 """Autotuner for the block-I/O path's geometry.
 
-Staged coordinate descent over line size, associativity, queue-pair count, queue depth and
-the number of emulated-controller wavefronts.  Each trial builds a context with the candidate
+Staged coordinate descent over line size, associativity, queue-pair count, queue depth,
+the number of emulated-controller wavefronts and the number of user wavefronts the
+serving kernel runs.  Each trial builds a context with the candidate
 geometry over the same store, runs a short closed-loop serving session (every request
 available at once, so the session measures sustainable throughput) and scores it in
 lookups per second.  Points the library rejects (for example fewer lines than ways) are
@@ -22,8 +23,10 @@ SPACE = {
     "num_qp": [4, 8, 16, 32, 64],
     "qp_depth": [256, 512, 1024, 2048, 4096],
     "ctrl_waves": [16, 32, 64, 128],
+    "user_waves": [16, 32, 64, 128, 256],
 }
-START = {"line_bytes": 4096, "assoc": 8, "num_qp": 16, "qp_depth": 1024, "ctrl_waves": 64}
+START = {"line_bytes": 4096, "assoc": 8, "num_qp": 16, "qp_depth": 1024, "ctrl_waves": 64,
+         "user_waves": 16}
 
 
 def _config(point: dict, cache_bytes: int, latency_ns: int, iops_cap: int) -> dict:
@@ -46,7 +49,8 @@ def serve_trial(image, rows: int, dim: int, point: dict, stream, cache_bytes: in
     try:
         ctx.open_store(image)
         tb = ctx.tables(rows, dim, 1)
-        _, lat, rep = ctx.serve(tb, K, np.zeros_like(arrival), req_bag0, bag_off, idx, mode=mode)
+        _, lat, rep = ctx.serve(tb, K, np.zeros_like(arrival), req_bag0, bag_off, idx, mode=mode,
+                                user_waves=point.get("user_waves", 0))
         ctx.close_store()
     finally:
         ctx.shutdown()
@@ -107,4 +111,4 @@ if __name__ == "__main__":
     buf = agile.PinnedBuffer(rows * dim * 4)
     gen.fill_table(buf.ptr, 0, rows, dim, 0)
     res = tune(buf, rows, dim, requests=int(sys.argv[1]) if len(sys.argv) > 1 else 2000)
-    print(json.dumps({k: v for k, v in res.items() if k != "trials"}))
+    print(json.dumps(res))
