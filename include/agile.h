@@ -211,7 +211,10 @@ agile_status agile_gather(agile_ctx ctx, agile_store store, const agile_tables* 
  * the table).  d_out[g*dim + d] = sum, in lookup order, of f_K(row value), where f_K is
  * K iterations of v = fmaf(v, 0.999f, 0.001f) (a compute loop that sets the
  * computation-to-communication ratio, Sec. 4.2); fp32 accumulator from +0.0f.
- * mode is AGILE_MODE_SYNC or AGILE_MODE_ASYNC; both give bit-identical output. */
+ * mode is AGILE_MODE_SYNC or AGILE_MODE_ASYNC; both give bit-identical output.
+ * Stream-ordered, one kernel launch, no host synchronisation, allocation or memset: the
+ * call may be captured in a HIP graph and the graph replayed, once an eager call with a
+ * table of the same dim has been made on the context (it caches an occupancy query). */
 agile_status agile_embbag_forward(agile_ctx ctx, agile_store store, const agile_tables* tb,
                                   const int64_t* d_idx, const int64_t* d_off, uint64_t B,
                                   uint32_t K, uint32_t mode, float* d_out, void* stream);

@@ -55,8 +55,7 @@ struct embbag_args {
 // range loaded) as soon as the previous one was taken, so that the grab's atomic and the
 // offset loads travel while the current bag is processed (except for the last bags of a
 // launch).  A held bag whose request is not yet published stays held.  After the first
-// failed grab the wave grabs no more, so every wave makes exactly one failed grab per
-// launch: the counter advances by (bags - min(2A, bags)) + A.
+// failed grab the wave grabs no more.  The work counter starts every launch at zero.
 struct src_state {
   int64_t g;       // held bag, or -1
   int64_t j0, j1;  // its lookups [j0, j1)
@@ -64,11 +63,6 @@ struct src_state {
   uint32_t uw;     // this wave's index among the active waves
   uint32_t dealt;  // static bags looked at so far (0..2)
 };
-// Work-counter increments of one launch over `nbags` bags with `active` waves.
-__host__ __device__ inline uint64_t launch_grabs(uint64_t nbags, uint64_t active) {
-  const uint64_t dealt = 2 * active < nbags ? 2 * active : nbags;
-  return nbags - dealt + active;
-}
 
 __device__ __forceinline__ float fK(float v, uint32_t K) {
   for (uint32_t k = 0; k < K; ++k) v = __builtin_fmaf(v, 0.999f, 0.001f);
@@ -87,7 +81,7 @@ __device__ __forceinline__ int64_t grab(const dev_ctx& c, const launch_t& li) {
   uint64_t v = 0;
   if (lane() == 0) v = add_rlx(counter(c, C_WORK), 1ull);
   v = rdlane64(v, 0);
-  return (int64_t)(v - li.work_base);
+  return (int64_t)v;
 }
 
 template <int VPL>
@@ -530,7 +524,7 @@ __global__ __launch_bounds__(WG) void k_embbag(dev_ctx c, launch_t li, embbag_ar
   } else if (uw < a.active_waves) {
     embbag_wave<VPL>(c, li, a, uw);
   }
-  user_wave_done(c);
+  user_wave_done(c, li);
 }
 
 // Serving kernel: the embedding-bag wave loop over a stream of requests.  One extra
@@ -569,7 +563,7 @@ __global__ __launch_bounds__(WG) void k_serve(dev_ctx c, launch_t li, embbag_arg
   user_wave_begin();
   const uint32_t uw = (blockIdx.x - li.service_blocks) * WPB + threadIdx.x / 64;
   if (uw < a.active_waves) embbag_wave<VPL>(c, li, a, uw);
-  user_wave_done(c);
+  user_wave_done(c, li);
 }
 
 // ---- host-level ticket API kernels
@@ -603,7 +597,7 @@ __global__ __launch_bounds__(WG) void k_async_read(dev_ctx c, launch_t li, const
                    ((uint64_t)(ok ? TK_OK : TK_EAGAIN) << 40) | ((uint64_t)(ch.off >> 12) << 48);
     }
   }
-  user_wave_done(c);
+  user_wave_done(c, li);
 }
 
 __global__ __launch_bounds__(WG) void k_wait(dev_ctx c, launch_t li, const agile_ticket* tickets,
@@ -648,7 +642,7 @@ __global__ __launch_bounds__(WG) void k_wait(dev_ctx c, launch_t li, const agile
   }
   const uint64_t ne = __popcll(ballot(i < n && st == TK_EAGAIN));
   if (lane() == 0 && ne) add_rlx(counter(c, C_AUX0), ne);
-  user_wave_done(c);
+  user_wave_done(c, li);
 }
 
 __global__ __launch_bounds__(WG) void k_release(dev_ctx c, launch_t li, const agile_ticket* tickets,
@@ -661,7 +655,7 @@ __global__ __launch_bounds__(WG) void k_release(dev_ctx c, launch_t li, const ag
     const uint32_t idx = (uint32_t)t;
     if (((t >> 40) & 0xFF) == TK_OK && idx < c.num_lines) add_rel(c.meta + idx, (uint64_t)0 - RC_ONE);
   }
-  user_wave_done(c);
+  user_wave_done(c, li);
 }
 
 // Flush: every DIRTY, unpinned line becomes WRITEBACK and gets one WRITE; the launch's
@@ -697,7 +691,7 @@ __global__ __launch_bounds__(WG) void k_flush(dev_ctx c, launch_t li) {
     if (lane() == 0) count(c, C_WB_FLUSH, nw);
     if (!submit(c, q, wb, OPC_WRITE, (uint32_t)i, slba, nblk)) break;
   }
-  user_wave_done(c);
+  user_wave_done(c, li);
 }
 
 __global__ __launch_bounds__(WG) void k_invalidate(dev_ctx c, launch_t li) {
@@ -715,7 +709,7 @@ __global__ __launch_bounds__(WG) void k_invalidate(dev_ctx c, launch_t li) {
   }
   // clock hands back to way 0 so that a cold cache replays like a fresh one
   for (uint64_t s = i; s < c.num_sets; s += (uint64_t)li.user_waves * 64) st_rlx(c.hand + s, 0u);
-  user_wave_done(c);
+  user_wave_done(c, li);
 }
 
 // Serialized request trace for the clock-policy comparison: lane 0 of one wave acquires
@@ -757,7 +751,7 @@ __global__ __launch_bounds__(WG) void k_trace(dev_ctx c, launch_t li, const uint
     }
   }
 out:
-  user_wave_done(c);
+  user_wave_done(c, li);
 }
 
 // ---- embedding-bag backward fused with SGD (write path)
@@ -896,7 +890,7 @@ __global__ __launch_bounds__(WG) void k_bwd_sgd(dev_ctx c, launch_t li, bwd_args
   user_wave_begin();
   const uint32_t uw = (blockIdx.x - li.service_blocks) * WPB + threadIdx.x / 64;
   bwd_wave<VPL>(c, a, uw);
-  user_wave_done(c);
+  user_wave_done(c, li);
 }
 
 // ---- graph workloads over a CSR graph held in the store (row_ptr int64, col int32, val fp32)
@@ -979,7 +973,7 @@ __global__ __launch_bounds__(WG) void k_bfs_front(dev_ctx c, launch_t li, bfs_ar
       a.cd[pos] = (uint64_t)(s1 - s0);
     }
   }
-  user_wave_done(c);
+  user_wave_done(c, li);
 }
 
 // Level step 2: the frontier's edges, flattened by the prefix sums, are split into chunks
@@ -1054,7 +1048,7 @@ __global__ __launch_bounds__(WG) void k_bfs_edges(dev_ctx c, launch_t li, bfs_ar
     }
   }
 done:
-  user_wave_done(c);
+  user_wave_done(c, li);
 }
 
 // SpMV: a wave takes 64 consecutive rows, one per lane, and folds each row in CSR order,
@@ -1143,7 +1137,7 @@ __global__ __launch_bounds__(WG) void k_spmv(dev_ctx c, launch_t li, spmv_args a
     if (act) a.y[r0 + lane()] = acc;
   }
 done:
-  user_wave_done(c);
+  user_wave_done(c, li);
 }
 
 // Roofline probe: waves copy 4 KiB blocks from `src` (pinned host or HBM) to `dst`
@@ -1196,8 +1190,6 @@ struct agile_ctx_s {
   uint32_t n_ctrl, n_cq, service_blocks;
   uint32_t cu_count;
   uint64_t clock_hz;
-  uint64_t user_done_total = 0;
-  uint64_t work_total = 0;
   agile_store_s* store = nullptr;
   std::string last_error;
   bool poisoned = false;
@@ -1289,17 +1281,13 @@ agile_status check_usable(agile_ctx ctx) {
 }
 
 // user_waves must be a multiple of WPB (every wave of a user workgroup reports done).
-// `grabs` is the number of work-counter increments the launch will make.
-launch_t make_launch(agile_ctx ctx, uint32_t user_waves, bool service, uint64_t grabs) {
+// The launch descriptor holds no host-side running totals: a captured launch replays.
+launch_t make_launch(agile_ctx ctx, uint32_t user_waves, bool service) {
   launch_t li{};
   li.service_blocks = service ? ctx->service_blocks : 0;
   li.n_ctrl = ctx->n_ctrl;
   li.n_cq = ctx->n_cq;
   li.user_waves = user_waves;
-  ctx->user_done_total += user_waves;
-  li.user_done_target = ctx->user_done_total;
-  li.work_base = ctx->work_total;
-  ctx->work_total += grabs;
   li.prio = (ctx->cfg.flags & AGILE_F_NO_PRIO) ? 0 : 1;
   return li;
 }
@@ -1590,7 +1578,7 @@ agile_status agile_invalidate(agile_ctx ctx, agile_store store, void* stream) {
   hipStream_t hs = (hipStream_t)stream;
   uint64_t waves = std::max<uint64_t>((std::max<uint64_t>(ctx->d.num_lines, ctx->d.num_sets) + 63) / 64, 1);
   waves = (waves + WPB - 1) / WPB * WPB;
-  launch_t li = make_launch(ctx, (uint32_t)waves, false, 0);
+  launch_t li = make_launch(ctx, (uint32_t)waves, false);
   hipLaunchKernelGGL(k_invalidate, dim3((uint32_t)(waves / WPB)), dim3(WG), 0, hs, ctx->d, li);
   HIPCHK(ctx, hipGetLastError());
   return sync_stream(ctx, hs);
@@ -1624,7 +1612,7 @@ agile_status agile_async_read(agile_ctx ctx, agile_store store, const uint64_t* 
   if (!d_blocks || !d_tickets) return fail(ctx, AGILE_EINVAL, "async_read: null pointer");
   uint32_t uw = std::min<uint32_t>((n + 63) / 64, user_wave_cap(ctx, KIND_READ));
   uw = (uw + WPB - 1) / WPB * WPB;
-  launch_t li = make_launch(ctx, uw, true, 0);
+  launch_t li = make_launch(ctx, uw, true);
   hipLaunchKernelGGL(k_async_read, dim3(li.service_blocks + uw / WPB), dim3(WG), ctx->iso_lds, (hipStream_t)stream,
                      ctx->d, li, d_blocks, n, d_tickets);
   HIPCHK(ctx, hipGetLastError());
@@ -1641,7 +1629,7 @@ agile_status agile_wait(agile_ctx ctx, const agile_ticket* d_tickets, uint32_t n
   if (n) {
     uint32_t uw = (n + 63) / 64;
     uw = (uw + WPB - 1) / WPB * WPB;
-    launch_t li = make_launch(ctx, uw, false, 0);
+    launch_t li = make_launch(ctx, uw, false);
     hipLaunchKernelGGL(k_wait, dim3(uw / WPB), dim3(WG), 0, hs, ctx->d, li, d_tickets, n, d_ptrs);
     HIPCHK(ctx, hipGetLastError());
   }
@@ -1659,7 +1647,7 @@ agile_status agile_release(agile_ctx ctx, const agile_ticket* d_tickets, uint32_
   if (!d_tickets) return fail(ctx, AGILE_EINVAL, "release: null pointer");
   uint32_t uw = (n + 63) / 64;
   uw = (uw + WPB - 1) / WPB * WPB;
-  launch_t li = make_launch(ctx, uw, false, 0);
+  launch_t li = make_launch(ctx, uw, false);
   hipLaunchKernelGGL(k_release, dim3(uw / WPB), dim3(WG), 0, (hipStream_t)stream, ctx->d, li, d_tickets, n);
   HIPCHK(ctx, hipGetLastError());
   return AGILE_OK;
@@ -1672,7 +1660,7 @@ agile_status agile_flush(agile_ctx ctx, agile_store store, void* stream) {
   hipStream_t hs = (hipStream_t)stream;
   uint32_t uw = std::min<uint32_t>((ctx->d.num_lines + 63) / 64, user_wave_cap(ctx, KIND_FLUSH));
   uw = (uw + WPB - 1) / WPB * WPB;
-  launch_t li = make_launch(ctx, uw, true, 0);
+  launch_t li = make_launch(ctx, uw, true);
   hipLaunchKernelGGL(k_flush, dim3(li.service_blocks + uw / WPB), dim3(WG), ctx->iso_lds, hs, ctx->d, li);
   HIPCHK(ctx, hipGetLastError());
   return sync_stream(ctx, hs);
@@ -1700,7 +1688,7 @@ agile_status agile_get_stats(agile_ctx ctx, agile_stats* out, int reset) {
   out->consumed = g(C_AUX1);
   out->rows_updated = g(C_WROWS);
   if (reset) {
-    const uint32_t keep[] = {C_SUBMITTED, C_COMPLETED, C_USER_DONE, C_WORK};
+    const uint32_t keep[] = {C_SUBMITTED, C_COMPLETED, C_USER_DONE, C_WORK, C_SVC_EXIT};
     for (uint32_t i = 0; i < C_COUNT; ++i) {
       if (std::find(std::begin(keep), std::end(keep), i) != std::end(keep)) continue;
       HIPCHK(ctx, hipMemset(ctx->d.cnt + (size_t)i * CSTRIDE, 0, 8));
@@ -1781,7 +1769,7 @@ static agile_status embbag_launch(agile_ctx ctx, agile_store store, const agile_
   }
   a.active_waves = active;
   const bool serial = (ctx->cfg.flags & AGILE_F_SERIALIZED) != 0;
-  launch_t li = make_launch(ctx, uw, true, serial ? 0 : launch_grabs(a.nbags, active));
+  launch_t li = make_launch(ctx, uw, true);
   const dim3 grid(li.service_blocks + uw / WPB);
   hipStream_t hs = (hipStream_t)stream;
   if (kind == KIND_EMBBAG1)
@@ -1889,7 +1877,7 @@ agile_status agile_bfs(agile_ctx ctx, agile_store store, const agile_csr* g, uin
     HIPCHK(ctx, hipMemsetAsync(a.ctr, 0, 256, hs));
     uint32_t uw = (uint32_t)std::min<uint64_t>({(nF + 63) / 64, (uint64_t)user_wave_cap(ctx, KIND_READ), by_cache});
     uw = (uw + WPB - 1) / WPB * WPB;
-    launch_t li = make_launch(ctx, uw, true, 0);
+    launch_t li = make_launch(ctx, uw, true);
     hipLaunchKernelGGL(k_bfs_front, dim3(li.service_blocks + uw / WPB), dim3(WG), ctx->iso_lds, hs, ctx->d, li, a);
     HIPCHK(ctx, hipGetLastError());
     uint32_t nC = 0;
@@ -1905,7 +1893,7 @@ agile_status agile_bfs(agile_ctx ctx, agile_store store, const agile_csr* g, uin
     a.Et = last[0] + last[1];
     uw = (uint32_t)std::min<uint64_t>({(a.Et + 1023) / 1024, (uint64_t)user_wave_cap(ctx, KIND_READ), by_cache});
     uw = (uw + WPB - 1) / WPB * WPB;
-    li = make_launch(ctx, uw, true, 0);
+    li = make_launch(ctx, uw, true);
     hipLaunchKernelGGL(k_bfs_edges, dim3(li.service_blocks + uw / WPB), dim3(WG), ctx->iso_lds, hs, ctx->d, li, a);
     HIPCHK(ctx, hipGetLastError());
     HIPCHK(ctx, hipMemcpyAsync(&nF, a.ctr + 1, 4, hipMemcpyDeviceToHost, hs));
@@ -1938,7 +1926,7 @@ agile_status agile_spmv(agile_ctx ctx, agile_store store, const agile_csr* g, co
   uint32_t uw = (uint32_t)std::min<uint64_t>({(g->num_vertices + 63) / 64, (uint64_t)user_wave_cap(ctx, KIND_READ),
                                               by_cache});
   uw = (uw + WPB - 1) / WPB * WPB;
-  launch_t li = make_launch(ctx, uw, true, 0);
+  launch_t li = make_launch(ctx, uw, true);
   hipLaunchKernelGGL(k_spmv, dim3(li.service_blocks + uw / WPB), dim3(WG), ctx->iso_lds, hs, ctx->d, li, a);
   HIPCHK(ctx, hipGetLastError());
   return AGILE_OK;
@@ -2009,7 +1997,7 @@ agile_status agile_embbag_backward_sgd(agile_ctx ctx, agile_store store, const a
   const uint64_t by_cache = std::max<uint64_t>(1, ctx->d.num_lines / 128);
   uint32_t uw = (uint32_t)std::min<uint64_t>({(n + 63) / 64, (uint64_t)user_wave_cap(ctx, kind), by_cache});
   uw = (uw + WPB - 1) / WPB * WPB;
-  launch_t li = make_launch(ctx, uw, true, 0);
+  launch_t li = make_launch(ctx, uw, true);
   const dim3 grid(li.service_blocks + uw / WPB);
   if (kind == KIND_BWD1)
     hipLaunchKernelGGL(k_bwd_sgd<1>, grid, dim3(WG), ctx->iso_lds, hs, ctx->d, li, a);
@@ -2139,7 +2127,7 @@ agile_status agile_serve(agile_ctx ctx, agile_store store, const agile_tables* t
   const uint32_t active = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(want, (uint64_t)user_wave_cap(ctx, kind)));
   const uint32_t uw = (active + WPB - 1) / WPB * WPB;
   a.active_waves = active;
-  launch_t li = make_launch(ctx, uw, true, launch_grabs(nbags, active));
+  launch_t li = make_launch(ctx, uw, true);
   li.service_blocks = (ctx->n_ctrl + ctx->n_cq + 1 + WPB - 1) / WPB;  // + the publication mirror
   const dim3 grid(li.service_blocks + uw / WPB);
   if (kind == KIND_SERVE1)
@@ -2235,7 +2223,7 @@ agile_status agile_debug_trace(agile_ctx ctx, agile_store store, const uint64_t*
   if (store != ctx->store) return fail(ctx, AGILE_EINVAL, "trace: store is not open on this context");
   if (n == 0) return AGILE_OK;
   if (!d_lines || !d_hit || !d_way) return fail(ctx, AGILE_EINVAL, "trace: null pointer");
-  launch_t li = make_launch(ctx, WPB, true, 0);
+  launch_t li = make_launch(ctx, WPB, true);
   hipLaunchKernelGGL(k_trace, dim3(li.service_blocks + 1), dim3(WG), ctx->iso_lds, (hipStream_t)stream, ctx->d, li, d_lines,
                      d_writes, n, d_hit, d_way);
   HIPCHK(ctx, hipGetLastError());

@@ -153,7 +153,7 @@ enum : uint32_t {
   // stage timers (ticks of s_memrealtime, summed over wavefronts; profile flag only)
   P_CTRL_FETCH, P_CTRL_COPY, P_CTRL_POST, P_CTRL_HOLD, P_CTRL_IDLE, P_CTRL_NOROOM, P_CQ_BUSY,
   P_CQ_IDLE, P_U_ISSUE, P_U_SUBMIT, P_U_WAIT, P_U_CONSUME, P_TOK_LEAD, P_TOK_N, P_U_DESC,
-  P_U_LIFE, C_COUNT
+  P_U_LIFE, C_SVC_EXIT, C_COUNT
 };
 constexpr uint32_t CSTRIDE = 16;  // u64 per counter
 
@@ -196,9 +196,7 @@ struct dev_ctx {
 struct launch_t {
   uint32_t service_blocks;  // leading workgroups that run service wavefronts
   uint32_t n_ctrl, n_cq;    // controller / completion wavefronts
-  uint32_t user_waves;      // user wavefronts in this launch
-  uint64_t user_done_target;
-  uint64_t work_base;
+  uint32_t user_waves;      // user wavefronts in this launch (the service waits for all)
   uint32_t prio;            // raise service issue priority
   uint32_t _l0;
 };
@@ -375,7 +373,7 @@ __device__ __forceinline__ bool submit(const dev_ctx& c, uint32_t q, bool want, 
 // ------------------------------------------------------------------ service wavefronts
 __device__ __forceinline__ bool service_should_exit(const dev_ctx& c, const launch_t& li) {
   if (aborted(c)) return true;
-  if (uni64(ld_rlx(counter(c, C_USER_DONE))) < li.user_done_target) return false;
+  if (uni64(ld_rlx(counter(c, C_USER_DONE))) < li.user_waves) return false;
   const uint64_t sub = uni64(ld_rlx(counter(c, C_SUBMITTED)));
   const uint64_t com = uni64(ld_rlx(counter(c, C_COMPLETED)));
   return com == sub;
@@ -802,6 +800,21 @@ __device__ __forceinline__ void run_service(const dev_ctx& c, const launch_t& li
     controller(c, li, sw);
   else if (sw < li.n_ctrl + li.n_cq)
     completion(c, li, sw - li.n_ctrl);
+  else
+    return;
+  // The launch-relative counters (user waves done, work grabbed) start every launch at
+  // zero: the last service wavefront to leave clears them.  By then every user wave has
+  // reported done and every other service wave has left its loop, and the next launch
+  // on the stream starts after this one ends.  Nothing is tracked on the host, so a
+  // launch can be captured once in a graph and replayed.
+  if (lane() == 0) {
+    const uint64_t n = add_acqrel(counter(c, C_SVC_EXIT), 1ull) + 1;
+    if (n == (uint64_t)li.n_ctrl + li.n_cq) {
+      st_rlx(counter(c, C_USER_DONE), 0ull);
+      st_rlx(counter(c, C_WORK), 0ull);
+      st_rel(counter(c, C_SVC_EXIT), 0ull);
+    }
+  }
 }
 
 // Per-wavefront statistics.  The counters that user waves bump on every chunk are summed
@@ -837,14 +850,15 @@ __device__ __forceinline__ uint64_t wtick(const dev_ctx& c, uint32_t k, uint64_t
   return n;
 }
 
-// Called by every user wavefront when it is done with this launch.
-__device__ __forceinline__ void user_wave_done(const dev_ctx& c) {
+// Called by every user wavefront when it is done with this launch (only launches with
+// service wavefronts count the waves).
+__device__ __forceinline__ void user_wave_done(const dev_ctx& c, const launch_t& li) {
   if (lane() < WS_COUNT) {
     uint64_t v = wave_stats()[lane()];
     if (lane() == WS_T_LIFE) v = profiling(c) ? v + now() : 0;
     if (v) add_rlx(counter(c, ws_counter(lane())), v);
   }
-  if (lane() == 0) add_rel(counter(c, C_USER_DONE), 1ull);
+  if (lane() == 0 && li.service_blocks) add_rel(counter(c, C_USER_DONE), 1ull);
 }
 
 // ------------------------------------------------------------------ cache (Sec. 3.4)
