@@ -376,7 +376,7 @@ class Context:
                      "ctrl_loops", "cq_loops", "wrows", "t_ctrl_fetch", "t_ctrl_copy", "t_ctrl_post",
                      "t_ctrl_hold", "t_ctrl_idle", "ctrl_noroom", "t_cq_busy", "t_cq_idle",
                      "t_u_issue", "t_u_submit", "t_u_wait", "t_u_consume", "tok_lead",
-                     "tok_n", "t_u_desc", "t_u_life", "svc_exit")
+                     "tok_n", "t_u_desc", "t_u_life", "svc_exit", "img_epoch")
 
     def debug_counters(self) -> dict:
         n = len(self.COUNTER_NAMES)

@@ -902,8 +902,11 @@ struct csr_t {
 // optimistically: lines are not pinned unless this wave's own miss filled them, and the
 // line's tag and generation are re-checked after the load.  Lanes whose line changed, or
 // whose set had no evictable way, retry while holding nothing.
-template <typename T>
-__device__ __forceinline__ bool cached_read(const dev_ctx& c, uint32_t q, bool act, uint64_t byte, T& out) {
+// `drop` runs before the wave backs off to retry: a caller that holds pins of its own
+// (a prefetch) releases them there, so it never waits for a way while pinning lines.
+template <typename T, typename Drop>
+__device__ __forceinline__ bool cached_read(const dev_ctx& c, uint32_t q, bool act, uint64_t byte, T& out,
+                                            Drop&& drop) {
   bool todo = act;
   spin_t sp;
   while (ballot(todo)) {
@@ -925,10 +928,15 @@ __device__ __forceinline__ bool cached_read(const dev_ctx& c, uint32_t q, bool a
     chunk_release(c, ch, false);
     if (ok) todo = false;
     if (ballot(todo) && !ballot(ok)) {
+      drop();
       if (!sp.step(c, 0xF4000000ull)) return false;
     }
   }
   return true;
+}
+template <typename T>
+__device__ __forceinline__ bool cached_read(const dev_ctx& c, uint32_t q, bool act, uint64_t byte, T& out) {
+  return cached_read<T>(c, q, act, byte, out, [] {});
 }
 
 struct bfs_args {
@@ -1059,8 +1067,174 @@ struct spmv_args {
   csr_t g;
   const float* x;
   float* y;
-  uint32_t* ctr;  // [0] work counter
+  uint32_t active;  // user waves that take work
 };
+
+// Edges per pinned window: col and val each get eight line slots; a window of
+// (L - 1) * line_bytes / 4 edges spans at most L lines of either array, and with
+// L <= the number of sets those lines fall in distinct sets.
+__device__ __forceinline__ uint64_t spmv_window(const dev_ctx& c) {
+  const uint64_t L = c.num_sets < 8 ? (c.num_sets > 2 ? c.num_sets : 2) : 8;
+  return ((L - 1) << c.line_shift) / 4;
+}
+
+// Lines of col[p0, p1) and val[p0, p1) requested ahead of their window (the asynchronous
+// pattern of Sec. 4.2 applied to the edge stream): a line this wave claims stays pinned
+// until the window that needs it has been pinned, and the request is never waited for.
+struct spmv_pref {
+  chunk_t ch;
+  bool held;
+};
+__device__ __forceinline__ void spmv_drop(const dev_ctx& c, spmv_pref& pf) {
+  if (pf.held) chunk_release(c, pf.ch, false);
+  pf.held = false;
+}
+__device__ __forceinline__ bool spmv_prefetch(const dev_ctx& c, uint32_t q, const spmv_args& a, uint64_t p0,
+                                              uint64_t p1, spmv_pref& pf) {
+  pf.held = false;
+  if (p0 >= p1) return true;
+  const uint32_t lc0 = (uint32_t)((a.g.col_off + 4 * p0) >> c.line_shift);
+  const uint32_t lv0 = (uint32_t)((a.g.val_off + 4 * p0) >> c.line_shift);
+  const uint32_t nc = (uint32_t)((a.g.col_off + 4 * p1 - 1) >> c.line_shift) - lc0 + 1;
+  const uint32_t nv = (uint32_t)((a.g.val_off + 4 * p1 - 1) >> c.line_shift) - lv0 + 1;
+  pf.ch.act = lane() < nc || (lane() >= 8 && lane() < 8 + nv);
+  pf.ch.line_id = lane() < 8 ? lc0 + lane() : lv0 + (lane() - 8);
+  pf.ch.off = 0;
+  if (!chunk_issue(c, pf.ch, q, true, PIN_NONE)) return false;
+  pf.held = true;
+  return true;
+}
+
+// Pins the lines that hold col[w0, w1) and val[w0, w1) (one line per lane, PIN_LINE) and
+// publishes their cache indices in win[0, 8) (col) and win[8, 16) (val).  A set without
+// an evictable way makes the wave drop everything, its prefetch included, and retry while
+// holding nothing.
+__device__ __forceinline__ bool spmv_pin(const dev_ctx& c, uint32_t q, const spmv_args& a, uint64_t w0,
+                                         uint64_t w1, uint32_t* win, uint32_t& lc0, uint32_t& lv0,
+                                         chunk_t& ch, spmv_pref& pf) {
+  const uint64_t cb0 = a.g.col_off + 4 * w0, cb1 = a.g.col_off + 4 * w1 - 1;
+  const uint64_t vb0 = a.g.val_off + 4 * w0, vb1 = a.g.val_off + 4 * w1 - 1;
+  lc0 = (uint32_t)(cb0 >> c.line_shift);
+  lv0 = (uint32_t)(vb0 >> c.line_shift);
+  const uint32_t nc = (uint32_t)(cb1 >> c.line_shift) - lc0 + 1;
+  const uint32_t nv = (uint32_t)(vb1 >> c.line_shift) - lv0 + 1;
+  const bool todo = lane() < nc || (lane() >= 8 && lane() < 8 + nv);
+  const uint32_t want = lane() < 8 ? lc0 + lane() : lv0 + (lane() - 8);
+  spin_t sp;
+  for (;;) {
+    ch.act = todo;
+    ch.line_id = want;
+    ch.off = 0;
+    if (!chunk_issue(c, ch, q, true, PIN_LINE)) return false;
+    if (ballot(ch.act && ch.st == A_EAGAIN)) {
+      chunk_release(c, ch, false);
+      spmv_drop(c, pf);
+      if (!sp.step(c, 0xF5000000ull)) return false;
+      continue;
+    }
+    // no acquire (an agent-scope acquire drops the whole L2 of the XCD): the window's
+    // lines are pinned, and their data is read with device-coherent loads issued after
+    // the fill was observed
+    if (!chunk_wait(c, ch, false)) return false;
+    break;
+  }
+  if (todo) win[lane() < 8 ? lane() : 8 + (lane() - 8)] = ch.idx;
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  return true;
+}
+
+struct spmv_edge {
+  int32_t col;
+  float val;
+};
+__device__ __forceinline__ spmv_edge spmv_load(const dev_ctx& c, const spmv_args& a, const uint32_t* win,
+                                               uint32_t lc0, uint32_t lv0, uint64_t k) {
+  const uint32_t lmask = (1u << c.line_shift) - 1;
+  const uint64_t cb = a.g.col_off + 4 * k, vb = a.g.val_off + 4 * k;
+  const uint32_t ci = win[(uint32_t)(cb >> c.line_shift) - lc0];
+  const uint32_t vi = win[8 + (uint32_t)(vb >> c.line_shift) - lv0];
+  spmv_edge e;
+  e.col = (int32_t)ld_rlx(reinterpret_cast<const uint32_t*>(line_ptr(c, ci) + (cb & lmask)));
+  e.val = __uint_as_float(ld_rlx(reinterpret_cast<const uint32_t*>(line_ptr(c, vi) + (vb & lmask))));
+  return e;
+}
+__device__ __forceinline__ float spmv_x(const spmv_args& a, int32_t col) {
+  return ((uint64_t)(uint32_t)col < a.g.V) ? a.x[col] : 0.0f;
+}
+
+// The rows of a wave's group (lane r holds row r's edge range [rs, re), the group's
+// edges are [e0, e1)) are folded edge-parallel: the lanes load 64 consecutive edges at a
+// time (four groups in flight: col and val from the pinned window, then x[col]) and the
+// wave walks them in CSR order through lane reads, closing a row when its end is reached.
+// Each row's result is therefore the fmaf chain of its edges in order, and the memory
+// work per edge is the same for hub rows and for short ones.  Returns row r's value in
+// lane r.
+__device__ __forceinline__ bool spmv_group(const dev_ctx& c, uint32_t q, const spmv_args& a, uint32_t* win,
+                                           uint64_t re, uint32_t nr, uint64_t e0, uint64_t e1, uint64_t pend,
+                                           spmv_pref& pf, float& yv) {
+  const uint64_t W = spmv_window(c);
+  uint32_t r = 0;                  // current row (uniform)
+  uint64_t er = rdlane64(re, 0);   // its end
+  float acc = 0.0f;
+  yv = 0.0f;
+  for (uint64_t w0 = e0; w0 < e1; w0 += W) {
+    const uint64_t w1 = (w0 + W < e1) ? w0 + W : e1;
+    uint32_t lc0, lv0;
+    chunk_t ch;
+    const uint64_t t_pin = now();
+    if (!spmv_pin(c, q, a, w0, w1, win, lc0, lv0, ch, pf)) return false;
+    const uint64_t t_pre = wtick(c, WS_T_WAIT, t_pin);
+    // this window is pinned: drop the request that brought it, and ask for the next one
+    // (up to `pend`, the end of the wave's run of groups) before computing on this one
+    spmv_drop(c, pf);
+    if (!spmv_prefetch(c, q, a, w1, (w1 + W < pend) ? w1 + W : pend, pf)) return false;
+    const uint64_t t_cons = wtick(c, WS_T_ISSUE, t_pre);
+    for (uint64_t k0 = w0; k0 < w1; k0 += 256) {
+      float v[4], xv[4];
+      int32_t col[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const uint64_t k = k0 + 64 * u + lane();
+        col[u] = -1;
+        v[u] = 0.0f;
+        if (k < w1) {
+          const spmv_edge e = spmv_load(c, a, win, lc0, lv0, k);
+          col[u] = e.col;
+          v[u] = e.val;
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) xv[u] = col[u] >= 0 ? spmv_x(a, col[u]) : 0.0f;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const uint64_t base = k0 + 64 * u;
+        if (base >= w1) break;
+        const uint32_t n = (w1 - base) < 64 ? (uint32_t)(w1 - base) : 64u;
+        for (uint32_t j = 0; j < n; ++j) {
+          while (base + j >= er) {  // row r is complete (rows without edges close at once)
+            if (lane() == r) yv = acc;
+            acc = 0.0f;
+            ++r;
+            er = rdlane64(re, r);
+          }
+          acc = __builtin_fmaf(__int_as_float(__builtin_amdgcn_readlane(__float_as_int(v[u]), j)),
+                               __int_as_float(__builtin_amdgcn_readlane(__float_as_int(xv[u]), j)), acc);
+        }
+      }
+    }
+    __builtin_amdgcn_wave_barrier();
+    chunk_release(c, ch, false);
+    wtick(c, WS_T_CONSUME, t_cons);
+  }
+  // the row being folded when the edges ran out; the rows after it have no edges
+  if (r < nr && lane() == r) yv = acc;
+  return true;
+}
+
+// Groups of 64 rows taken per grab: a wave streams through their edges in order, so the
+// next window to prefetch is the one after the current.
+constexpr uint64_t SPMV_RUN = 16;
 
 __global__ __launch_bounds__(WG) void k_spmv(dev_ctx c, launch_t li, spmv_args a) {
   __shared__ uint32_t win[WPB][16];
@@ -1072,71 +1246,42 @@ __global__ __launch_bounds__(WG) void k_spmv(dev_ctx c, launch_t li, spmv_args a
   const uint32_t wv = threadIdx.x / 64;
   const uint32_t uw = (blockIdx.x - li.service_blocks) * WPB + wv;
   const uint32_t q = uw % c.num_qp;
-  const uint32_t lmask = (1u << c.line_shift) - 1;
+  spmv_pref pf;
+  pf.held = false;
   for (;;) {
-    uint32_t g = 0;
-    if (lane() == 0) g = atomicAdd(a.ctr, 1u);
-    g = rdlane(g, 0);
-    const uint64_t r0 = (uint64_t)g * 64;
-    if (r0 >= a.g.V) break;
-    const uint32_t nr = (uint32_t)((a.g.V - r0) < 64 ? (a.g.V - r0) : 64);
-    const bool act = lane() < nr;
-    int64_t rs = 0, rend = 0;
-    if (!cached_read<int64_t>(c, q, act, a.g.rp_off + 8 * (r0 + lane()), rs)) goto done;
-    if (!cached_read<int64_t>(c, q, lane() == 0, a.g.rp_off + 8 * (r0 + nr), rend)) goto done;
-    rend = (int64_t)rdlane64((uint64_t)rend, 0);
-    int64_t re = (int64_t)shfl64((uint64_t)rs, (lane() + 1) & 63);
-    if (lane() == nr - 1) re = rend;
-    float acc = 0.0f;
-    const uint64_t E0 = rdlane64((uint64_t)rs, 0), E1 = (uint64_t)rend;
-    for (uint64_t w0 = E0; w0 < E1; w0 += 2048) {
-      const uint64_t w1 = (w0 + 2048 < E1) ? w0 + 2048 : E1;
-      const uint64_t cb0 = a.g.col_off + 4 * w0, cb1 = a.g.col_off + 4 * w1 - 1;
-      const uint64_t vb0 = a.g.val_off + 4 * w0, vb1 = a.g.val_off + 4 * w1 - 1;
-      const uint32_t lc0 = (uint32_t)(cb0 >> c.line_shift), nc = (uint32_t)(cb1 >> c.line_shift) - lc0 + 1;
-      const uint32_t lv0 = (uint32_t)(vb0 >> c.line_shift), nv = (uint32_t)(vb1 >> c.line_shift) - lv0 + 1;
-      // pin the window's lines (col lines in lanes [0, nc), val lines in [8, 8 + nv))
-      bool todo = lane() < nc || (lane() >= 8 && lane() < 8 + nv);
-      const uint32_t want = lane() < 8 ? lc0 + lane() : lv0 + (lane() - 8);
-      chunk_t ch;
-      spin_t sp;
-      bool held = false;
-      for (;;) {
-        ch.act = todo;
-        ch.line_id = want;
-        ch.off = 0;
-        if (!chunk_issue(c, ch, q, true, PIN_LINE)) goto done;
-        if (ballot(ch.act && ch.st == A_EAGAIN)) {
-          chunk_release(c, ch, false);
-          if (!sp.step(c, 0xF5000000ull)) goto done;
-          continue;
-        }
-        if (!chunk_wait(c, ch, true)) goto done;
-        held = true;
-        break;
-      }
-      if (todo) win[wv][lane() < 8 ? lane() : 8 + (lane() - 8)] = ch.idx;
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-      __builtin_amdgcn_wave_barrier();
-      if (act) {
-        const uint64_t k0 = (uint64_t)rs > w0 ? (uint64_t)rs : w0;
-        const uint64_t k1 = (uint64_t)re < w1 ? (uint64_t)re : w1;
-        for (uint64_t k = k0; k < k1; ++k) {
-          const uint64_t cb = a.g.col_off + 4 * k, vb = a.g.val_off + 4 * k;
-          const uint32_t ci = win[wv][(uint32_t)(cb >> c.line_shift) - lc0];
-          const uint32_t vi = win[wv][8 + (uint32_t)(vb >> c.line_shift) - lv0];
-          const int32_t col = *reinterpret_cast<const int32_t*>(line_ptr(c, ci) + (cb & lmask));
-          const float val = *reinterpret_cast<const float*>(line_ptr(c, vi) + (vb & lmask));
-          const float xv = ((uint64_t)col < a.g.V) ? a.x[col] : 0.0f;
-          acc = __builtin_fmaf(val, xv, acc);
-        }
-      }
-      __builtin_amdgcn_wave_barrier();
-      if (held) chunk_release(c, ch, false);
+    if (uw >= a.active) break;
+    uint64_t gi = 0;
+    if (lane() == 0) gi = add_rlx(counter(c, C_WORK), 1ull);
+    gi = rdlane64(gi, 0);
+    const uint64_t rr0 = gi * 64 * SPMV_RUN;
+    if (rr0 >= a.g.V) break;
+    const uint64_t rr1 = (a.g.V - rr0) < 64 * SPMV_RUN ? a.g.V : rr0 + 64 * SPMV_RUN;
+    auto drop = [&] { spmv_drop(c, pf); };
+    int64_t pend = 0;
+    if (!cached_read<int64_t>(c, q, lane() == 0, a.g.rp_off + 8 * rr1, pend, drop)) goto done;
+    pend = (int64_t)rdlane64((uint64_t)pend, 0);
+    for (uint64_t r0 = rr0; r0 < rr1; r0 += 64) {
+      const uint32_t nr = (uint32_t)((rr1 - r0) < 64 ? (rr1 - r0) : 64);
+      const bool act = lane() < nr;
+      int64_t rs = 0, rend = 0;
+      const uint64_t t_desc = now();
+      if (!cached_read<int64_t>(c, q, act, a.g.rp_off + 8 * (r0 + lane()), rs, drop)) goto done;
+      if (!cached_read<int64_t>(c, q, lane() == 0, a.g.rp_off + 8 * (r0 + nr), rend, drop)) goto done;
+      wtick(c, WS_T_DESC, t_desc);
+      rend = (int64_t)rdlane64((uint64_t)rend, 0);
+      int64_t re = (int64_t)shfl64((uint64_t)rs, (lane() + 1) & 63);
+      if (lane() == nr - 1) re = rend;
+      if (!act) re = rend;
+      float yv;
+      if (!spmv_group(c, q, a, win[wv], (uint64_t)re, nr, rdlane64((uint64_t)rs, 0), (uint64_t)rend,
+                      (uint64_t)pend, pf, yv))
+        goto done;
+      if (act) a.y[r0 + lane()] = yv;
     }
-    if (act) a.y[r0 + lane()] = acc;
+    spmv_drop(c, pf);
   }
 done:
+  spmv_drop(c, pf);
   user_wave_done(c, li);
 }
 
@@ -1915,17 +2060,16 @@ agile_status agile_spmv(agile_ctx ctx, agile_store store, const agile_csr* g, co
   if (!d_x || !d_y) return fail(ctx, AGILE_EINVAL, "spmv: null vector");
   if (ctx->cfg.line_bytes < 4096) return fail(ctx, AGILE_EINVAL, "spmv: line too small");
   hipStream_t hs = (hipStream_t)stream;
-  if ((s = ensure_scratch(ctx, 256, hs)) != AGILE_OK) return s;
   spmv_args a{};
   a.g = to_csr(g);
   a.x = d_x;
   a.y = d_y;
-  a.ctr = (uint32_t*)ctx->scratch;
-  HIPCHK(ctx, hipMemsetAsync(a.ctr, 0, 4, hs));
   const uint64_t by_cache = std::max<uint64_t>(1, ctx->d.num_lines / 32);
-  uint32_t uw = (uint32_t)std::min<uint64_t>({(g->num_vertices + 63) / 64, (uint64_t)user_wave_cap(ctx, KIND_READ),
-                                              by_cache});
-  uw = (uw + WPB - 1) / WPB * WPB;
+  // a wave pins at most two windows (the current one and the prefetch) of 2 x 8 lines
+  const uint32_t active = (uint32_t)std::min<uint64_t>(
+      {(g->num_vertices + 64 * SPMV_RUN - 1) / (64 * SPMV_RUN), (uint64_t)user_wave_cap(ctx, KIND_READ), by_cache});
+  a.active = std::max<uint32_t>(1, active);
+  const uint32_t uw = (a.active + WPB - 1) / WPB * WPB;
   launch_t li = make_launch(ctx, uw, true);
   hipLaunchKernelGGL(k_spmv, dim3(li.service_blocks + uw / WPB), dim3(WG), ctx->iso_lds, hs, ctx->d, li, a);
   HIPCHK(ctx, hipGetLastError());

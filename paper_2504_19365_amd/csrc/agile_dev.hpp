@@ -153,7 +153,7 @@ enum : uint32_t {
   // stage timers (ticks of s_memrealtime, summed over wavefronts; profile flag only)
   P_CTRL_FETCH, P_CTRL_COPY, P_CTRL_POST, P_CTRL_HOLD, P_CTRL_IDLE, P_CTRL_NOROOM, P_CQ_BUSY,
   P_CQ_IDLE, P_U_ISSUE, P_U_SUBMIT, P_U_WAIT, P_U_CONSUME, P_TOK_LEAD, P_TOK_N, P_U_DESC,
-  P_U_LIFE, C_SVC_EXIT, C_COUNT
+  P_U_LIFE, C_SVC_EXIT, C_IMG_EPOCH, C_COUNT
 };
 constexpr uint32_t CSTRIDE = 16;  // u64 per counter
 
@@ -255,19 +255,29 @@ __device__ __forceinline__ void raise_error(const dev_ctx& c, uint32_t code, uin
 
 // Bounded spin helper: returns false (and raises E_TIMEDOUT) when the deadline passes or
 // the context is aborted.
-// Exponential backoff (about 0.1 us doubling to about 7 us): thousands of waiting waves
-// must not flood the memory system that the controller's copies share.
+// Backoff: about 0.1 us doubling to about 3 us for the first few polls, then a sleep of
+// about an eighth of the time already waited (at most about 50 us), so a wave is never
+// woken more than ~12% late and thousands of waves that wait for queued I/O (milliseconds
+// when the device is saturated) do not flood the memory system that the controller's
+// copies share.
 struct spin_t {
   uint64_t t0;
   uint32_t n;
   __device__ spin_t() : t0(now()), n(0) {}
   __device__ __forceinline__ bool step(const dev_ctx& c, uint64_t info) {
     ++n;
-    const uint32_t reps = n < 7 ? (1u << (n - 1)) : 64u;
-    for (uint32_t r = 0; r < reps; ++r) __builtin_amdgcn_s_sleep(4);
+    if (n < 7) {
+      const uint32_t reps = 1u << (n - 1);
+      for (uint32_t r = 0; r < reps; ++r) __builtin_amdgcn_s_sleep(4);
+    } else {
+      // s_sleep(127) is 127 * 64 clocks, about 340 wall-clock ticks (10 ns each)
+      const uint64_t k = (now() - t0) / (8 * 340);
+      const uint32_t reps = k < 1 ? 1u : (k > 14 ? 14u : (uint32_t)k);
+      for (uint32_t r = 0; r < reps; ++r) __builtin_amdgcn_s_sleep(127);
+    }
     if (n >= 7 || (n & 3) == 0) {
       if (aborted(c)) return false;
-      if ((n & 255) == 0 && host_abort_poll(c)) return false;  // about every 2 ms
+      if ((n & 63) == 0 && host_abort_poll(c)) return false;  // every few ms
       if (now() - t0 > c.timeout_ticks) {
         if (lane() == ffs64(ballot(true))) raise_error(c, E_TIMEDOUT, info);
         return false;
@@ -473,6 +483,7 @@ __device__ __forceinline__ void controller(const dev_ctx& c, const launch_t& li,
   uint64_t busy = 0;
   uint32_t loops = 0, idle_rounds = 0;
   uint64_t host_seen = idle_since;
+  uint64_t img_epoch = ~0ull;  // unknown: the first copy of the launch drops stale lines
   for (;;) {
     if (((++loops) & 1023) == 0 && lane() == 0) count(c, C_CTRL_LOOPS, 1);
     const uint64_t t = now();
@@ -572,8 +583,23 @@ __device__ __forceinline__ void controller(const dev_ctx& c, const launch_t& li,
     const uint64_t tn = now();
     const uint64_t ready = ballot(pend && !p_copied && p_deadline <= tn);
     if (ready) {
-      fence_acq_sys();  // no stale copy of the store image (or of a line) survives in L2
+      // The store image changes during a launch only through WRITE commands.  A
+      // controller that copied writes releases them at system scope and then bumps the
+      // image epoch; one that sees a new epoch drops its L2's copies of host memory
+      // before copying (an acquire at system scope invalidates the whole L2 of its XCD,
+      // which costs every wave there, so it is not done per batch).  A READ of a block
+      // that was written back is submitted only after that write's completion has
+      // reached the reader, so the reader sees the new epoch.
+      const uint64_t ep = uni64(ld_rlx(counter(c, C_IMG_EPOCH)));
+      if (ep != img_epoch) {
+        fence_acq_sys();
+        img_epoch = ep;
+      }
       copy_cmds(c, ready, p_opc, p_nblk, p_status, p_slba, p_prp);
+      if (ballot(((ready >> lane()) & 1ull) && p_opc == OPC_WRITE && !p_status)) {
+        fence_rel_sys();
+        if (lane() == 0) add_rel(counter(c, C_IMG_EPOCH), 1ull);
+      }
       if ((ready >> lane()) & 1ull) p_copied = true;
       if (lane() == 0) count(c, C_CTRL_CMDS, __popcll(ready));
       progress = true;

@@ -30,11 +30,16 @@ def _graph(scale, ef, seed=0):
     (12, 16, dict(cache_bytes=64 << 10, assoc=4)),
     (16, 16, dict(cache_bytes=1 << 20, assoc=8)),
     (20, 16, dict(cache_bytes=64 << 20, assoc=16)),
+    # multi-block lines: one command moves 4 or 16 blocks; SpMV windows sized by the sets
+    (18, 16, dict(cache_bytes=4 << 20, assoc=4, line_bytes=16384)),
+    (20, 16, dict(cache_bytes=64 << 20, assoc=16, line_bytes=65536)),
 ])
 def test_bfs_and_spmv_bit_exact(scale, ef, cache_kw):
     import torch
     buf, g, row_ptr, col, val = _graph(scale, ef)
-    ctx = agile.Context(line_bytes=4096, num_qp=8, qp_depth=256, timeout_ns=int(10e9), **cache_kw)
+    kw = dict(line_bytes=4096, num_qp=8, qp_depth=256, timeout_ns=int(10e9))
+    kw.update(cache_kw)
+    ctx = agile.Context(**kw)
     try:
         ctx.open_store(buf)
         src = gen.bfs_source(0, row_ptr)
