@@ -821,14 +821,17 @@ __device__ __forceinline__ void bwd_wave(const dev_ctx& c, const bwd_args& a, ui
         ch.off = (uint32_t)(byte & ((1ull << c.line_shift) - 1));
       }
       if (!chunk_issue(c, ch, q, true, PIN_LINE)) return;
-      if (!chunk_wait(c, ch, true)) return;
+      // No acquire (it would drop the whole L2 of the XCD): within a launch a row has one
+      // writer, this wave, so its current value is the one the fill (or an earlier
+      // launch) left, read below with device-coherent loads past any stale L2 copy.
+      if (!chunk_wait(c, ch, false)) return;
       // a line pinned while its earlier write-back was in flight: wait for it to finish
+      // (the write-back only reads the line)
       bool wbw = ch.act && st_ok(ch.st) && ch.leader == lane();
       while (ballot(wbw)) {
         if (wbw && m_state(ld_rlx(c.meta + ch.idx)) != ST_WRITEBACK) wbw = false;
         if (ballot(wbw) && !sp.step(c, 0xB1000000ull | ch.idx)) return;
       }
-      fence_acq();
       const uint64_t okm = ballot(ch.act && st_ok(ch.st));
       for (uint64_t m = okm; m; m &= m - 1) {
         const uint32_t k = ffs64(m);
@@ -860,8 +863,10 @@ __device__ __forceinline__ void bwd_wave(const dev_ctx& c, const bwd_args& a, ui
         const uint32_t off = rdlane(ch.off, k);
         float* w = reinterpret_cast<float*>(line_ptr(c, idx) + off) + d0;
         if (mine) {
+          float wv[VPL];
+          ld_row<VPL>(w, wv);
 #pragma unroll
-          for (int v = 0; v < VPL; ++v) w[v] = __builtin_fmaf(-a.lr, acc[v], w[v]);
+          for (int v = 0; v < VPL; ++v) w[v] = __builtin_fmaf(-a.lr, acc[v], wv[v]);
         }
       }
       // mark the written lines MODIFIED (leaders), then unpin with release ordering
