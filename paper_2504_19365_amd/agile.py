@@ -376,7 +376,8 @@ class Context:
                      "ctrl_loops", "cq_loops", "wrows", "t_ctrl_fetch", "t_ctrl_copy", "t_ctrl_post",
                      "t_ctrl_hold", "t_ctrl_idle", "ctrl_noroom", "t_cq_busy", "t_cq_idle",
                      "t_u_issue", "t_u_submit", "t_u_wait", "t_u_consume", "tok_lead",
-                     "tok_n", "t_u_desc", "t_u_life", "svc_exit", "img_epoch")
+                     "tok_n", "t_u_desc", "t_u_life", "svc_exit", "img_epoch", "work_p1",
+                     "work_p2", "work_p3", "work_p4", "work_p5", "work_p6", "work_p7")
 
     def debug_counters(self) -> dict:
         n = len(self.COUNTER_NAMES)

@@ -49,20 +49,24 @@ struct embbag_args {
 };
 
 // Per-wave state of the bag source.  Bags [0, 2A) of a launch with A active waves are
-// dealt out statically (wave u gets bags u and u + A), so that no wave starts behind a
-// queue of thousands of same-address atomics; the rest are grabbed one at a time from
-// the work counter.  The wave holds the next bag it will work on, taken (and its lookup
-// range loaded) as soon as the previous one was taken, so that the grab's atomic and the
-// offset loads travel while the current bag is processed (except for the last bags of a
-// launch).  A held bag whose request is not yet published stays held.  After the first
-// failed grab the wave grabs no more.  The work counter starts every launch at zero.
+// dealt out statically (wave u starts with bags u and u + A); the rest are taken
+// dynamically from WORK_PARTS partitions (bag b in partition (b - 2A) mod WORK_PARTS,
+// each with its own counter): a wave starts at partition u mod WORK_PARTS and moves on
+// once its partition is used up, so no wave starts behind thousands of same-address
+// atomics and the last bags still go to whichever waves are free.  The wave holds the next bag it
+// will work on, taken (and its lookup range loaded) as soon as the previous one was
+// taken, so that the atomic and the offset loads travel while the current bag is
+// processed (except near the end of the launch).  A held bag whose request is not yet
+// published stays held.  The work counters start every launch at zero.
 struct src_state {
   int64_t g;       // held bag, or -1
   int64_t j0, j1;  // its lookups [j0, j1)
   bool exhausted;
   uint32_t uw;     // this wave's index among the active waves
-  uint32_t dealt;  // static bags looked at so far (0..2)
+  uint32_t dealt;  // static bags looked at so far (0..STATIC_ROUNDS)
+  uint32_t tried;  // partitions found used up so far
 };
+constexpr uint32_t STATIC_ROUNDS = 2;
 
 __device__ __forceinline__ float fK(float v, uint32_t K) {
   for (uint32_t k = 0; k < K; ++k) v = __builtin_fmaf(v, 0.999f, 0.001f);
@@ -76,13 +80,6 @@ struct desc_t {
   uint32_t n;
   bool valid, last;
 };
-
-__device__ __forceinline__ int64_t grab(const dev_ctx& c, const launch_t& li) {
-  uint64_t v = 0;
-  if (lane() == 0) v = add_rlx(counter(c, C_WORK), 1ull);
-  v = rdlane64(v, 0);
-  return (int64_t)v;
-}
 
 template <int VPL>
 __device__ __forceinline__ void write_bag(const dev_ctx& c, const embbag_args& a, int64_t g,
@@ -129,9 +126,9 @@ __device__ __forceinline__ bool wait_published(const dev_ctx& c, const embbag_ar
 __device__ __forceinline__ void hold_next(const dev_ctx& c, const launch_t& li, const embbag_args& a,
                                           src_state& ss) {
   const int64_t A = (int64_t)a.active_waves, nb = (int64_t)a.nbags;
-  const int64_t dealt = 2 * A < nb ? 2 * A : nb;
+  const int64_t dealt = (int64_t)STATIC_ROUNDS * A < nb ? (int64_t)STATIC_ROUNDS * A : nb;
   int64_t g = -1;
-  while (ss.dealt < 2) {
+  while (ss.dealt < STATIC_ROUNDS) {
     const int64_t s = (int64_t)ss.uw + (int64_t)ss.dealt * A;
     ++ss.dealt;
     if (s < dealt) {
@@ -139,17 +136,21 @@ __device__ __forceinline__ void hold_next(const dev_ctx& c, const launch_t& li, 
       break;
     }
   }
+  while (g < 0 && ss.tried < WORK_PARTS) {
+    const uint32_t p = (ss.uw + ss.tried) % WORK_PARTS;
+    uint64_t v = 0;
+    if (lane() == 0) v = add_rlx(counter(c, work_counter(p)), 1ull);
+    v = rdlane64(v, 0);
+    const int64_t b = dealt + (int64_t)v * WORK_PARTS + p;
+    if (b < nb)
+      g = b;
+    else
+      ++ss.tried;
+  }
   if (g < 0) {
-    const int64_t v = grab(c, li);
-    if (v < 0 || dealt + v >= nb) {
-      // below zero: the work counter is behind this launch's base (never in a healthy
-      // context); report it instead of indexing with it
-      if (v < 0 && lane() == 0) raise_error(c, E_STATE, 0xE0000000ull);
-      ss.exhausted = true;
-      ss.g = -1;
-      return;
-    }
-    g = dealt + v;
+    ss.exhausted = true;
+    ss.g = -1;
+    return;
   }
   ss.g = g;
   if (a.gather) {
@@ -381,7 +382,7 @@ __device__ __forceinline__ void embbag_wave(const dev_ctx& c, const launch_t& li
   for (int v = 0; v < VPL; ++v) acc[v] = 0.0f;
   desc_t none;
   none.valid = false;
-  src_state ss{-1, 0, 0, false, uw, 0};
+  src_state ss{-1, 0, 0, false, uw, 0, 0};
   desc_t dc = next_desc<VPL>(c, li, a, none, ss, true);
   if (!dc.valid) return;
   chunk_t cc, cn;
@@ -1838,7 +1839,8 @@ agile_status agile_get_stats(agile_ctx ctx, agile_stats* out, int reset) {
   out->consumed = g(C_AUX1);
   out->rows_updated = g(C_WROWS);
   if (reset) {
-    const uint32_t keep[] = {C_SUBMITTED, C_COMPLETED, C_USER_DONE, C_WORK, C_SVC_EXIT};
+    const uint32_t keep[] = {C_SUBMITTED, C_COMPLETED, C_USER_DONE, C_WORK, C_SVC_EXIT, C_IMG_EPOCH,
+                             C_WORK_P1, C_WORK_P2, C_WORK_P3, C_WORK_P4, C_WORK_P5, C_WORK_P6, C_WORK_P7};
     for (uint32_t i = 0; i < C_COUNT; ++i) {
       if (std::find(std::begin(keep), std::end(keep), i) != std::end(keep)) continue;
       HIPCHK(ctx, hipMemset(ctx->d.cnt + (size_t)i * CSTRIDE, 0, 8));

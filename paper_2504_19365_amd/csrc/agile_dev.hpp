@@ -153,7 +153,9 @@ enum : uint32_t {
   // stage timers (ticks of s_memrealtime, summed over wavefronts; profile flag only)
   P_CTRL_FETCH, P_CTRL_COPY, P_CTRL_POST, P_CTRL_HOLD, P_CTRL_IDLE, P_CTRL_NOROOM, P_CQ_BUSY,
   P_CQ_IDLE, P_U_ISSUE, P_U_SUBMIT, P_U_WAIT, P_U_CONSUME, P_TOK_LEAD, P_TOK_N, P_U_DESC,
-  P_U_LIFE, C_SVC_EXIT, C_IMG_EPOCH, C_COUNT
+  P_U_LIFE, C_SVC_EXIT, C_IMG_EPOCH,
+  // work counters of partitions 1..7 (partition 0 is C_WORK)
+  C_WORK_P1, C_WORK_P2, C_WORK_P3, C_WORK_P4, C_WORK_P5, C_WORK_P6, C_WORK_P7, C_COUNT
 };
 constexpr uint32_t CSTRIDE = 16;  // u64 per counter
 
@@ -214,6 +216,11 @@ constexpr uint32_t FLAG_PROFILE = 0x4;
 // any distance, with either sign).
 constexpr uint32_t TOK_FRAC = 20;
 constexpr uint32_t WPB = WG / 64;
+
+// Dynamic work is split over WORK_PARTS counters, each in its own 128-byte segment, so
+// that thousands of waves taking work do not all meet at one address.
+constexpr uint32_t WORK_PARTS = 8;
+__device__ __forceinline__ uint32_t work_counter(uint32_t p) { return p == 0 ? C_WORK : C_WORK_P1 + (p - 1); }
 
 __device__ __forceinline__ uint64_t* counter(const dev_ctx& c, uint32_t i) {
   return c.cnt + (size_t)i * CSTRIDE;
@@ -837,7 +844,7 @@ __device__ __forceinline__ void run_service(const dev_ctx& c, const launch_t& li
     const uint64_t n = add_acqrel(counter(c, C_SVC_EXIT), 1ull) + 1;
     if (n == (uint64_t)li.n_ctrl + li.n_cq) {
       st_rlx(counter(c, C_USER_DONE), 0ull);
-      st_rlx(counter(c, C_WORK), 0ull);
+      for (uint32_t p = 0; p < WORK_PARTS; ++p) st_rlx(counter(c, work_counter(p)), 0ull);
       st_rel(counter(c, C_SVC_EXIT), 0ull);
     }
   }
