@@ -76,8 +76,10 @@ def parse():
                          "reference kernel that scales the HBM traffic counters)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
-    ap.add_argument("--profile-only", action="store_true",
-                    help="run warmup + timed steps only (for profilers)")
+    ap.add_argument("--profile-only", nargs="?", const="step", default=None,
+                    choices=("step", "hit"),
+                    help="for profilers: 'step' runs the warm-up and timed steps only, 'hit' "
+                         "the hit-path replay only")
     ap.add_argument("--extras", default="serve",
                     help="comma list of extra measurements: serve, bwd, graph, randread "
                          "('' = none)")
@@ -379,6 +381,32 @@ def main():
         dst_c.copy_(src_c)
         torch.cuda.synchronize()
         del src_c, dst_c
+
+    if args.profile_only == "hit":
+        last = nb - 1
+        hctx = agile.Context(**{**cfg, "cache_bytes": int(args.hit_cache_gib * 2**30)})
+        hctx.open_store(buf)
+        htb = hctx.tables(rows, dim, T)
+        hout = torch.empty((B * T, dim), dtype=torch.float32, device="cuda")
+        off_b, idx_b, n_b = batches[last]
+        hctx.embbag_forward(htb, idx_b, off_b, B, args.K, hout)
+        hctx.sync()
+        h0 = hctx.stats()
+        ms = []
+        for _ in range(5):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            hctx.embbag_forward(htb, idx_b, off_b, B, args.K, hout)
+            e1.record(stream)
+            hctx.sync()
+            ms.append(e0.elapsed_time(e1))
+        h1 = hctx.stats()
+        print(json.dumps({"profile_only": "hit", "ms": ms, "misses": h1["misses"] - h0["misses"],
+                          "lookups": n_b}))
+        hctx.close_store()
+        hctx.shutdown()
+        return
 
     # ---- timed step: asynchronous mode
     cold()
