@@ -922,7 +922,7 @@ __device__ __forceinline__ bool cached_read(const dev_ctx& c, uint32_t q, bool a
       ch.line_id = (uint32_t)(byte >> c.line_shift);
       ch.off = (uint32_t)(byte & ((1ull << c.line_shift) - 1));
     }
-    if (!chunk_issue(c, ch, q, true, PIN_NONE)) return false;
+    if (!chunk_issue(c, ch, q, true, PIN_NONE, false)) return false;
     if (!chunk_wait(c, ch, false)) return false;
     const bool got = todo && st_ok(ch.st);
     T v = 0;

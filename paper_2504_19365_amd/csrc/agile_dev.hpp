@@ -1111,12 +1111,15 @@ __device__ __forceinline__ void dedup(chunk_t& ch, bool part) {
 
 // Acquire + submit for the leaders of `ch`.  On return every active lane has st in
 // {A_HIT, A_JOIN, A_MISS, A_EAGAIN} (or the context aborted).  Counts stats.
+// `probe_first` (optimistic readers only) suits lanes that mostly want distinct lines
+// (embedding rows); readers whose lanes share lines (consecutive CSR entries) coalesce
+// first and probe once per distinct line.
 __device__ __forceinline__ bool chunk_issue(const dev_ctx& c, chunk_t& ch, uint32_t q, bool count_stats,
-                            uint32_t pin_mode = PIN_LINE) {
+                            uint32_t pin_mode = PIN_LINE, bool probe_first = true) {
   const uint64_t t_issue = now();
   uint32_t st = A_NONE, idx = 0, gen = 0;
   bool part = ch.act;  // lanes that go through dedup and the acquire loop
-  if (pin_mode == PIN_NONE) {
+  if (pin_mode == PIN_NONE && probe_first) {
     // optimistic readers: every lane first probes its own set; a resident or in-flight
     // line is taken unpinned on the spot, and only the lanes left over elect leaders
     if (ch.act) {
