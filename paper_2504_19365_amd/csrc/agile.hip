@@ -553,8 +553,7 @@ template <int VPL>
 __global__ __launch_bounds__(WG) void k_serve(dev_ctx c, launch_t li, embbag_args a, uint32_t nreq,
                                               uint32_t* pub_dev) {
   if (blockIdx.x < li.service_blocks) {
-    const uint32_t sw = blockIdx.x * WPB + threadIdx.x / 64;
-    if (sw == li.n_ctrl + li.n_cq) {
+    if (service_role(li) == li.n_ctrl + li.n_cq) {
       mirror_published(c, a, nreq, pub_dev);
       return;
     }
@@ -1417,13 +1416,14 @@ int occupancy(agile_ctx ctx, int kind) {
 
 // User wavefronts a launch of `kind` may use so that the whole grid (service included)
 // is resident at once.
-uint32_t user_wave_cap(agile_ctx ctx, int kind) {
+uint32_t user_wave_cap(agile_ctx ctx, int kind, uint32_t service_blocks) {
   const uint64_t blocks = (uint64_t)occupancy(ctx, kind) * ctx->cu_count;
-  uint64_t ub = blocks > ctx->service_blocks ? blocks - ctx->service_blocks : 1;
+  uint64_t ub = blocks > service_blocks ? blocks - service_blocks : 1;
   uint64_t uw = ub * WPB;
   if (ctx->cfg.max_user_waves && uw > ctx->cfg.max_user_waves) uw = ctx->cfg.max_user_waves;
   return (uint32_t)std::max<uint64_t>(uw, 1);
 }
+uint32_t user_wave_cap(agile_ctx ctx, int kind) { return user_wave_cap(ctx, kind, ctx->service_blocks); }
 
 agile_status check_usable(agile_ctx ctx) {
   if (!ctx) return AGILE_EINVAL;
@@ -1593,7 +1593,7 @@ agile_status agile_init(const agile_config* cfg_in, agile_ctx* out) {
   }
   ctx->n_ctrl = n_ctrl;
   ctx->n_cq = n_cq;
-  ctx->service_blocks = (n_ctrl + n_cq + WPB - 1) / WPB;
+  ctx->service_blocks = service_blocks_for(n_ctrl + n_cq);
 
   dev_ctx& d = ctx->d;
   memset(&d, 0, sizeof(d));
@@ -2275,11 +2275,13 @@ agile_status agile_serve(agile_ctx ctx, agile_store store, const agile_tables* t
   // EAGAIN drain keeps an over-subscribed cache deadlock-free, only slower)
   const uint64_t by_cache = std::max<uint64_t>(1, ctx->d.num_lines / 16);
   const uint64_t want = opts && opts->user_waves ? opts->user_waves : by_cache;
-  const uint32_t active = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(want, (uint64_t)user_wave_cap(ctx, kind)));
+  const uint32_t svc_blocks = service_blocks_for(ctx->n_ctrl + ctx->n_cq + 1);  // + the publication mirror
+  const uint32_t active =
+      (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(want, (uint64_t)user_wave_cap(ctx, kind, svc_blocks)));
   const uint32_t uw = (active + WPB - 1) / WPB * WPB;
   a.active_waves = active;
   launch_t li = make_launch(ctx, uw, true);
-  li.service_blocks = (ctx->n_ctrl + ctx->n_cq + 1 + WPB - 1) / WPB;  // + the publication mirror
+  li.service_blocks = svc_blocks;
   const dim3 grid(li.service_blocks + uw / WPB);
   if (kind == KIND_SERVE1)
     hipLaunchKernelGGL(k_serve<1>, grid, dim3(WG), ctx->iso_lds, hs, ctx->d, li, a, (uint32_t)nreq, (uint32_t*)(sb + o_pub));

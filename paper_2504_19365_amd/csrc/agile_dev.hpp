@@ -216,6 +216,17 @@ constexpr uint32_t FLAG_PROFILE = 0x4;
 // any distance, with either sign).
 constexpr uint32_t TOK_FRAC = 20;
 constexpr uint32_t WPB = WG / 64;
+// Workgroups are dealt to the 8 XCDs round robin, and each XCD has its own L2 and its
+// own share of the fabric path to host memory.  Service roles are numbered across the
+// service workgroups first (role = wave * service_blocks + workgroup) and there are at
+// least this many service workgroups, so the controller wavefronts, which do all the
+// PCIe copying, are spread over every XCD.
+constexpr uint32_t XCDS = 8;
+__host__ __device__ constexpr uint32_t service_blocks_for(uint32_t service_waves) {
+  return (service_waves + WPB - 1) / WPB > (service_waves < XCDS ? service_waves : XCDS)
+             ? (service_waves + WPB - 1) / WPB
+             : (service_waves < XCDS ? service_waves : XCDS);
+}
 
 // Dynamic work is split over WORK_PARTS counters, each in its own 128-byte segment, so
 // that thousands of waves taking work do not all meet at one address.
@@ -825,8 +836,11 @@ __device__ __forceinline__ void completion(const dev_ctx& c, const launch_t& li,
   }
 }
 
+__device__ __forceinline__ uint32_t service_role(const launch_t& li) {
+  return (threadIdx.x / 64) * li.service_blocks + blockIdx.x;
+}
 __device__ __forceinline__ void run_service(const dev_ctx& c, const launch_t& li) {
-  const uint32_t sw = blockIdx.x * WPB + threadIdx.x / 64;
+  const uint32_t sw = service_role(li);
   if (li.prio) __builtin_amdgcn_s_setprio(3);
   if (lane() == 0 && sw < li.n_ctrl + li.n_cq) count(c, C_SVC_START, 1);
   if (sw < li.n_ctrl)
