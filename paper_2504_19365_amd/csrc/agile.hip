@@ -2020,7 +2020,12 @@ agile_status agile_bfs(agile_ctx ctx, agile_store store, const agile_csr* g, uin
   uint32_t nF = 1;
   int32_t L = 0;
   uint32_t levels = 1;  // levels that hold at least one vertex
-  const uint64_t by_cache = std::max<uint64_t>(1, ctx->d.num_lines / 128);
+  // user waves per level: a 128th of the lines, and at most BFS_MAX_WAVES (past that,
+  // more waves walking the edges while the controllers copy make every memory access of
+  // the level slower than the extra latency hiding gains: measured on RMAT scale 24 and
+  // 26 with 4 and 16 KiB lines, 1536 waves beat both 1024 and the full grid)
+  constexpr uint64_t BFS_MAX_WAVES = 1536;
+  const uint64_t by_cache = std::max<uint64_t>(1, std::min<uint64_t>(ctx->d.num_lines / 128, BFS_MAX_WAVES));
   while (nF > 0) {
     a.F = F;
     a.N = N;
