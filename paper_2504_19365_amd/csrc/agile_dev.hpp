@@ -877,13 +877,21 @@ __device__ __forceinline__ uint32_t ws_counter(uint32_t k) {
                                       P_U_ISSUE, P_U_SUBMIT, P_U_WAIT, P_U_CONSUME, P_U_DESC, P_U_LIFE};
   return map[k];
 }
-__device__ __forceinline__ uint64_t* wave_stats() {
-  __shared__ uint64_t ws[WPB][WS_COUNT];
-  return ws[threadIdx.x / 64];
+struct wg_stats_t {
+  uint64_t ws[WPB][WS_COUNT];  // each wave's own slots
+  uint32_t waves_done;         // waves of the workgroup that have finished
+};
+__device__ __forceinline__ wg_stats_t& wg_stats() {
+  __shared__ wg_stats_t s;
+  return s;
 }
-// Called by every user wavefront before its first chunk.
+__device__ __forceinline__ uint64_t* wave_stats() { return wg_stats().ws[threadIdx.x / 64]; }
+// Called by every wavefront of a user workgroup (all of them, unconditionally) before
+// its first chunk.
 __device__ __forceinline__ void user_wave_begin() {
   if (lane() < WS_COUNT) wave_stats()[lane()] = lane() == WS_T_LIFE ? (uint64_t)0 - now() : 0;
+  if (threadIdx.x == 0) wg_stats().waves_done = 0;
+  __syncthreads();
 }
 // Lane 0 only.
 __device__ __forceinline__ void wcount(uint32_t k, uint64_t v) {
@@ -897,15 +905,29 @@ __device__ __forceinline__ uint64_t wtick(const dev_ctx& c, uint32_t k, uint64_t
   return n;
 }
 
-// Called by every user wavefront when it is done with this launch (only launches with
-// service wavefronts count the waves).
+// Called by every user wavefront when it is done with this launch.  The last wave of the
+// workgroup to finish adds the workgroup's totals to the device counters and reports
+// its WPB waves done (only launches with service wavefronts count them): thousands of
+// waves each adding to the same few device-scope words at the end of a launch had
+// serialised there for tens of microseconds.
 __device__ __forceinline__ void user_wave_done(const dev_ctx& c, const launch_t& li) {
+  wg_stats_t& s = wg_stats();
+  if (lane() == WS_T_LIFE) {
+    uint64_t& v = wave_stats()[WS_T_LIFE];
+    v = profiling(c) ? v + now() : 0;
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  uint32_t n = 0;
+  if (lane() == 0)
+    n = __hip_atomic_fetch_add(&s.waves_done, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_WORKGROUP);
+  if (rdlane(n, 0) != WPB - 1) return;
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
   if (lane() < WS_COUNT) {
-    uint64_t v = wave_stats()[lane()];
-    if (lane() == WS_T_LIFE) v = profiling(c) ? v + now() : 0;
+    uint64_t v = 0;
+    for (uint32_t w = 0; w < WPB; ++w) v += s.ws[w][lane()];
     if (v) add_rlx(counter(c, ws_counter(lane())), v);
   }
-  if (lane() == 0 && li.service_blocks) add_rel(counter(c, C_USER_DONE), 1ull);
+  if (lane() == 0 && li.service_blocks) add_rel(counter(c, C_USER_DONE), (uint64_t)WPB);
 }
 
 // ------------------------------------------------------------------ cache (Sec. 3.4)
