@@ -88,7 +88,8 @@ def parse():
     return ap.parse_args()
 
 
-SERVE_TUNED = dict(line_bytes=4096, assoc=4, num_qp=64, qp_depth=1024, ctrl_waves=64)
+SERVE_TUNED = dict(line_bytes=4096, assoc=4, num_qp=64, qp_depth=1024, ctrl_waves=16)
+SERVE_TUNED_OPTS = dict(user_waves=512, max_inflight_lines=512)
 
 
 def measure_serve(agile, gen, seconds: float, log):
@@ -101,10 +102,10 @@ def measure_serve(agile, gen, seconds: float, log):
     rows, dim = 65536, 64
     buf = agile.PinnedBuffer(rows * dim * 4)
     gen.fill_table(buf.ptr, 0, rows, dim, 0)
-    res = {"tuned_geometry": {**SERVE_TUNED, "user_waves": 1024, "max_inflight_lines": 2048},
+    res = {"tuned_geometry": {**SERVE_TUNED, **SERVE_TUNED_OPTS},
            "points": []}
     runs = [("default", dict(line_bytes=4096, assoc=8, num_qp=16, qp_depth=1024), {}, 20000.0)]
-    runs += [("tuned", SERVE_TUNED, dict(user_waves=1024, max_inflight_lines=2048), r)
+    runs += [("tuned", SERVE_TUNED, SERVE_TUNED_OPTS, r)
              for r in (1000.0, 2500.0, 5000.0, 10000.0, 20000.0)]
     for label, geom, opts, rate in runs:
         nreq = max(100, int(rate * seconds))

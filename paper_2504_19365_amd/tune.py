@@ -1,8 +1,9 @@
 """Autotuner for the block-I/O path's geometry.
 
 Staged coordinate descent over line size, associativity, queue-pair count, queue depth,
-the number of emulated-controller wavefronts and the number of user wavefronts the
-serving kernel runs.  Each trial builds a context with the candidate
+the number of emulated-controller wavefronts, the number of user wavefronts the
+serving kernel runs and the admission budget of cache lines (0 = as many as the cache
+holds).  Each trial builds a context with the candidate
 geometry over the same store, runs a short closed-loop serving session (every request
 available at once, so the session measures sustainable throughput) and scores it in
 lookups per second.  Points the library rejects (for example fewer lines than ways) are
@@ -23,10 +24,11 @@ SPACE = {
     "num_qp": [4, 8, 16, 32, 64],
     "qp_depth": [256, 512, 1024, 2048, 4096],
     "ctrl_waves": [16, 32, 64, 128],
-    "user_waves": [16, 32, 64, 128, 256],
+    "user_waves": [16, 32, 64, 128, 256, 512, 1024],
+    "max_inflight_lines": [0, 256, 512, 768, 1024, 2048],
 }
 START = {"line_bytes": 4096, "assoc": 8, "num_qp": 16, "qp_depth": 1024, "ctrl_waves": 64,
-         "user_waves": 16}
+         "user_waves": 16, "max_inflight_lines": 0}
 
 
 def _config(point: dict, cache_bytes: int, latency_ns: int, iops_cap: int) -> dict:
@@ -50,7 +52,8 @@ def serve_trial(image, rows: int, dim: int, point: dict, stream, cache_bytes: in
         ctx.open_store(image)
         tb = ctx.tables(rows, dim, 1)
         _, lat, rep = ctx.serve(tb, K, np.zeros_like(arrival), req_bag0, bag_off, idx, mode=mode,
-                                user_waves=point.get("user_waves", 0))
+                                user_waves=point.get("user_waves", 0),
+                                max_inflight_lines=point.get("max_inflight_lines", 0))
         ctx.close_store()
     finally:
         ctx.shutdown()
