@@ -231,8 +231,9 @@ def measure_bwd(agile, gen, log, steps: int = 4):
 def measure_graph(agile, gen, oracle, scale: int, log):
     """Out-of-HBM graph: RMAT(0.57, 0.19, 0.19) with 2^scale vertices and 16 edges per
     vertex held in the store, 4 GiB cache, no emulated latency or cap (PCIe bound).
-    BFS uses 16 KiB lines and SpMV 64 KiB lines (the configuration leaves the line size
-    open; these were the fastest of 4, 16 and 64 KiB for each).  BFS levels are validated
+    BFS uses 16 KiB lines and SpMV 128 KiB lines (the configuration leaves the line size
+    open; these were the fastest of 4 KiB to 64 KiB for BFS and of 4 KiB to 256 KiB for
+    SpMV at scale 24 and 26).  BFS levels are validated
     with the Graph500 rules and SpMV sampled rows against the oracle, bit-exact."""
     import torch
     abc = (0.57, 0.19, 0.19)
@@ -254,7 +255,7 @@ def measure_graph(agile, gen, oracle, scale: int, log):
         ctx.open_store(buf)
         return ctx
 
-    bfs_line, spmv_line = 16384, 65536
+    bfs_line, spmv_line = 16384, 131072
     ctx = context(bfs_line)
     ctx.invalidate()
     ctx.stats(reset=True)
