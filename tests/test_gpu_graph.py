@@ -33,6 +33,10 @@ def _graph(scale, ef, seed=0):
     # multi-block lines: one command moves 4 or 16 blocks; SpMV windows sized by the sets
     (18, 16, dict(cache_bytes=4 << 20, assoc=4, line_bytes=16384)),
     (20, 16, dict(cache_bytes=64 << 20, assoc=16, line_bytes=65536)),
+    # 32 blocks per command (the SpMV line size of the scale-26 measurement), roomy and
+    # with 16 lines in 4 sets
+    (20, 16, dict(cache_bytes=64 << 20, assoc=16, line_bytes=131072)),
+    (18, 16, dict(cache_bytes=2 << 20, assoc=4, line_bytes=131072)),
 ])
 def test_bfs_and_spmv_bit_exact(scale, ef, cache_kw):
     import torch
