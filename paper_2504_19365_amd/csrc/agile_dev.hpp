@@ -223,10 +223,13 @@ constexpr uint32_t WPB = WG / 64;
 // PCIe copying, are spread over every XCD.
 constexpr uint32_t XCDS = 8;
 __host__ __device__ constexpr uint32_t service_blocks_for(uint32_t service_waves) {
-  return (service_waves + WPB - 1) / WPB > (service_waves < XCDS ? service_waves : XCDS)
-             ? (service_waves + WPB - 1) / WPB
-             : (service_waves < XCDS ? service_waves : XCDS);
+  const uint32_t packed = (service_waves + WPB - 1) / WPB;               // WPB roles per group
+  const uint32_t spread = service_waves < XCDS ? service_waves : XCDS;  // one group per XCD
+  return packed > spread ? packed : spread;
 }
+static_assert(service_blocks_for(80) == 8 && service_blocks_for(144) == 9 && service_blocks_for(2) == 2 &&
+                  service_blocks_for(1) == 1,
+              "service workgroups: at least one per XCD, at most WPB roles each");
 
 // Dynamic work is split over WORK_PARTS counters, each in its own 128-byte segment, so
 // that thousands of waves taking work do not all meet at one address.
