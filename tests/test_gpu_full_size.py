@@ -1,0 +1,130 @@
+"""GPU parity at the full sizes of the measured configurations, in the launch
+configuration the benchmark times (default wave counts, the same cache and queue
+geometry).  Outputs the oracle can compute one by one are sampled; where the whole result
+is cheap to check (the write path's store image, BFS levels through the Graph500 rules,
+which pin exact distances) all of it is checked.  Expected values come from the oracle."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2504_19365_amd import agile, gen
+
+from gpu_helpers import check_quiescent_invariants, cuda, table_store
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.timeout(300)
+def test_dlrm_step_full_size_sampled_bags():
+    """8 tables of 4,194,304 x 128 fp32 (16 GiB store), 80 us per command, 1.5M IOPS cap,
+    2 GiB 16-way cache, 16 queue pairs of depth 1024; batch 2048 x 8 bags of U[1,80]
+    Zipf(1.05) rows.  A cold asynchronous launch and a synchronous one on the same batch
+    give identical outputs, and 256 sampled bags equal the oracle bit for bit."""
+    import torch
+    rows, dim, T, B = 4194304, 128, 8, 2048
+    buf = table_store(rows, dim, list(range(T)))
+    ctx = agile.Context(cache_bytes=2 << 30, line_bytes=4096, assoc=16, num_qp=16, qp_depth=1024,
+                        latency_ns=80_000, iops_cap=1_500_000, timeout_ns=int(30e9))
+    try:
+        ctx.open_store(buf)
+        tb = ctx.tables(rows, dim, T)
+        off, idx = gen.embbag_batch(gen.zipf_cum(rows, 1.05), B, T, 1, 80, seed=1000)
+        d_off, d_idx = cuda(off), cuda(idx)
+        out_a = torch.empty((B * T, dim), dtype=torch.float32, device="cuda")
+        out_s = torch.empty_like(out_a)
+        ctx.invalidate()
+        ctx.stats(reset=True)
+        ctx.embbag_forward(tb, d_idx, d_off, B, 0, out_a, mode=agile.MODE_ASYNC)
+        ctx.sync()
+        st = ctx.stats()
+        assert st["consumed"] == idx.size and st["misses"] > 0
+        ctx.embbag_forward(tb, d_idx, d_off, B, 0, out_s, mode=agile.MODE_SYNC)
+        ctx.sync()
+        assert torch.equal(out_a, out_s)
+        sample = np.sort(np.random.default_rng(5).choice(B * T, 256, replace=False))
+        ref = oracle.embbag_forward(buf.array, rows, dim, T, idx, off, B, 0, bags=sample)
+        got = out_a.cpu().numpy()[sample]
+        assert np.array_equal(got.view(np.uint32), ref.view(np.uint32))
+        check_quiescent_invariants(ctx, 16)
+    finally:
+        ctx.close_store()
+        ctx.shutdown()
+        buf.free()
+
+
+@pytest.mark.timeout(400)
+def test_graph_scale26_bfs_valid_and_spmv_sampled_rows():
+    """RMAT(0.57, 0.19, 0.19) scale 26, 16 edges per vertex (8.5 GiB store), 4 GiB cache:
+    BFS on 16 KiB lines passes the Graph500 checks (which fix every level), and 2048
+    sampled rows of SpMV on 128 KiB lines equal the oracle's fold bit for bit."""
+    import torch
+    scale, ef, abc = 26, 16, (0.57, 0.19, 0.19)
+    row_ptr, lay = gen.rmat_layout(scale, ef, *abc, 0)
+    buf = agile.PinnedBuffer(lay["total"])
+    try:
+        gen.rmat_fill_store(buf.ptr, row_ptr, lay, scale, ef, *abc, 0)
+        V, E = lay["V"], lay["E"]
+        g = agile.CSR(V, E, lay["row_ptr_offset"], lay["col_offset"], lay["val_offset"])
+        col = buf.array[lay["col_offset"]:lay["col_offset"] + 4 * E].view(np.int32)
+        val = buf.array[lay["val_offset"]:lay["val_offset"] + 4 * E].view(np.float32)
+        src = gen.bfs_source(0, row_ptr)
+        for line, work in ((16384, "bfs"), (131072, "spmv")):
+            ctx = agile.Context(cache_bytes=4 << 30, line_bytes=line, assoc=16, num_qp=16,
+                                qp_depth=1024, timeout_ns=int(30e9))
+            try:
+                ctx.open_store(buf)
+                if work == "bfs":
+                    level = torch.empty(V, dtype=torch.int32, device="cuda")
+                    nl = ctx.bfs(g, src, level)
+                    lev = level.cpu().numpy()
+                    assert oracle.bfs_validate(row_ptr, col, src, lev) == 0
+                    assert nl == int(lev.max()) + 1
+                else:
+                    x = gen.uniform_f32(1, gen.S_X, V, -1.0, 1.0)
+                    y = torch.empty(V, dtype=torch.float32, device="cuda")
+                    ctx.spmv(g, cuda(x), y)
+                    ctx.sync()
+                    yh = y.cpu().numpy()
+                    rows_s = np.sort(np.random.default_rng(3).choice(V, 2048, replace=False))
+                    # include the rows with the most and the fewest edges
+                    deg = np.diff(row_ptr)
+                    rows_s = np.unique(np.concatenate([rows_s, [int(np.argmax(deg)), int(np.argmin(deg))]]))
+                    for r in rows_s:
+                        exp = oracle.spmv(row_ptr, col, val, x, int(r), int(r) + 1)[0]
+                        assert yh[r].view(np.uint32) == exp.view(np.uint32), int(r)
+                check_quiescent_invariants(ctx, 16)
+            finally:
+                ctx.close_store()
+                ctx.shutdown()
+    finally:
+        buf.free()
+
+
+@pytest.mark.timeout(300)
+def test_backward_sgd_full_size_whole_store():
+    """4 tables of 8,388,608 x 64 fp32 (8 GiB store), 1 GiB cache; batch 4096 x 4 bags of
+    U[1,40] Zipf(1.1) rows, upstream gradient normal(0, 1), lr 0.01: after the fused
+    backward + SGD and a flush, the whole store image equals the oracle's update."""
+    rows, dim, T, B, lr = 8388608, 64, 4, 4096, 0.01
+    buf = table_store(rows, dim, [20, 21, 22, 23])
+    ref = buf.array.copy()
+    ctx = agile.Context(cache_bytes=1 << 30, line_bytes=4096, assoc=16, num_qp=16, qp_depth=1024,
+                        latency_ns=80_000, iops_cap=1_500_000, timeout_ns=int(30e9))
+    try:
+        ctx.open_store(buf)
+        tb = ctx.tables(rows, dim, T)
+        off, idx = gen.embbag_batch(gen.zipf_cum(rows, 1.1), B, T, 1, 40, seed=2000)
+        g = gen.normal_f32(2001, B * T * dim).reshape(B * T, dim)
+        ctx.stats(reset=True)
+        ctx.embbag_backward_sgd(tb, cuda(idx), cuda(off), B, cuda(g), lr)
+        ctx.sync()
+        st = ctx.stats()
+        uniq = oracle.embbag_backward_sgd(ref, rows, dim, T, idx, off, B, g, lr)
+        assert st["rows_updated"] == uniq
+        ctx.flush()
+        check_quiescent_invariants(ctx, 16)
+        assert np.array_equal(buf.array, ref)
+    finally:
+        ctx.close_store()
+        ctx.shutdown()
+        buf.free()
