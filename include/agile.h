@@ -117,8 +117,14 @@ agile_status agile_close_store(agile_ctx ctx, agile_store store);
  * uint64), coalesces duplicates within a wavefront, looks up the cache and, on a miss,
  * claims a line and submits a READ.  Writes one ticket per block to d_tickets (device).
  * Each successful ticket pins its line until agile_release; a ticket whose set has no
- * evictable way carries status EAGAIN and pins nothing.  Stream-ordered; the reads
- * complete during the launch (its service wavefronts drain every command). */
+ * evictable way carries status EAGAIN and pins nothing.  Stream-ordered and returns at
+ * once to the host.  Unlike the paper's prefetch(), whose reads proceed beside the
+ * calling kernel, the reads of this call complete within its own kernel launch (the
+ * launch carries the service wavefronts that drain every command, see the note at the
+ * top): a user kernel queued after it on the same stream starts once the blocks are in
+ * HBM, so host-level tickets overlap I/O with host work and with other streams, not with
+ * a later kernel on this stream.  Overlap of I/O with compute inside one kernel is what
+ * the library's workload entry points do (AGILE_MODE_ASYNC). */
 agile_status agile_async_read(agile_ctx ctx, agile_store store, const uint64_t* d_blocks,
                               uint32_t n, agile_ticket* d_tickets, void* stream);
 
@@ -130,7 +136,13 @@ agile_status agile_async_read(agile_ctx ctx, agile_store store, const uint64_t* 
 agile_status agile_wait(agile_ctx ctx, const agile_ticket* d_tickets, uint32_t n, void** d_ptrs,
                         void* stream);
 
-/* Unpins the lines of n tickets (EAGAIN tickets are skipped).  Stream-ordered. */
+/* Ends the use of n tickets' lines: drops the pin each ticket holds, so the line may be
+ * evicted again.  A line in use must not be evicted before its accesses are done, and
+ * pins that are never dropped are what deadlocks a software cache (Sec. 2.3.2); a line
+ * is only evicted in the READY/MODIFIED states once nobody holds it (Sec. 3.4 case d).
+ * EAGAIN tickets (which pin nothing) are skipped.  d_tickets is device memory written by
+ * agile_async_read; releasing a ticket twice is an error the library does not detect.
+ * Stream-ordered. */
 agile_status agile_release(agile_ctx ctx, const agile_ticket* d_tickets, uint32_t n,
                            void* stream);
 
@@ -179,6 +191,9 @@ typedef struct agile_info {
   uint32_t cu_count, max_user_waves; /* user wavefronts one launch may run */
   uint64_t wallclock_hz;             /* rate of s_memrealtime */
   uint64_t cache_base;               /* device address of line 0 */
+  uint32_t service_lds_bytes;        /* dynamic LDS each workgroup of a launch with service
+                                        wavefronts reserves (0 = none) */
+  uint32_t service_blocks;           /* workgroups that run service wavefronts */
 } agile_info;
 agile_status agile_get_info(agile_ctx ctx, agile_info* out);
 
@@ -200,8 +215,11 @@ typedef struct agile_tables {
 #define AGILE_MODE_ASYNC 1u /* reads for the next chunk are issued before this chunk is
                                computed, overlapping I/O with compute (Sec. 4.2) */
 
-/* Gathers n rows: d_out[i*dim + d] = table[d_idx[i] / rows][d_idx[i] % rows][d], where
- * d_idx holds global row numbers (int64, device).  Stream-ordered. */
+/* The array-like synchronous access of Sec. 3.5 (Listing 1, method 3), for a batch:
+ * gathers n rows, d_out[i*dim + d] = table[d_idx[i] / rows][d_idx[i] % rows][d], where
+ * d_idx holds global row numbers (int64, device) and d_out is device fp32 [n, dim].  Rows
+ * go through the cache with the two-level coalescing of Sec. 3.3.2 (duplicates within a
+ * wavefront, then the cache).  Stream-ordered; errors as for the workloads below. */
 agile_status agile_gather(agile_ctx ctx, agile_store store, const agile_tables* tb,
                           const int64_t* d_idx, uint64_t n, uint32_t mode, float* d_out,
                           void* stream);
@@ -238,6 +256,18 @@ agile_status agile_debug_trace(agile_ctx ctx, agile_store store, const uint64_t*
 agile_status agile_probe_copy(const void* src, const uint64_t* d_list, uint64_t n, void* d_dst,
                               uint64_t dst_blocks, uint32_t waves, uint32_t per_wave,
                               void* stream);
+
+/* The library's own device-wide exclusive prefix sum (used per BFS level):
+ * d_out[i] = d_in[0] + ... + d_in[i-1] (uint64, device; d_out may equal d_in).  Allocates
+ * its work area; blocks. */
+agile_status agile_debug_exclusive_scan_u64(const uint64_t* d_in, uint64_t* d_out, uint64_t n,
+                                            void* stream);
+
+/* The library's own stable LSD radix sort (used by the backward pass): sorts the n
+ * uint64 keys of d_keys (device, in place) by their bits [lo, hi), keeping the input
+ * order of keys whose bits agree.  Allocates its work area; blocks. */
+agile_status agile_debug_radix_sort_u64(uint64_t* d_keys, uint64_t n, uint32_t lo, uint32_t hi,
+                                        void* stream);
 
 /* Raw device counters in their internal order (for diagnostics): out[i] for i < n. */
 agile_status agile_debug_counters(agile_ctx ctx, uint64_t* out, uint32_t n);

@@ -21,8 +21,11 @@ def build(force: bool = True) -> str:
     """Compile liboracle.so with gcc (plain C, single-threaded, no fused multiply-adds
     other than explicit fmaf)."""
     if force or not os.path.exists(LIB_PATH):
+        # oracle.c has no OpenMP pragma: -fopenmp only builds the all-cores baseline loop
+        # of cpu_baseline.c
         cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fPIC",
-               "-shared", "-o", LIB_PATH + ".tmp", os.path.join(_HERE, "oracle.c"), "-lm"]
+               "-fopenmp", "-shared", "-o", LIB_PATH + ".tmp", os.path.join(_HERE, "oracle.c"),
+               os.path.join(_HERE, "cpu_baseline.c"), "-lm"]
         subprocess.check_call(cmd)
         os.replace(LIB_PATH + ".tmp", LIB_PATH)
     return LIB_PATH
@@ -40,6 +43,8 @@ def lib():
         L.oracle_fK.argtypes = [f32, u32]
         L.oracle_gather.argtypes = [vp, u64, vp, u64, vp]
         L.oracle_embbag_forward.argtypes = [vp, u64, u32, u32, vp, vp, u64, u32, vp, u64, vp]
+        L.oracle_embbag_forward_par.argtypes = [vp, u64, u32, u32, vp, vp, u64, u32, vp]
+        L.oracle_par_threads.restype = C.c_int
         L.oracle_embbag_backward_sgd.restype = u64
         L.oracle_embbag_backward_sgd.argtypes = [vp, u64, u32, u32, vp, vp, u64, vp, f32]
         L.oracle_bfs.argtypes = [vp, vp, u64, i64, vp]
@@ -80,6 +85,19 @@ def gather(image: np.ndarray, row_bytes: int, rows: np.ndarray) -> np.ndarray:
     out = np.empty((rows.size, row_bytes), dtype=np.uint8)
     lib().oracle_gather(_p(image), row_bytes, _p(rows), rows.size, _p(out))
     return out
+
+
+def embbag_forward_par(image, rows: int, dim: int, T: int, idx, off, B: int, K: int) -> np.ndarray:
+    """All bags, spread over the cores (the all-cores CPU baseline)."""
+    idx = np.ascontiguousarray(idx, dtype=np.int64)
+    off = np.ascontiguousarray(off, dtype=np.int64)
+    out = np.empty((B * T, dim), dtype=np.float32)
+    lib().oracle_embbag_forward_par(_p(image), rows, dim, T, _p(idx), _p(off), B, K, _p(out))
+    return out
+
+
+def par_threads() -> int:
+    return int(lib().oracle_par_threads())
 
 
 def embbag_forward(image, rows: int, dim: int, T: int, idx, off, B: int, K: int,

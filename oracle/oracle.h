@@ -48,6 +48,14 @@ void oracle_embbag_forward(const uint8_t* image, uint64_t rows, uint32_t dim, ui
                            const int64_t* idx, const int64_t* off, uint64_t B, uint32_t K,
                            const int64_t* bags, uint64_t nbags, float* out);
 
+/* The same forward with its bags spread over all cores (OpenMP), each bag computed by
+ * oracle_embbag_forward: the all-cores CPU baseline (cpu_baseline.c).  Pin: equals
+ * oracle_embbag_forward bit for bit (test_oracle_core). */
+void oracle_embbag_forward_par(const uint8_t* image, uint64_t rows, uint32_t dim, uint32_t T,
+                               const int64_t* idx, const int64_t* off, uint64_t B, uint32_t K,
+                               float* out);
+int oracle_par_threads(void);
+
 /* Embedding-bag backward (K = 0) fused with SGD, in place on the image.
  * Loss L = sum_g sum_d grad_out[g][d] * pooled[g][d]; dL/dW_t[r][d] is the sum of
  * grad_out[g][d] over the occurrences (g, j) of row r of table t, taken in ascending

@@ -49,7 +49,8 @@ class Info(C.Structure):
                 ("line_bytes", C.c_uint32), ("num_qp", C.c_uint32), ("qp_depth", C.c_uint32),
                 ("ctrl_waves", C.c_uint32), ("cq_waves", C.c_uint32), ("cu_count", C.c_uint32),
                 ("max_user_waves", C.c_uint32), ("wallclock_hz", C.c_uint64),
-                ("cache_base", C.c_uint64)]
+                ("cache_base", C.c_uint64), ("service_lds_bytes", C.c_uint32),
+                ("service_blocks", C.c_uint32)]
 
     def as_dict(self):
         return {n: int(getattr(self, n)) for n, _ in self._fields_}
@@ -127,6 +128,8 @@ def lib():
             "agile_spmv": (st, [vp, vp, C.POINTER(CSR), vp, vp, vp]),
             "agile_serve": (st, [vp, vp, C.POINTER(Tables), u32, u32, u64, vp, vp, vp, vp, vp,
                                  vp, C.POINTER(ServeOpts), C.POINTER(ServeReport)]),
+            "agile_debug_exclusive_scan_u64": (st, [vp, vp, u64, vp]),
+            "agile_debug_radix_sort_u64": (st, [vp, u64, u32, u32, vp]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -166,6 +169,20 @@ def probe_copy(src, lst, n: int, dst, dst_blocks: int, waves: int, per_wave: int
                                _stream(stream))
     if s != OK:
         raise AgileError(s, "agile_probe_copy")
+
+
+def exclusive_scan_u64(d_in, d_out, n: int, stream=None):
+    """The library's device-wide exclusive prefix sum (agile_debug_exclusive_scan_u64)."""
+    s = lib().agile_debug_exclusive_scan_u64(_ptr(d_in), _ptr(d_out), n, _stream(stream))
+    if s != OK:
+        raise AgileError(s, "agile_debug_exclusive_scan_u64")
+
+
+def radix_sort_u64(d_keys, n: int, lo: int, hi: int, stream=None):
+    """The library's stable radix sort by bits [lo, hi) (agile_debug_radix_sort_u64)."""
+    s = lib().agile_debug_radix_sort_u64(_ptr(d_keys), n, lo, hi, _stream(stream))
+    if s != OK:
+        raise AgileError(s, "agile_debug_radix_sort_u64")
 
 
 def default_config(**kw) -> Config:

@@ -15,10 +15,9 @@
 #include <thread>
 #include <vector>
 
-#include <hipcub/hipcub.hpp>
-
 #include "agile.h"
 #include "agile_dev.hpp"
+#include "agile_sort.hpp"
 
 using namespace ag;
 
@@ -50,8 +49,8 @@ struct embbag_args {
 
 // Per-wave state of the bag source.  Bags [0, 2A) of a launch with A active waves are
 // dealt out statically (wave u starts with bags u and u + A); the rest are taken
-// dynamically from WORK_PARTS partitions (bag b in partition (b - 2A) mod WORK_PARTS,
-// each with its own counter): a wave starts at partition u mod WORK_PARTS and moves on
+// dynamically from P = min(WORK_PARTS, A) partitions (bag b in partition (b - 2A) mod P,
+// each with its own counter): a wave starts at partition u mod P and moves on
 // once its partition is used up, so no wave starts behind thousands of same-address
 // atomics and the last bags still go to whichever waves are free.  The wave holds the next bag it
 // will work on, taken (and its lookup range loaded) as soon as the previous one was
@@ -136,12 +135,16 @@ __device__ __forceinline__ void hold_next(const dev_ctx& c, const launch_t& li, 
       break;
     }
   }
-  while (g < 0 && ss.tried < WORK_PARTS) {
-    const uint32_t p = (ss.uw + ss.tried) % WORK_PARTS;
+  // never more partitions than waves: every partition then has a wave that starts in it
+  // and stays until it is used up, so a bag is never left where no wave looks (a serving
+  // wave that waits on an unpublished bag of its partition blocks only that partition)
+  const uint32_t parts = a.active_waves < WORK_PARTS ? a.active_waves : WORK_PARTS;
+  while (g < 0 && ss.tried < parts) {
+    const uint32_t p = (ss.uw + ss.tried) % parts;
     uint64_t v = 0;
     if (lane() == 0) v = add_rlx(counter(c, work_counter(p)), 1ull);
     v = rdlane64(v, 0);
-    const int64_t b = dealt + (int64_t)v * WORK_PARTS + p;
+    const int64_t b = dealt + (int64_t)v * parts + p;
     if (b < nb)
       g = b;
     else
@@ -1327,6 +1330,14 @@ __global__ void k_dump(dev_ctx c, int64_t* tags, uint8_t* states, uint32_t* rc) 
 }  // namespace
 
 // =============================================================================== host side
+static constexpr size_t bwd_al(size_t v) { return (v + 255) & ~(size_t)255; }
+
+// Work area of a backward launch over n lookups: sort keys, the bag of every lookup
+// position, the heads of the distinct rows, two counters and the radix sort's own area.
+static constexpr size_t bwd_work_bytes(uint64_t n) {
+  return bwd_al(n * 8) + bwd_al(n * 4) + bwd_al(n * 4) + 256 + sort::radix_work_bytes(n);
+}
+
 struct agile_store_s {
   void* host;
   uint8_t* dev;
@@ -1870,6 +1881,8 @@ agile_status agile_get_info(agile_ctx ctx, agile_info* out) {
   out->max_user_waves = user_wave_cap(ctx, KIND_EMBBAG2);
   out->wallclock_hz = ctx->clock_hz;
   out->cache_base = (uint64_t)(uintptr_t)ctx->d.lines;
+  out->service_lds_bytes = ctx->iso_lds;
+  out->service_blocks = ctx->service_blocks;
   return AGILE_OK;
 }
 
@@ -1983,6 +1996,12 @@ static csr_t to_csr(const agile_csr* g) {
   return c;
 }
 
+// Zeroes n 32-bit words (a kernel, so that a captured graph holds no memset node).
+__global__ void k_zero32(uint32_t* p, uint32_t n) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0;
+}
+
 __global__ void k_bfs_init(int32_t* level, uint64_t V, uint64_t src, int32_t* F) {
   const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < V) level[i] = (i == src) ? 0 : -1;
@@ -1998,9 +2017,7 @@ agile_status agile_bfs(agile_ctx ctx, agile_store store, const agile_csr* g, uin
   if (!d_level || src >= g->num_vertices) return fail(ctx, AGILE_EINVAL, "bfs: bad level array or source");
   hipStream_t hs = (hipStream_t)stream;
   const uint64_t V = g->num_vertices;
-  size_t scan_bytes = 0;
-  HIPCHK(ctx, hipcub::DeviceScan::ExclusiveSum(nullptr, scan_bytes, (uint64_t*)nullptr, (uint64_t*)nullptr,
-                                               (int)V, hs));
+  const size_t scan_bytes = 8 * sort::scan_work_elems(V);
   auto al = [](size_t v) { return (v + 255) & ~(size_t)255; };
   const size_t oF = 0, oN = oF + al(4 * V), ocs = oN + al(4 * V), ocd = ocs + al(8 * V), oco = ocd + al(8 * V),
                octr = oco + al(8 * (V + 1)), osc = octr + 256, need = osc + al(scan_bytes);
@@ -2031,7 +2048,7 @@ agile_status agile_bfs(agile_ctx ctx, agile_store store, const agile_csr* g, uin
     a.N = N;
     a.nF = nF;
     a.L = L;
-    HIPCHK(ctx, hipMemsetAsync(a.ctr, 0, 256, hs));
+    hipLaunchKernelGGL(k_zero32, dim3(1), dim3(64), 0, hs, a.ctr, 64u);
     uint32_t uw = (uint32_t)std::min<uint64_t>({(nF + 63) / 64, (uint64_t)user_wave_cap(ctx, KIND_READ), by_cache});
     uw = (uw + WPB - 1) / WPB * WPB;
     launch_t li = make_launch(ctx, uw, true);
@@ -2041,7 +2058,8 @@ agile_status agile_bfs(agile_ctx ctx, agile_store store, const agile_csr* g, uin
     HIPCHK(ctx, hipMemcpyAsync(&nC, a.ctr, 4, hipMemcpyDeviceToHost, hs));
     if ((s = sync_stream(ctx, hs)) != AGILE_OK) return s;
     if (nC == 0) break;
-    HIPCHK(ctx, hipcub::DeviceScan::ExclusiveSum(sb + osc, scan_bytes, a.cd, a.co, (int)nC, hs));
+    if (!sort::exclusive_scan<uint64_t>(a.cd, a.co, nC, (uint64_t*)(sb + osc), hs))
+      return fail(ctx, AGILE_EHIP, std::string("bfs: scan launch failed: ") + hipGetErrorString(hipGetLastError()));
     uint64_t last[2] = {0, 0};
     HIPCHK(ctx, hipMemcpyAsync(&last[0], a.co + nC - 1, 8, hipMemcpyDeviceToHost, hs));
     HIPCHK(ctx, hipMemcpyAsync(&last[1], a.cd + nC - 1, 8, hipMemcpyDeviceToHost, hs));
@@ -2088,11 +2106,13 @@ agile_status agile_spmv(agile_ctx ctx, agile_store store, const agile_csr* g, co
   return AGILE_OK;
 }
 
-agile_status agile_embbag_backward_sgd(agile_ctx ctx, agile_store store, const agile_tables* tb,
-                                       const int64_t* d_idx, const int64_t* d_off, uint64_t B, uint64_t n,
-                                       const float* d_grad, float lr, void* stream) {
-  agile_status s = check_usable(ctx);
-  if (s) return s;
+
+static agile_status bwd_launch(agile_ctx ctx, const agile_tables* tb, const int64_t* d_idx, const int64_t* d_off,
+                               uint64_t B, uint64_t n, const float* d_grad, float lr, void* work, hipStream_t hs);
+
+// Argument checks shared by both backward entry points (nothing is launched on failure).
+static agile_status bwd_check(agile_ctx ctx, agile_store store, const agile_tables* tb, const int64_t* d_idx,
+                              const int64_t* d_off, uint64_t n, const float* d_grad) {
   if (store != ctx->store) return fail(ctx, AGILE_EINVAL, "backward: store is not open on this context");
   if (!tb || !d_off || !d_grad || (n && !d_idx)) return fail(ctx, AGILE_EINVAL, "backward: null pointer");
   if (tb->dim == 0 || tb->dim > 256 || tb->num_tables == 0 || tb->rows == 0)
@@ -2104,33 +2124,33 @@ agile_status agile_embbag_backward_sgd(agile_ctx ctx, agile_store store, const a
     return fail(ctx, AGILE_EINVAL, "backward: tables exceed the store");
   if (n >= (1ull << 32) || tb->rows * tb->num_tables >= (1ull << 32))
     return fail(ctx, AGILE_EINVAL, "backward: too many lookups or rows");
+  return AGILE_OK;
+}
+
+agile_status agile_embbag_backward_sgd(agile_ctx ctx, agile_store store, const agile_tables* tb,
+                                       const int64_t* d_idx, const int64_t* d_off, uint64_t B, uint64_t n,
+                                       const float* d_grad, float lr, void* stream) {
+  agile_status s = check_usable(ctx);
+  if (s) return s;
+  if ((s = bwd_check(ctx, store, tb, d_idx, d_off, n, d_grad)) != AGILE_OK) return s;
   if (n == 0 || B == 0) return AGILE_OK;
   hipStream_t hs = (hipStream_t)stream;
+  const size_t need = bwd_work_bytes(n);
+  if ((s = ensure_scratch(ctx, need, hs)) != AGILE_OK) return s;
+  return bwd_launch(ctx, tb, d_idx, d_off, B, n, d_grad, lr, ctx->scratch, hs);
+}
+
+static agile_status bwd_launch(agile_ctx ctx, const agile_tables* tb, const int64_t* d_idx, const int64_t* d_off,
+                               uint64_t B, uint64_t n, const float* d_grad, float lr, void* work, hipStream_t hs) {
   const uint64_t nbags = B * tb->num_tables;
-  // scratch: keys in/out, bag ids, heads, counters, sort workspace
-  size_t sort_bytes = 0;
-  HIPCHK(ctx, hipcub::DeviceRadixSort::SortKeys(nullptr, sort_bytes, (uint64_t*)nullptr, (uint64_t*)nullptr,
-                                                (int)n, 0, 64, hs));
-  auto al = [](size_t v) { return (v + 255) & ~(size_t)255; };
-  const size_t o_kin = 0, o_kout = o_kin + al(n * 8), o_bag = o_kout + al(n * 8), o_head = o_bag + al(n * 4),
-               o_ctr = o_head + al(n * 4), o_sort = o_ctr + 256, need = o_sort + al(sort_bytes);
-  if (need > ctx->scratch_bytes) {
-    HIPCHK(ctx, hipStreamSynchronize(hs));
-    if (ctx->scratch) HIPCHK(ctx, hipFree(ctx->scratch));
-    ctx->scratch = nullptr;
-    ctx->scratch_bytes = 0;
-    if (hipMalloc(&ctx->scratch, need) != hipSuccess) {
-      (void)hipGetLastError();
-      return fail(ctx, AGILE_ENOMEM, "backward: scratch allocation failed");
-    }
-    ctx->scratch_bytes = need;
-  }
-  uint8_t* sb = (uint8_t*)ctx->scratch;
+  const uint64_t row_bytes = (uint64_t)tb->dim * 4;
+  uint8_t* sb = (uint8_t*)work;
+  const size_t o_keys = 0, o_bag = o_keys + bwd_al(n * 8), o_head = o_bag + bwd_al(n * 4),
+               o_ctr = o_head + bwd_al(n * 4), o_sort = o_ctr + 256;
   bwd_args a{};
   a.idx = d_idx;
   a.off = d_off;
   a.grad = d_grad;
-  a.keys = (uint64_t*)(sb + o_kout);
   a.bagid = (uint32_t*)(sb + o_bag);
   a.heads = (uint32_t*)(sb + o_head);
   a.ctr = (uint32_t*)(sb + o_ctr);
@@ -2142,11 +2162,17 @@ agile_status agile_embbag_backward_sgd(agile_ctx ctx, agile_store store, const a
   a.dim = tb->dim;
   a.row_bytes = (uint32_t)row_bytes;
   a.lr = lr;
-  HIPCHK(ctx, hipMemsetAsync(a.ctr, 0, 256, hs));
-  hipLaunchKernelGGL(k_bwd_keys, dim3((uint32_t)((nbags + 255) / 256)), dim3(256), 0, hs, a, (uint64_t*)(sb + o_kin));
+  hipLaunchKernelGGL(k_zero32, dim3(1), dim3(64), 0, hs, a.ctr, 64u);
+  uint64_t* keys_in = (uint64_t*)(sb + o_keys);
+  hipLaunchKernelGGL(k_bwd_keys, dim3((uint32_t)((nbags + 255) / 256)), dim3(256), 0, hs, a, keys_in);
   HIPCHK(ctx, hipGetLastError());
-  HIPCHK(ctx, hipcub::DeviceRadixSort::SortKeys(sb + o_sort, sort_bytes, (uint64_t*)(sb + o_kin), a.keys, (int)n, 0,
-                                                64, hs));
+  // the keys are written in ascending lookup position, so a stable sort by the row bits
+  // alone leaves every row's occurrences in ascending position
+  const uint32_t row_bits = log2u(tb->rows * tb->num_tables);
+  uint64_t* sorted = nullptr;
+  if (!sort::radix_sort(keys_in, n, 32, 32 + std::max<uint32_t>(row_bits, 1), sb + o_sort, hs, &sorted))
+    return fail(ctx, AGILE_EHIP, std::string("backward: sort launch failed: ") + hipGetErrorString(hipGetLastError()));
+  a.keys = sorted;
   hipLaunchKernelGGL(k_bwd_heads, dim3((uint32_t)((n + 255) / 256)), dim3(256), 0, hs, a);
   HIPCHK(ctx, hipGetLastError());
   const int kind = tb->dim <= 64 ? KIND_BWD1 : (tb->dim <= 128 ? KIND_BWD2 : KIND_BWD4);
@@ -2386,6 +2412,40 @@ agile_status agile_debug_trace(agile_ctx ctx, agile_store store, const uint64_t*
                      d_writes, n, d_hit, d_way);
   HIPCHK(ctx, hipGetLastError());
   return sync_stream(ctx, (hipStream_t)stream);
+}
+
+agile_status agile_debug_exclusive_scan_u64(const uint64_t* d_in, uint64_t* d_out, uint64_t n, void* stream) {
+  if (n == 0) return AGILE_OK;
+  if (!d_in || !d_out) return AGILE_EINVAL;
+  hipStream_t hs = (hipStream_t)stream;
+  void* work = nullptr;
+  const size_t wb = 8 * sort::scan_work_elems(n) + 8;
+  if (hipMalloc(&work, wb) != hipSuccess) {
+    (void)hipGetLastError();
+    return AGILE_ENOMEM;
+  }
+  bool ok = sort::exclusive_scan<uint64_t>(d_in, d_out, n, (uint64_t*)work, hs);
+  ok = hipStreamSynchronize(hs) == hipSuccess && ok;
+  (void)hipFree(work);
+  return ok ? AGILE_OK : AGILE_EHIP;
+}
+
+agile_status agile_debug_radix_sort_u64(uint64_t* d_keys, uint64_t n, uint32_t lo, uint32_t hi, void* stream) {
+  if (n == 0) return AGILE_OK;
+  if (!d_keys || lo > hi || hi > 64) return AGILE_EINVAL;
+  hipStream_t hs = (hipStream_t)stream;
+  void* work = nullptr;
+  if (hipMalloc(&work, sort::radix_work_bytes(n)) != hipSuccess) {
+    (void)hipGetLastError();
+    return AGILE_ENOMEM;
+  }
+  uint64_t* sorted = nullptr;
+  bool ok = sort::radix_sort(d_keys, n, lo, hi, work, hs, &sorted);
+  if (ok && sorted != d_keys)
+    ok = hipMemcpyAsync(d_keys, sorted, n * 8, hipMemcpyDeviceToDevice, hs) == hipSuccess;
+  ok = hipStreamSynchronize(hs) == hipSuccess && ok;
+  (void)hipFree(work);
+  return ok ? AGILE_OK : AGILE_EHIP;
 }
 
 agile_status agile_debug_counters(agile_ctx ctx, uint64_t* out, uint32_t n) {

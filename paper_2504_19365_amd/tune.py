@@ -12,6 +12,7 @@ skipped.  The result is a JSON-serialisable dict: the chosen geometry and every 
 from __future__ import annotations
 
 import json
+import os
 import time
 
 import numpy as np
@@ -108,10 +109,73 @@ def tune(image, rows: int, dim: int, cache_bytes: int = 1 << 20, requests: int =
             "cache_bytes": cache_bytes}
 
 
-if __name__ == "__main__":
+# The committed summary of the tuning run whose chosen point the serving measurements use.
+SUMMARY_PATH = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                            "profiles", "serve_autotune_tiny_table.md")
+
+# Geometry keys that go to the context (agile_init); the others are serving options.
+CONTEXT_KEYS = ("line_bytes", "assoc", "num_qp", "qp_depth", "ctrl_waves")
+CHOSEN_PREFIX = "chosen: "
+
+
+def split_point(point: dict):
+    """(context geometry, serving options) of a tuned point."""
+    geom = {k: point[k] for k in CONTEXT_KEYS if k in point}
+    opts = {k: v for k, v in point.items() if k not in CONTEXT_KEYS and v}
+    return geom, opts
+
+
+def summary_markdown(res: dict, command: str) -> str:
+    """A short text summary of a tuning run: the command, the chosen point on one
+    machine-readable line, and every trial."""
+    lines = ["# Serving autotuner: tiny table (65,536 x 64 fp32), 1 MiB cache", "",
+             f"command: `{command}`", "",
+             f"requests per trial: {res['requests']} (Poisson stream of the serving "
+             f"workload, all available at once: a closed loop that measures sustainable "
+             f"throughput); trials: {len(res['trials'])}", "",
+             CHOSEN_PREFIX + json.dumps(res["best"], sort_keys=True),
+             f"best_lookups_per_s: {res['best_lookups_per_s']:.1f}", "",
+             "| # | " + " | ".join(SPACE) + " | M lookups/s | p50 ms | p99 ms |",
+             "|---" * (len(SPACE) + 4) + "|"]
+    for i, t in enumerate(res["trials"]):
+        p = t["point"]
+        lines.append(f"| {i} | " + " | ".join(str(p.get(k, "")) for k in SPACE) +
+                     f" | {t['lookups_per_s'] / 1e6:.3f} | {t['p50_s'] * 1e3:.2f} | "
+                     f"{t['p99_s'] * 1e3:.2f} |")
+    return "\n".join(lines) + "\n"
+
+
+def load_chosen(path: str) -> dict:
+    """The chosen point of a committed tuning summary (see summary_markdown)."""
+    with open(path) as f:
+        for line in f:
+            if line.startswith(CHOSEN_PREFIX):
+                return json.loads(line[len(CHOSEN_PREFIX):])
+    raise ValueError(f"{path}: no '{CHOSEN_PREFIX.strip()}' line")
+
+
+def main(argv=None) -> None:
+    import argparse
     import sys
+    ap = argparse.ArgumentParser(description="tune the serving geometry on the tiny table")
+    ap.add_argument("--requests", type=int, default=2000)
+    ap.add_argument("--rounds", type=int, default=2)
+    ap.add_argument("--out", default="", help="write the markdown summary here")
+    args = ap.parse_args(argv)
     rows, dim = 65536, 64
     buf = agile.PinnedBuffer(rows * dim * 4)
     gen.fill_table(buf.ptr, 0, rows, dim, 0)
-    res = tune(buf, rows, dim, requests=int(sys.argv[1]) if len(sys.argv) > 1 else 2000)
-    print(json.dumps(res))
+    res = tune(buf, rows, dim, requests=args.requests, rounds=args.rounds,
+               log=lambda *a: print(*a, flush=True))
+    buf.free()
+    res["requests"] = args.requests
+    cmd = "python -m paper_2504_19365_amd.tune " + " ".join(argv if argv is not None else sys.argv[1:])
+    text = summary_markdown(res, cmd.strip())
+    if args.out:
+        with open(args.out, "w") as f:
+            f.write(text)
+    print(text)
+
+
+if __name__ == "__main__":
+    main()

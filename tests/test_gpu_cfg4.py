@@ -152,3 +152,30 @@ def test_autograd_function_matches_direct_calls():
         ctx.close_store()
         ctx.shutdown()
         buf.free()
+
+
+def test_backward_rejects_lookup_counts_past_32_bits():
+    """The backward pass sorts lookup positions in 32 bits: a count of 2^32 or more is
+    rejected with AGILE_EINVAL before anything is launched, and the context stays
+    usable."""
+    import ctypes as C
+    rows, dim = 4096, 64
+    buf = table_store(rows, dim, [0])
+    ctx = agile.Context(cache_bytes=1 << 20, line_bytes=4096, assoc=8, num_qp=1, qp_depth=64)
+    try:
+        ctx.open_store(buf)
+        tb = ctx.tables(rows, dim, 1)
+        d_idx = cuda(np.zeros(4, dtype=np.int64))
+        d_off = cuda(np.array([0, 4], dtype=np.int64))
+        d_g = cuda(np.zeros((1, dim), dtype=np.float32))
+        L = agile.lib()
+        for n in (1 << 32, (1 << 32) + 5):
+            st = L.agile_embbag_backward_sgd(ctx.h, ctx.store.handle, C.byref(tb), d_idx.data_ptr(),
+                                             d_off.data_ptr(), 1, n, d_g.data_ptr(), C.c_float(0.01),
+                                             agile._stream(None))
+            assert st == agile.EINVAL
+        ctx.sync()
+    finally:
+        ctx.close_store()
+        ctx.shutdown()
+        buf.free()

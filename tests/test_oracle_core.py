@@ -142,6 +142,47 @@ def test_backward_sgd_vs_dense_transpose_product():
     assert np.all(np.abs(W1 - (W0 - lr * grad)) <= bound)
 
 
+def test_backward_sgd_tiny_brute_force_bit_exact():
+    # The update of every touched row is pinned bit for bit: the gradient summed in fp32
+    # from +0.0f over the row's occurrences in ascending lookup position, then one
+    # correctly rounded fused multiply-add w' = round(w - lr * g), here from exact
+    # rationals.  The data are chosen so that a plausible slip is caught: summing the
+    # occurrences in another order, or rounding the product before the add, changes at
+    # least one element.
+    rows, dim, T, B = 64, 8, 2, 24
+    tabs, image = _tables_image(rows, dim, T, 11)
+    off, idx = gen.embbag_batch(gen.zipf_cum(rows, 1.1), B, T, 1, 12, seed=6)
+    g = gen.normal_f32(33, B * T * dim).reshape(B * T, dim)
+    lr = np.float32(0.01)
+    upd = image.copy()
+    uniq = oracle.embbag_backward_sgd(upd, rows, dim, T, idx, off, B, g, float(lr))
+    occ = {}
+    for gb in range(B * T):
+        for j in range(off[gb], off[gb + 1]):
+            occ.setdefault((gb % T, int(idx[j])), []).append((j, gb))
+    assert uniq == len(occ)
+    got = upd.view(np.float32).reshape(T, rows, dim)
+    expect = np.stack(tabs).copy()
+    order_sensitive = rounding_sensitive = False
+    for (t, r), lst in occ.items():
+        lst.sort()
+        acc = np.zeros(dim, dtype=np.float32)
+        for _, gb in lst:
+            acc = (acc + g[gb]).astype(np.float32)
+        rev = np.zeros(dim, dtype=np.float32)
+        for _, gb in reversed(lst):
+            rev = (rev + g[gb]).astype(np.float32)
+        order_sensitive |= bool(np.any(rev != acc))
+        for d in range(dim):
+            w = Fraction(float(tabs[t][r, d]))
+            exact = w - Fraction(float(lr)) * Fraction(float(acc[d]))
+            expect[t, r, d] = np.float32(_round_f32(exact))
+            two = np.float32(np.float32(tabs[t][r, d]) - np.float32(lr * acc[d]))
+            rounding_sensitive |= bool(two != expect[t, r, d])
+    assert order_sensitive and rounding_sensitive
+    assert np.array_equal(got.view(np.uint32), expect.view(np.uint32))
+
+
 def test_backward_matches_central_finite_differences():
     # L(W) = sum_g sum_d gout[g,d] * pooled[g,d] is linear in W, so the central
     # difference of L equals dL/dW up to the rounding of the fp32 pooled values.
@@ -292,3 +333,15 @@ def test_protocol_model_shared_fetch_reads_fetch_pointer_first(controllers, tota
         n, bad = pm.explore_fetch(order, controllers=controllers, total=total, guard=guard)
         assert bad is None, (order, guard, bad)
         assert n > 100
+
+
+# ---------------------------------------------------------------- all-cores CPU baseline
+def test_parallel_forward_equals_oracle_bit_for_bit():
+    rows, dim, T, B = 1024, 32, 4, 96
+    _, image = _tables_image(rows, dim, T, 40)
+    off, idx = gen.embbag_batch(gen.zipf_cum(rows, 1.05), B, T, 1, 80, seed=8)
+    for K in (0, 5):
+        a = oracle.embbag_forward(image, rows, dim, T, idx, off, B, K)
+        b = oracle.embbag_forward_par(image, rows, dim, T, idx, off, B, K)
+        assert np.array_equal(a.view(np.uint32), b.view(np.uint32))
+    assert oracle.par_threads() >= 1
