@@ -290,6 +290,21 @@ agile_status agile_embbag_backward_sgd(agile_ctx ctx, agile_store store, const a
                                        const int64_t* d_idx, const int64_t* d_off, uint64_t B,
                                        uint64_t n, const float* d_grad, float lr, void* stream);
 
+/* The same backward pass for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): identical
+ * arguments, results and errors, but the work area (sort keys, bag ids, row heads,
+ * counters, the radix sort's buffers: about 25 MiB) is one fixed array in device memory
+ * that the library holds on each device from agile_init until the process ends, instead
+ * of the context's growable area.  n (lookups) must be <= 1,048,576 (2^20); a larger n is
+ * rejected with AGILE_EINVAL before anything is launched.  No call allocates or frees
+ * memory.  Every call on one device shares that array, and each call leaves its contents
+ * behind (the counters are cleared by the call itself): calls that overlap in time on one
+ * device, from any context or stream, race and must not be issued. */
+agile_status agile_embbag_backward_sgd_noalloc(agile_ctx ctx, agile_store store,
+                                               const agile_tables* tb, const int64_t* d_idx,
+                                               const int64_t* d_off, uint64_t B, uint64_t n,
+                                               const float* d_grad, float lr, void* stream);
+
 /* A CSR graph held in the store: row_ptr int64[V+1] at row_ptr_offset, col int32[E] at
  * col_offset and, for SpMV, val fp32[E] at val_offset (byte offsets into the store). */
 typedef struct agile_csr {

@@ -1338,6 +1338,18 @@ static constexpr size_t bwd_work_bytes(uint64_t n) {
   return bwd_al(n * 8) + bwd_al(n * 4) + bwd_al(n * 4) + 256 + sort::radix_work_bytes(n);
 }
 
+// Work area of the allocation-free backward entry point: one fixed array per device,
+// shared by every call on that device (see agile_embbag_backward_sgd_noalloc), about
+// 25 MiB for up to 2^20 lookups per call.  In host code `scratch` only names the symbol;
+// its device address comes from hipGetSymbolAddress, taken once per device at
+// agile_init and kept in scratch_dev.
+constexpr uint64_t NOALLOC_MAX_LOOKUPS = 1ull << 20;
+constexpr size_t NOALLOC_SCRATCH_BYTES = bwd_work_bytes(NOALLOC_MAX_LOOKUPS);
+static __device__ __align__(256) uint8_t scratch[NOALLOC_SCRATCH_BYTES];
+constexpr int MAX_DEVICES = 64;
+static void* scratch_dev[MAX_DEVICES];
+static std::mutex scratch_mu;
+
 struct agile_store_s {
   void* host;
   uint8_t* dev;
@@ -1360,6 +1372,7 @@ struct agile_ctx_s {
   void* scratch = nullptr;     // backward-pass work arrays, grown on demand
   size_t scratch_bytes = 0;
   uint32_t iso_lds = 0;        // dynamic LDS that makes one workgroup fill a CU
+  void* noalloc_scratch = nullptr;  // device address of `scratch` on this context's device
 };
 
 namespace {
@@ -1575,6 +1588,24 @@ agile_status agile_init(const agile_config* cfg_in, agile_ctx* out) {
     (void)hipGetLastError();
     delete ctx;
     return AGILE_EHIP;
+  }
+  if (cfg.device < 0 || cfg.device >= MAX_DEVICES) {
+    delete ctx;
+    return AGILE_EINVAL;
+  }
+  {
+    // the allocation-free entry point's work area on this device (the current one)
+    std::lock_guard<std::mutex> lk(scratch_mu);
+    if (!scratch_dev[cfg.device]) {
+      void* p = nullptr;
+      if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) {
+        (void)hipGetLastError();
+        delete ctx;
+        return AGILE_EHIP;
+      }
+      scratch_dev[cfg.device] = p;
+    }
+    ctx->noalloc_scratch = scratch_dev[cfg.device];
   }
   int cus = 0, wclk_khz = 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, cfg.device) != hipSuccess ||
@@ -2138,6 +2169,21 @@ agile_status agile_embbag_backward_sgd(agile_ctx ctx, agile_store store, const a
   const size_t need = bwd_work_bytes(n);
   if ((s = ensure_scratch(ctx, need, hs)) != AGILE_OK) return s;
   return bwd_launch(ctx, tb, d_idx, d_off, B, n, d_grad, lr, ctx->scratch, hs);
+}
+
+agile_status agile_embbag_backward_sgd_noalloc(agile_ctx ctx, agile_store store, const agile_tables* tb,
+                                               const int64_t* d_idx, const int64_t* d_off, uint64_t B,
+                                               uint64_t n, const float* d_grad, float lr, void* stream) {
+  agile_status s = check_usable(ctx);
+  if (s) return s;
+  if ((s = bwd_check(ctx, store, tb, d_idx, d_off, n, d_grad)) != AGILE_OK) return s;
+  if (n > NOALLOC_MAX_LOOKUPS)
+    return fail(ctx, AGILE_EINVAL,
+                "backward_noalloc: " + std::to_string(n) + " lookups exceed the fixed work area's maximum of " +
+                    std::to_string(NOALLOC_MAX_LOOKUPS));
+  if (n == 0 || B == 0) return AGILE_OK;
+  if (!ctx->noalloc_scratch) return fail(ctx, AGILE_ESTATE, "backward_noalloc: no work area on this device");
+  return bwd_launch(ctx, tb, d_idx, d_off, B, n, d_grad, lr, ctx->noalloc_scratch, (hipStream_t)stream);
 }
 
 static agile_status bwd_launch(agile_ctx ctx, const agile_tables* tb, const int64_t* d_idx, const int64_t* d_off,
