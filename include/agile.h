@@ -191,8 +191,8 @@ typedef struct agile_info {
   uint32_t cu_count, max_user_waves; /* user wavefronts one launch may run */
   uint64_t wallclock_hz;             /* rate of s_memrealtime */
   uint64_t cache_base;               /* device address of line 0 */
-  uint32_t service_lds_bytes;        /* dynamic LDS each workgroup of a launch with service
-                                        wavefronts reserves (0 = none) */
+  uint32_t service_lds_bytes;        /* LDS (static + dynamic) per workgroup of an
+                                        embedding-bag launch, dim 65..128 */
   uint32_t service_blocks;           /* workgroups that run service wavefronts */
 } agile_info;
 agile_status agile_get_info(agile_ctx ctx, agile_info* out);
@@ -328,6 +328,18 @@ agile_status agile_bfs(agile_ctx ctx, agile_store store, const agile_csr* g, uin
  * through the cache; d_x and d_y are device fp32[V].  Stream-ordered. */
 agile_status agile_spmv(agile_ctx ctx, agile_store store, const agile_csr* g, const float* d_x,
                         float* d_y, void* stream);
+
+/* The kernel-only baselines of the breakdown in Sec. 4.5: the same BFS and SpMV kernels
+ * (same levels, same fold order, so bit-identical results) reading a copy of the store
+ * image resident in device memory (d_image, image_bytes, the same layout and offsets)
+ * with no cache, queue or service wavefront involved.  The context supplies the launch
+ * geometry and the work area; no store needs to be open.  Blocking as agile_bfs /
+ * stream-ordered as agile_spmv. */
+agile_status agile_bfs_resident(agile_ctx ctx, const void* d_image, uint64_t image_bytes,
+                                const agile_csr* g, uint64_t src, int32_t* d_level,
+                                uint32_t* out_levels, void* stream);
+agile_status agile_spmv_resident(agile_ctx ctx, const void* d_image, uint64_t image_bytes,
+                                 const agile_csr* g, const float* d_x, float* d_y, void* stream);
 
 /* ---------------------------------------------------------------- serving --------- */
 typedef struct agile_serve_opts {

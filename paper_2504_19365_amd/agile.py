@@ -129,6 +129,11 @@ def lib():
             "agile_serve": (st, [vp, vp, C.POINTER(Tables), u32, u32, u64, vp, vp, vp, vp, vp,
                                  vp, C.POINTER(ServeOpts), C.POINTER(ServeReport)]),
             "agile_debug_exclusive_scan_u64": (st, [vp, vp, u64, vp]),
+            "agile_bfs_resident": (st, [vp, vp, u64, C.POINTER(CSR), u64, vp, C.POINTER(C.c_uint32),
+                                        vp]),
+            "agile_spmv_resident": (st, [vp, vp, u64, C.POINTER(CSR), vp, vp, vp]),
+            "agile_embbag_backward_sgd_noalloc": (st, [vp, vp, C.POINTER(Tables), vp, vp, u64, u64,
+                                                       vp, C.c_float, vp]),
             "agile_debug_radix_sort_u64": (st, [vp, u64, u32, u32, vp]),
         }
         for name, (res, args) in sig.items():
@@ -357,6 +362,19 @@ class Context:
         self._check(lib().agile_spmv(self.h, store.handle, C.byref(g), _ptr(x), _ptr(y),
                                      _stream(stream)), "agile_spmv")
 
+    def bfs_resident(self, image, nbytes: int, g: CSR, src: int, level, stream=None) -> int:
+        """BFS over a copy of the store image resident in device memory (no cache)."""
+        nl = C.c_uint32(0)
+        self._check(lib().agile_bfs_resident(self.h, _ptr(image), nbytes, C.byref(g), src,
+                                             _ptr(level), C.byref(nl), _stream(stream)),
+                    "agile_bfs_resident")
+        return int(nl.value)
+
+    def spmv_resident(self, image, nbytes: int, g: CSR, x, y, stream=None):
+        """SpMV over a copy of the store image resident in device memory (no cache)."""
+        self._check(lib().agile_spmv_resident(self.h, _ptr(image), nbytes, C.byref(g), _ptr(x),
+                                              _ptr(y), _stream(stream)), "agile_spmv_resident")
+
     def serve(self, tb: Tables, K: int, arrival, req_bag0, bag_off, idx,
               mode: int = MODE_ASYNC, max_inflight_lookups: int = 0,
               max_inflight_requests: int = 0, user_waves: int = 0,
@@ -394,7 +412,9 @@ class Context:
                      "t_ctrl_hold", "t_ctrl_idle", "ctrl_noroom", "t_cq_busy", "t_cq_idle",
                      "t_u_issue", "t_u_submit", "t_u_wait", "t_u_consume", "tok_lead",
                      "tok_n", "t_u_desc", "t_u_life", "svc_exit", "img_epoch", "work_p1",
-                     "work_p2", "work_p3", "work_p4", "work_p5", "work_p6", "work_p7")
+                     "work_p2", "work_p3", "work_p4", "work_p5", "work_p6", "work_p7", "defer",
+                     "hwork", "hwork_p1", "hwork_p2", "hwork_p3", "hwork_p4", "hwork_p5",
+                     "hwork_p6", "hwork_p7", "exh", "hexh")
 
     def debug_counters(self) -> dict:
         n = len(self.COUNTER_NAMES)

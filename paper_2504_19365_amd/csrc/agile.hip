@@ -45,6 +45,10 @@ struct embbag_args {
   const uint32_t* pub_dev;    // device mirror of the number of published requests
   const uint32_t* pub_host;   // pinned: [0] published requests, [1] stop
   uint32_t* done;             // pinned: done[r] = 1 once request r's outputs are visible
+  // the resident-hit launch before this one defers bags to this list, and this launch
+  // runs only them; their number is the device counter C_DEFER, read by every wave when
+  // it starts.  NULL: this launch runs every bag.
+  const uint32_t* list;
 };
 
 // Per-wave state of the bag source.  Bags [0, 2A) of a launch with A active waves are
@@ -58,12 +62,15 @@ struct embbag_args {
 // processed (except near the end of the launch).  A held bag whose request is not yet
 // published stays held.  The work counters start every launch at zero.
 struct src_state {
-  int64_t g;       // held bag, or -1
+  int64_t g;       // position of the held bag in the launch's bag sequence, or -1
+  int64_t bag;     // the held bag itself (differs from g when the launch runs a list)
   int64_t j0, j1;  // its lookups [j0, j1)
   bool exhausted;
   uint32_t uw;     // this wave's index among the active waves
   uint32_t dealt;  // static bags looked at so far (0..STATIC_ROUNDS)
   uint32_t tried;  // partitions found used up so far
+  int64_t nb;      // bags of the launch: a.nbags, or the deferred count for a list
+  uint32_t skip;   // partitions known to be used up (read once the wave's own one is)
 };
 constexpr uint32_t STATIC_ROUNDS = 2;
 
@@ -124,7 +131,7 @@ __device__ __forceinline__ bool wait_published(const dev_ctx& c, const embbag_ar
 // Takes the next bag into the held slot (or marks the source exhausted).
 __device__ __forceinline__ void hold_next(const dev_ctx& c, const launch_t& li, const embbag_args& a,
                                           src_state& ss) {
-  const int64_t A = (int64_t)a.active_waves, nb = (int64_t)a.nbags;
+  const int64_t A = (int64_t)a.active_waves, nb = ss.nb;
   const int64_t dealt = (int64_t)STATIC_ROUNDS * A < nb ? (int64_t)STATIC_ROUNDS * A : nb;
   int64_t g = -1;
   while (ss.dealt < STATIC_ROUNDS) {
@@ -139,16 +146,27 @@ __device__ __forceinline__ void hold_next(const dev_ctx& c, const launch_t& li, 
   // and stays until it is used up, so a bag is never left where no wave looks (a serving
   // wave that waits on an unpublished bag of its partition blocks only that partition)
   const uint32_t parts = a.active_waves < WORK_PARTS ? a.active_waves : WORK_PARTS;
+  if (nb <= dealt) ss.tried = parts;  // every bag was dealt: no counter to visit
   while (g < 0 && ss.tried < parts) {
     const uint32_t p = (ss.uw + ss.tried) % parts;
+    // once its own partition is used up, a wave reads which partitions others have found
+    // used up and skips them, so the last searches of a launch cost one read each
+    // instead of an atomic per partition
+    if (ss.tried == 1) ss.skip = uni((uint32_t)ld_rlx(counter(c, C_EXH)));
+    if (ss.tried > 0 && ((ss.skip >> p) & 1u)) {
+      ++ss.tried;
+      continue;
+    }
     uint64_t v = 0;
     if (lane() == 0) v = add_rlx(counter(c, work_counter(p)), 1ull);
     v = rdlane64(v, 0);
     const int64_t b = dealt + (int64_t)v * parts + p;
-    if (b < nb)
+    if (b < nb) {
       g = b;
-    else
+    } else {
+      if (lane() == 0) or_rlx(counter(c, C_EXH), 1ull << p);
       ++ss.tried;
+    }
   }
   if (g < 0) {
     ss.exhausted = true;
@@ -156,12 +174,14 @@ __device__ __forceinline__ void hold_next(const dev_ctx& c, const launch_t& li, 
     return;
   }
   ss.g = g;
+  const int64_t bag = a.list ? (int64_t)a.list[g] : g;
+  ss.bag = bag;
   if (a.gather) {
-    ss.j0 = g * 64;
+    ss.j0 = bag * 64;
     ss.j1 = ((int64_t)a.n < ss.j0 + 64) ? (int64_t)a.n : ss.j0 + 64;
   } else {
-    ss.j0 = a.off[g];
-    ss.j1 = a.off[g + 1];
+    ss.j0 = a.off[bag];
+    ss.j1 = a.off[bag + 1];
   }
 }
 
@@ -184,9 +204,9 @@ __device__ __forceinline__ desc_t next_desc(const dev_ctx& c, const launch_t& li
         hold_next(c, li, a, ss);
         if (ss.g < 0) return r;
       }
-      const int64_t g = ss.g;
+      const int64_t g = ss.g, bag = ss.bag;
       if (a.serve) {
-        const uint32_t rq = a.bag_req[g];
+        const uint32_t rq = a.bag_req[bag];
         if (uni(ld_rlx(a.pub_dev)) <= rq) {
           if (!may_wait) return r;  // keep holding it
           if (!wait_published(c, a, rq)) {
@@ -202,9 +222,9 @@ __device__ __forceinline__ desc_t next_desc(const dev_ctx& c, const launch_t& li
       // hold the next bag now, except near the end of the work: a held bag cannot go to
       // a wave that runs out, so the last bags are taken only when needed
       ss.g = -1;
-      if (g + 2 * (int64_t)a.active_waves < (int64_t)a.nbags) hold_next(c, li, a, ss);
+      if (g + 2 * (int64_t)a.active_waves < ss.nb) hold_next(c, li, a, ss);
       if (j1 > j0) {
-        r.g = g;
+        r.g = bag;
         r.j = j0;
         r.end = j1;
         break;
@@ -213,7 +233,7 @@ __device__ __forceinline__ desc_t next_desc(const dev_ctx& c, const launch_t& li
         float z[VPL];
 #pragma unroll
         for (int v = 0; v < VPL; ++v) z[v] = 0.0f;
-        write_bag<VPL>(c, a, g, z);
+        write_bag<VPL>(c, a, bag, z);
       }
     }
   }
@@ -375,7 +395,79 @@ __device__ __forceinline__ uint32_t consume(const dev_ctx& c, const embbag_args&
   return n;
 }
 
-// One user wavefront of the embedding-bag / gather workload.
+// Consumes chunk `cc` of descriptor `dc` (already issued) into acc, in order, and writes
+// the bag's output when dc is its last chunk.  A row whose unpinned line changed tenant
+// while it was read (the seqlock check failed) is presented again optimistically, with
+// the rest of the chunk, up to twice: waiting for the lines of a fresh claim is safe while
+// this wave holds pins, since a claimed line always fills.  A row that met a full set, or
+// keeps losing its line, is drained: the wave first drops every pin it holds (the other
+// issued chunk `cn` included, if *n_issued; the caller then issues it again), then
+// acquires the remaining rows one at a time while holding nothing, so that no wave ever
+// waits for a line while it pins others (Sec. 2.3.2).  Returns false on abort/timeout.
+template <int VPL>
+__device__ __forceinline__ bool finish_chunk(const dev_ctx& c, const embbag_args& a, uint32_t q, desc_t dc,
+                                             chunk_t& cc, float (&acc)[VPL], chunk_t& cn, bool& n_issued) {
+  uint32_t k = 0;
+  for (uint32_t attempt = 0;; ++attempt) {
+    if (attempt) {
+      dc.j += k;
+      dc.n -= k;
+      make_chunk(c, a, dc, cc);
+      if (!chunk_issue(c, cc, q, true, PIN_NONE)) return false;
+    }
+    if (!chunk_wait(c, cc, false)) return false;
+    const uint64_t t_cons = now();
+    k = consume<VPL>(c, a, dc, cc, acc, true);
+    chunk_release(c, cc, false);
+    wtick(c, WS_T_CONSUME, t_cons);
+    if (lane() == 0) wcount(WS_AUX1, k);
+    if (k == dc.n || attempt == 2 || !st_ok(rdlane(cc.st, k))) break;
+  }
+  if (k < dc.n) {
+    if (n_issued) {
+      if (!chunk_wait(c, cn, false)) return false;
+      chunk_release(c, cn, false);
+      n_issued = false;
+    }
+    dc.j += k;
+    dc.n -= k;
+    while (dc.n > 0) {
+      desc_t one = dc;
+      one.n = 1;
+      spin_t sp;
+      for (;;) {
+        make_chunk(c, a, one, cc);
+        if (!chunk_issue(c, cc, q, true, PIN_LINE)) return false;
+        if (rdlane(cc.st, 0) != A_EAGAIN) break;
+        if (!sp.step(c, 0xF0000000ull | (uint32_t)dc.g)) return false;
+      }
+      if (!chunk_wait(c, cc, false)) return false;
+      consume<VPL>(c, a, one, cc, acc, false);
+      chunk_release(c, cc, false);
+      if (lane() == 0) wcount(WS_AUX1, 1);
+      dc.j += 1;
+      dc.n -= 1;
+    }
+  }
+  if (dc.last && !a.gather) {
+    write_bag<VPL>(c, a, dc.g, acc);
+#pragma unroll
+    for (int v = 0; v < VPL; ++v) acc[v] = 0.0f;
+  }
+  return true;
+}
+
+// One user wavefront of the embedding-bag / gather workload.  Both modes keep at most two
+// chunks of reads in flight per wave, so they present the queues the same concurrency:
+//  * asynchronous (Sec. 4.2): once the current chunk's lines are filled, the reads of the
+//    next chunk are issued and then the current chunk is computed, so this wave's I/O
+//    overlaps its own compute.  The next chunk is requested only after the current one
+//    has arrived: the queues are first-come first-served at the store's IOPS cap, and a
+//    prefetch queued earlier would stand in front of other waves' reads that are needed
+//    now (it would not make the data arrive sooner, only later for someone else);
+//  * synchronous (the plain method, array-like issue-and-wait): the reads of two chunks
+//    are issued, both are waited for, then both are computed; the wave's compute never
+//    overlaps its own I/O.
 template <int VPL>
 __device__ __forceinline__ void embbag_wave(const dev_ctx& c, const launch_t& li, const embbag_args& a, uint32_t uw) {
   const uint32_t q = uw % c.num_qp;
@@ -385,93 +477,71 @@ __device__ __forceinline__ void embbag_wave(const dev_ctx& c, const launch_t& li
   for (int v = 0; v < VPL; ++v) acc[v] = 0.0f;
   desc_t none;
   none.valid = false;
-  src_state ss{-1, 0, 0, false, uw, 0, 0};
+  // a list launch runs the bags the resident-hit pass before it deferred
+  const int64_t nb = a.list ? (int64_t)uni64(ld_rlx(counter(c, C_DEFER))) : (int64_t)a.nbags;
+  src_state ss{-1, -1, 0, 0, false, uw, 0, 0, nb, 0u};
+  chunk_t cc, cn;
+  if (!async) {
+    desc_t dc = next_desc<VPL>(c, li, a, none, ss, true);
+    while (dc.valid) {
+      make_chunk(c, a, dc, cc);
+      if (!chunk_issue(c, cc, q, true, PIN_NONE)) return;
+      // the pair's second chunk: the next one if it is already available
+      desc_t dn = next_desc<VPL>(c, li, a, dc, ss, false);
+      bool n_issued = false;
+      if (dn.valid) {
+        make_chunk(c, a, dn, cn);
+        if (!chunk_issue(c, cn, q, true, PIN_NONE)) return;
+        n_issued = true;
+      }
+      // every read of the pair completes before any of its compute
+      if (!chunk_wait(c, cc, false)) return;
+      if (n_issued && !chunk_wait(c, cn, false)) return;
+      if (!finish_chunk<VPL>(c, a, q, dc, cc, acc, cn, n_issued)) return;
+      if (dn.valid) {
+        if (!n_issued) {  // dropped to drain the first chunk: issue it again
+          make_chunk(c, a, dn, cn);
+          if (!chunk_issue(c, cn, q, true, PIN_NONE)) return;
+        }
+        bool none_held = false;
+        if (!finish_chunk<VPL>(c, a, q, dn, cn, acc, cc, none_held)) return;
+        dc = dn;
+      }
+      const uint64_t t_desc = now();
+      dc = next_desc<VPL>(c, li, a, dc, ss, true);
+      wtick(c, WS_T_DESC, t_desc);
+    }
+    return;
+  }
   desc_t dc = next_desc<VPL>(c, li, a, none, ss, true);
   if (!dc.valid) return;
-  chunk_t cc, cn;
   make_chunk(c, a, dc, cc);
   if (!chunk_issue(c, cc, q, true, PIN_NONE)) return;
   while (dc.valid) {
+    if (!chunk_wait(c, cc, false)) return;
     desc_t dn;
     bool n_issued = false;
-    dn.valid = false;
-    if (async) {
-      const uint64_t t_desc = now();
-      dn = next_desc<VPL>(c, li, a, dc, ss, false);
-      if (dn.valid) {
-        make_chunk(c, a, dn, cn);
-        wtick(c, WS_T_DESC, t_desc);
-        if (!chunk_issue(c, cn, q, true, PIN_NONE)) return;
-        n_issued = true;
-      } else {
-        wtick(c, WS_T_DESC, t_desc);
-      }
-    }
-    // Consume the current chunk in order up to its first row without a line.  A row
-    // whose line changed tenant while it was read (the seqlock check failed) is presented
-    // again optimistically, with the rest of the chunk, up to twice: waiting for the lines
-    // of a fresh claim is safe while this wave holds pins, since a claimed line always
-    // fills.  A row that met a full set, or keeps losing its line, is drained below.
-    uint32_t k = 0;
-    for (uint32_t attempt = 0;; ++attempt) {
-      if (attempt) {
-        dc.j += k;
-        dc.n -= k;
-        make_chunk(c, a, dc, cc);
-        if (!chunk_issue(c, cc, q, true, PIN_NONE)) return;
-      }
-      if (!chunk_wait(c, cc, false)) return;
-      const uint64_t t_cons = now();
-      k = consume<VPL>(c, a, dc, cc, acc, true);
-      chunk_release(c, cc, false);
-      wtick(c, WS_T_CONSUME, t_cons);
-      if (lane() == 0) wcount(WS_AUX1, k);
-      if (k == dc.n || attempt == 2 || !st_ok(rdlane(cc.st, k))) break;
-    }
-    if (k < dc.n) {
-      // EAGAIN: drop every pin this wave holds (including the prefetched chunk), then
-      // drain the rest of the chunk one row at a time, acquiring each row while holding
-      // nothing, so that no wave ever waits for a line while it pins others (Sec. 2.3.2).
-      if (n_issued) {
-        if (!chunk_wait(c, cn, false)) return;
-        chunk_release(c, cn, false);
-        n_issued = false;
-      }
-      dc.j += k;
-      dc.n -= k;
-      while (dc.n > 0) {
-        desc_t one = dc;
-        one.n = 1;
-        spin_t sp;
-        for (;;) {
-          make_chunk(c, a, one, cc);
-          if (!chunk_issue(c, cc, q, true, PIN_LINE)) return;
-          if (rdlane(cc.st, 0) != A_EAGAIN) break;
-          if (!sp.step(c, 0xF0000000ull | (uint32_t)dc.g)) return;
-        }
-        if (!chunk_wait(c, cc, false)) return;
-        consume<VPL>(c, a, one, cc, acc, false);
-        chunk_release(c, cc, false);
-        if (lane() == 0) wcount(WS_AUX1, 1);
-        dc.j += 1;
-        dc.n -= 1;
-      }
-    }
-    if (dc.last && !a.gather) {
-      write_bag<VPL>(c, a, dc.g, acc);
-#pragma unroll
-      for (int v = 0; v < VPL; ++v) acc[v] = 0.0f;
-    }
     const uint64_t t_desc = now();
-    if (!async || (!dn.valid && ss.g >= 0)) dn = next_desc<VPL>(c, li, a, dc, ss, true);
+    dn = next_desc<VPL>(c, li, a, dc, ss, false);
+    if (dn.valid) {
+      make_chunk(c, a, dn, cn);
+      wtick(c, WS_T_DESC, t_desc);
+      if (!chunk_issue(c, cn, q, true, PIN_NONE)) return;
+      n_issued = true;
+    } else {
+      wtick(c, WS_T_DESC, t_desc);
+    }
+    if (!finish_chunk<VPL>(c, a, q, dc, cc, acc, cn, n_issued)) return;
+    const uint64_t t_next = now();
+    if (!dn.valid && ss.g >= 0) dn = next_desc<VPL>(c, li, a, dc, ss, true);
     dc = dn;
     if (!dc.valid) break;
     if (n_issued) {
       cc = cn;
-      wtick(c, WS_T_DESC, t_desc);
+      wtick(c, WS_T_DESC, t_next);
     } else {
       make_chunk(c, a, dc, cc);
-      wtick(c, WS_T_DESC, t_desc);
+      wtick(c, WS_T_DESC, t_next);
       if (!chunk_issue(c, cc, q, true, PIN_NONE)) return;
     }
   }
@@ -513,6 +583,197 @@ __device__ __forceinline__ void embbag_serial(const dev_ctx& c, const launch_t& 
     }
     if (!a.gather) write_bag<VPL>(c, a, (int64_t)g, acc);
   }
+}
+
+// ---- resident-hit pass: the first of the two launches of every embedding-bag / gather call
+// A lean loop with no pins, no locks and no queue traffic: each wave takes whole bags
+// and, chunk by chunk, probes the sets of the chunk's lines (the LDS-staged probe), and
+// if every line is resident with its data (READY, MODIFIED or being written back) reads
+// the rows optimistically, adds them in order and checks the lines' tags and generations
+// once the loads have completed (the seqlock order).  A bag with a line that is absent
+// or still being fetched, or whose line changed tenant while it was read, is appended to
+// the deferred list and left entirely to the I/O launch that follows on the stream (which
+// recomputes it from the start, so the two launches never split a bag's sum).  Hits here
+// count as requests and hits like any other.
+// Rows [r, r + g) of a chunk whose lane u holds the address of row u: the row's address
+// is made uniform with two lane reads, and every lane loads its own columns of it.
+template <int VPL>
+__device__ __forceinline__ void hit_load(uint64_t raddr, uint32_t r, uint32_t g, uint32_t d0, bool mine,
+                                         float (&v)[rows_per_round<VPL>()][VPL]) {
+#pragma unroll
+  for (uint32_t u = 0; u < rows_per_round<VPL>(); ++u) {
+    if (u < g) {
+      const uint64_t p = ((uint64_t)rdlane((uint32_t)(raddr >> 32), r + u) << 32) |
+                         rdlane((uint32_t)raddr, r + u);
+      if (mine) {
+        ld_row<VPL>(reinterpret_cast<const float*>(p) + d0, v[u]);
+      } else {
+#pragma unroll
+        for (int e = 0; e < VPL; ++e) v[u][e] = 0.0f;
+      }
+    }
+  }
+}
+// Adds (or, gathering, writes out) rows [r, r + g) held in v; lookup j of the chunk's
+// first row gives the gather output position.
+template <int VPL>
+__device__ __forceinline__ void hit_use(const embbag_args& a, int64_t j, uint32_t g, uint32_t d0, bool mine,
+                                        const float (&v)[rows_per_round<VPL>()][VPL], float (&acc)[VPL]) {
+  if (!mine) return;
+  if (a.gather) {
+#pragma unroll
+    for (uint32_t u = 0; u < rows_per_round<VPL>(); ++u)
+      if (u < g) {
+        float* o = a.out + (uint64_t)(j + u) * a.dim + d0;
+#pragma unroll
+        for (int e = 0; e < VPL; ++e) o[e] = v[u][e];
+      }
+  } else if (a.K == 0) {
+#pragma unroll
+    for (uint32_t u = 0; u < rows_per_round<VPL>(); ++u)
+      if (u < g) {
+#pragma unroll
+        for (int e = 0; e < VPL; ++e) acc[e] = acc[e] + v[u][e];
+      }
+  } else {
+#pragma unroll
+    for (uint32_t u = 0; u < rows_per_round<VPL>(); ++u)
+      if (u < g) {
+#pragma unroll
+        for (int e = 0; e < VPL; ++e) acc[e] = acc[e] + fK(v[u][e], a.K);
+      }
+  }
+}
+
+template <int VPL>
+__device__ __forceinline__ bool hit_wave(const dev_ctx& c, const embbag_args& a, uint32_t uw, uint32_t* list) {
+  bool appended = false;
+  const uint32_t A = a.active_waves;
+  const uint64_t nb = a.nbags;
+  const uint32_t d0 = lane() * VPL;
+  const bool mine = d0 < a.dim;
+  constexpr uint32_t R = rows_per_round<VPL>();
+  const uint64_t lmask = (1ull << c.line_shift) - 1;
+  // bags [0, 2A) are dealt statically (wave u takes u and u + A); the rest one at a time
+  // from P = min(8, A) partition counters (bag 2A + v*P + p in partition p), a wave
+  // starting at partition u mod P and moving on once it is used up
+  const uint32_t parts = A < WORK_PARTS ? A : WORK_PARTS;
+  uint32_t tried = 0, skip = 0;
+  for (uint32_t round = 0;; ++round) {
+    uint64_t g;
+    if (round < 2) {
+      g = (uint64_t)uw + (uint64_t)round * A;
+      if (g >= nb) continue;
+    } else {
+      if (nb <= 2ull * A || tried >= parts) break;
+      const uint32_t p = (uw + tried) % parts;
+      // past its own partition a wave skips the ones others found used up
+      if (tried == 1) skip = uni((uint32_t)ld_rlx(counter(c, C_HEXH)));
+      if (tried > 0 && ((skip >> p) & 1u)) {
+        ++tried;
+        continue;
+      }
+      uint64_t v = 0;
+      if (lane() == 0) v = add_rlx(counter(c, C_HWORK + p), 1ull);
+      g = 2ull * A + rdlane64(v, 0) * parts + p;
+      if (g >= nb) {
+        if (lane() == 0) or_rlx(counter(c, C_HEXH), 1ull << p);
+        ++tried;
+        continue;
+      }
+    }
+    int64_t j0, j1;
+    if (a.gather) {
+      j0 = (int64_t)g * 64;
+      j1 = ((int64_t)a.n < j0 + 64) ? (int64_t)a.n : j0 + 64;
+    } else {
+      j0 = a.off[g];
+      j1 = a.off[g + 1];
+    }
+    const uint32_t t = a.gather ? 0u : (uint32_t)(g % a.T);
+    float acc[VPL];
+#pragma unroll
+    for (int v = 0; v < VPL; ++v) acc[v] = 0.0f;
+    bool deferred = false;
+    for (int64_t j = j0; j < j1 && !deferred; j += 64) {
+      const uint32_t n = (uint32_t)((j1 - j) < 64 ? (j1 - j) : 64);
+      chunk_t ch;
+      ch.act = lane() < n;
+      ch.pinned = false;
+      ch.line_id = 0;
+      ch.off = 0;
+      if (ch.act) {
+        const int64_t row = a.idx[j + lane()];
+        const uint64_t byte = a.base_off + (uint64_t)t * a.table_bytes + (uint64_t)row * a.row_bytes;
+        ch.line_id = (uint32_t)(byte >> c.line_shift);
+        ch.off = (uint32_t)(byte & lmask);
+      }
+      const uint32_t base = ch.act ? set_of(c, ch.line_id) * c.assoc : 0u;
+      uint64_t m = 0;
+      int w = -1;
+      if (probe_staged_ok(c.assoc))
+        w = probe_staged(c, ch.act, base, ch.line_id, m);
+      else if (ch.act)
+        w = probe_set(c, base, ch.line_id, m);
+      const bool hit = ch.act && w >= 0 && m_valid_data(m_state(m));
+      if (ballot(ch.act && !hit)) {
+        deferred = true;
+        break;
+      }
+      ch.idx = base + (uint32_t)(w < 0 ? 0 : w);
+      ch.gen = m_gen(m);
+      ch.st = A_HIT;
+      if (ch.act && !(m & M_REF)) or_rlx(c.meta + ch.idx, M_REF);
+      // each lane's row address, so a row costs two lane reads and one load
+      const uint64_t raddr = (uint64_t)(uintptr_t)line_ptr(c, ch.idx) + ch.off;
+      // the rows in rounds of R, two rounds in flight, added as they arrive
+      float va[R][VPL], vb[R][VPL];
+      hit_load<VPL>(raddr, 0, n < R ? n : R, d0, mine, va);
+      for (uint32_t r = 0; r < n;) {
+        uint32_t gcur = (n - r) < R ? (n - r) : R;
+        uint32_t rn = r + gcur;
+        uint32_t gn = rn < n ? ((n - rn) < R ? (n - rn) : R) : 0;
+        if (gn) hit_load<VPL>(raddr, rn, gn, d0, mine, vb);
+        hit_use<VPL>(a, j + r, gcur, d0, mine, va, acc);
+        r = rn;
+        if (r >= n) break;
+        gcur = gn;
+        rn = r + gcur;
+        gn = rn < n ? ((n - rn) < R ? (n - rn) : R) : 0;
+        if (gn) hit_load<VPL>(raddr, rn, gn, d0, mine, va);
+        hit_use<VPL>(a, j + r, gcur, d0, mine, vb, acc);
+        r = rn;
+      }
+      // every row load of this wave has completed before the metadata is read again
+      __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
+      asm volatile("" ::: "memory");
+      const bool bad = ch.act && !line_still_valid(c, ch.idx, ch.line_id, ch.gen);
+      if (ballot(bad)) deferred = true;
+    }
+    if (deferred) {
+      if (lane() == 0) list[add_rlx(counter(c, C_DEFER), 1ull)] = (uint32_t)g;
+      appended = true;
+      continue;
+    }
+    if (!a.gather) write_bag<VPL>(c, a, (int64_t)g, acc);
+    if (lane() == 0) {
+      const uint64_t len = (uint64_t)(j1 - j0);
+      wcount(WS_REQUESTS, len);
+      wcount(WS_HITS, len);
+      wcount(WS_AUX1, len);
+    }
+  }
+  return appended;
+}
+
+// The resident-hit pass as a kernel of its own: it carries no service wavefronts and none
+// of the I/O path's code, so its loop keeps to few registers.
+template <int VPL>
+__global__ __launch_bounds__(WG) void k_embbag_hit(dev_ctx c, launch_t li, embbag_args a, uint32_t* list) {
+  user_wave_begin();
+  const uint32_t uw = blockIdx.x * WPB + threadIdx.x / 64;
+  if (uw < a.active_waves) hit_wave<VPL>(c, a, uw, list);
+  user_wave_done(c, li);
 }
 
 template <int VPL>
@@ -947,8 +1208,22 @@ __device__ __forceinline__ bool cached_read(const dev_ctx& c, uint32_t q, bool a
   return cached_read<T>(c, q, act, byte, out, [] {});
 }
 
+// A store word for the graph kernels: through the cache, or, when `img` is set, straight
+// from a copy of the store image resident in HBM (the kernel-only baseline of Sec. 4.5,
+// where the graph kernels run with no cache, queue or service in the way).
+template <typename T>
+__device__ __forceinline__ bool graph_read(const dev_ctx& c, uint32_t q, const uint8_t* img, bool act, uint64_t byte,
+                                           T& out) {
+  if (img) {
+    if (act) out = *reinterpret_cast<const T*>(img + byte);
+    return true;
+  }
+  return cached_read<T>(c, q, act, byte, out);
+}
+
 struct bfs_args {
   csr_t g;
+  const uint8_t* img;  // resident copy of the store image (NULL: read through the cache)
   const int32_t* F;   // frontier
   uint32_t nF;
   uint64_t* cs;       // compacted: first edge of each frontier vertex with edges
@@ -977,8 +1252,8 @@ __global__ __launch_bounds__(WG) void k_bfs_front(dev_ctx c, launch_t li, bfs_ar
     const uint64_t v = act ? (uint64_t)a.F[base + lane()] : 0;
     const uint64_t b0 = a.g.rp_off + 8 * v;
     int64_t s0 = 0, s1 = 0;
-    if (!cached_read<int64_t>(c, q, act, b0, s0)) break;
-    if (!cached_read<int64_t>(c, q, act, b0 + 8, s1)) break;
+    if (!graph_read<int64_t>(c, q, a.img, act, b0, s0)) break;
+    if (!graph_read<int64_t>(c, q, a.img, act, b0 + 8, s1)) break;
     const bool has = act && s1 > s0;
     const uint64_t hm = ballot(has);
     uint32_t pos = 0;
@@ -1041,7 +1316,7 @@ __global__ __launch_bounds__(WG) void k_bfs_edges(dev_ctx c, launch_t li, bfs_ar
       const uint64_t vs = act ? a.cs[i + k] : 0;
       const uint64_t pos = vs + (my - vo);
       int32_t u = 0;
-      if (!cached_read<int32_t>(c, q, act, a.g.col_off + 4 * pos, u)) goto done;
+      if (!graph_read<int32_t>(c, q, a.img, act, a.g.col_off + 4 * pos, u)) goto done;
       bool added = false;
       if (act && (uint64_t)u < a.g.V) {
         if (__hip_atomic_load(a.level + u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == -1) {
@@ -1073,6 +1348,7 @@ done:
 // for the window and their indices kept in LDS, so lanes with long rows walk them freely.
 struct spmv_args {
   csr_t g;
+  const uint8_t* img;  // resident copy of the store image (NULL: read through the cache)
   const float* x;
   float* y;
   uint32_t active;  // user waves that take work
@@ -1188,16 +1464,20 @@ __device__ __forceinline__ bool spmv_group(const dev_ctx& c, uint32_t q, const s
   yv = 0.0f;
   for (uint64_t w0 = e0; w0 < e1; w0 += W) {
     const uint64_t w1 = (w0 + W < e1) ? w0 + W : e1;
-    uint32_t lc0, lv0;
+    uint32_t lc0 = 0, lv0 = 0;
     chunk_t ch;
+    ch.act = false;
     const uint64_t t_pin = now();
-    if (!spmv_pin(c, q, a, w0, w1, win, lc0, lv0, ch, pf)) return false;
-    const uint64_t t_pre = wtick(c, WS_T_WAIT, t_pin);
-    // this window is pinned: drop the request that brought it, and ask for the next one
-    // (up to `pend`, the end of the wave's run of groups) before computing on this one
-    spmv_drop(c, pf);
-    if (!spmv_prefetch(c, q, a, w1, (w1 + W < pend) ? w1 + W : pend, pf)) return false;
-    const uint64_t t_cons = wtick(c, WS_T_ISSUE, t_pre);
+    uint64_t t_cons = t_pin;
+    if (!a.img) {
+      if (!spmv_pin(c, q, a, w0, w1, win, lc0, lv0, ch, pf)) return false;
+      const uint64_t t_pre = wtick(c, WS_T_WAIT, t_pin);
+      // this window is pinned: drop the request that brought it, and ask for the next one
+      // (up to `pend`, the end of the wave's run of groups) before computing on this one
+      spmv_drop(c, pf);
+      if (!spmv_prefetch(c, q, a, w1, (w1 + W < pend) ? w1 + W : pend, pf)) return false;
+      t_cons = wtick(c, WS_T_ISSUE, t_pre);
+    }
     for (uint64_t k0 = w0; k0 < w1; k0 += 256) {
       float v[4], xv[4];
       int32_t col[4];
@@ -1207,9 +1487,14 @@ __device__ __forceinline__ bool spmv_group(const dev_ctx& c, uint32_t q, const s
         col[u] = -1;
         v[u] = 0.0f;
         if (k < w1) {
-          const spmv_edge e = spmv_load(c, a, win, lc0, lv0, k);
-          col[u] = e.col;
-          v[u] = e.val;
+          if (a.img) {
+            col[u] = *reinterpret_cast<const int32_t*>(a.img + a.g.col_off + 4 * k);
+            v[u] = *reinterpret_cast<const float*>(a.img + a.g.val_off + 4 * k);
+          } else {
+            const spmv_edge e = spmv_load(c, a, win, lc0, lv0, k);
+            col[u] = e.col;
+            v[u] = e.val;
+          }
         }
       }
 #pragma unroll
@@ -1231,8 +1516,10 @@ __device__ __forceinline__ bool spmv_group(const dev_ctx& c, uint32_t q, const s
         }
       }
     }
-    __builtin_amdgcn_wave_barrier();
-    chunk_release(c, ch, false);
+    if (!a.img) {
+      __builtin_amdgcn_wave_barrier();
+      chunk_release(c, ch, false);
+    }
     wtick(c, WS_T_CONSUME, t_cons);
   }
   // the row being folded when the edges ran out; the rows after it have no edges
@@ -1266,15 +1553,24 @@ __global__ __launch_bounds__(WG) void k_spmv(dev_ctx c, launch_t li, spmv_args a
     const uint64_t rr1 = (a.g.V - rr0) < 64 * SPMV_RUN ? a.g.V : rr0 + 64 * SPMV_RUN;
     auto drop = [&] { spmv_drop(c, pf); };
     int64_t pend = 0;
-    if (!cached_read<int64_t>(c, q, lane() == 0, a.g.rp_off + 8 * rr1, pend, drop)) goto done;
+    if (a.img) {
+      if (lane() == 0) pend = *reinterpret_cast<const int64_t*>(a.img + a.g.rp_off + 8 * rr1);
+    } else if (!cached_read<int64_t>(c, q, lane() == 0, a.g.rp_off + 8 * rr1, pend, drop)) {
+      goto done;
+    }
     pend = (int64_t)rdlane64((uint64_t)pend, 0);
     for (uint64_t r0 = rr0; r0 < rr1; r0 += 64) {
       const uint32_t nr = (uint32_t)((rr1 - r0) < 64 ? (rr1 - r0) : 64);
       const bool act = lane() < nr;
       int64_t rs = 0, rend = 0;
       const uint64_t t_desc = now();
-      if (!cached_read<int64_t>(c, q, act, a.g.rp_off + 8 * (r0 + lane()), rs, drop)) goto done;
-      if (!cached_read<int64_t>(c, q, lane() == 0, a.g.rp_off + 8 * (r0 + nr), rend, drop)) goto done;
+      if (a.img) {
+        if (act) rs = *reinterpret_cast<const int64_t*>(a.img + a.g.rp_off + 8 * (r0 + lane()));
+        if (lane() == 0) rend = *reinterpret_cast<const int64_t*>(a.img + a.g.rp_off + 8 * (r0 + nr));
+      } else {
+        if (!cached_read<int64_t>(c, q, act, a.g.rp_off + 8 * (r0 + lane()), rs, drop)) goto done;
+        if (!cached_read<int64_t>(c, q, lane() == 0, a.g.rp_off + 8 * (r0 + nr), rend, drop)) goto done;
+      }
       wtick(c, WS_T_DESC, t_desc);
       rend = (int64_t)rdlane64((uint64_t)rend, 0);
       int64_t re = (int64_t)shfl64((uint64_t)rs, (lane() + 1) & 63);
@@ -1371,8 +1667,12 @@ struct agile_ctx_s {
   std::vector<int> occ_cache;  // resident workgroups per CU, per kernel kind
   void* scratch = nullptr;     // backward-pass work arrays, grown on demand
   size_t scratch_bytes = 0;
-  uint32_t iso_lds = 0;        // dynamic LDS that makes one workgroup fill a CU
+  uint32_t iso_lds = 0;        // LDS per workgroup that makes one workgroup fill a CU
+  std::vector<std::pair<const void*, uint32_t>> dyn_lds;  // per kernel: dynamic LDS to add
   void* noalloc_scratch = nullptr;  // device address of `scratch` on this context's device
+  uint32_t* defer_list = nullptr;   // bags the resident-hit pass leaves to the I/O pass
+  uint64_t defer_cap = 0;
+  int hit_occ[3] = {0, 0, 0};       // resident workgroups per CU of k_embbag_hit<1, 2, 4>
 };
 
 namespace {
@@ -1413,26 +1713,34 @@ agile_status dalloc(agile_ctx ctx, T** p, size_t bytes) {
   return AGILE_OK;
 }
 
+// Dynamic LDS a launch of kernel f adds (see agile_init).
+uint32_t lds_of(agile_ctx ctx, const void* f) {
+  for (const auto& e : ctx->dyn_lds)
+    if (e.first == f) return e.second;
+  return 0;
+}
+
 int occupancy(agile_ctx ctx, int kind) {
   int& v = ctx->occ_cache[kind];
   if (v > 0) return v;
   int nb = 0;
   hipError_t e = hipSuccess;
-  const size_t L = ctx->iso_lds;
+  const void* f;
   switch (kind) {
-    case KIND_EMBBAG1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_embbag<1>, WG, L); break;
-    case KIND_EMBBAG2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_embbag<2>, WG, L); break;
-    case KIND_EMBBAG4: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_embbag<4>, WG, L); break;
-    case KIND_READ: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_async_read, WG, L); break;
-    case KIND_FLUSH: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_flush, WG, L); break;
-    case KIND_BWD1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_bwd_sgd<1>, WG, L); break;
-    case KIND_BWD2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_bwd_sgd<2>, WG, L); break;
-    case KIND_BWD4: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_bwd_sgd<4>, WG, L); break;
-    case KIND_SERVE1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_serve<1>, WG, L); break;
-    case KIND_SERVE2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_serve<2>, WG, L); break;
-    case KIND_SERVE4: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_serve<4>, WG, L); break;
-    default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_trace, WG, L); break;
+    case KIND_EMBBAG1: f = (const void*)k_embbag<1>; break;
+    case KIND_EMBBAG2: f = (const void*)k_embbag<2>; break;
+    case KIND_EMBBAG4: f = (const void*)k_embbag<4>; break;
+    case KIND_READ: f = (const void*)k_async_read; break;
+    case KIND_FLUSH: f = (const void*)k_flush; break;
+    case KIND_BWD1: f = (const void*)k_bwd_sgd<1>; break;
+    case KIND_BWD2: f = (const void*)k_bwd_sgd<2>; break;
+    case KIND_BWD4: f = (const void*)k_bwd_sgd<4>; break;
+    case KIND_SERVE1: f = (const void*)k_serve<1>; break;
+    case KIND_SERVE2: f = (const void*)k_serve<2>; break;
+    case KIND_SERVE4: f = (const void*)k_serve<4>; break;
+    default: f = (const void*)k_trace; break;
   }
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, f, WG, lds_of(ctx, f));
   if (e != hipSuccess || nb <= 0) nb = 1;
   v = nb;
   return v;
@@ -1620,17 +1928,25 @@ agile_status agile_init(const agile_config* cfg_in, agile_ctx* out) {
     int lds_cu = 0;
     if (hipDeviceGetAttribute(&lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, cfg.device) != hipSuccess)
       lds_cu = 0;
-    uint32_t iso = lds_cu > 0 ? (uint32_t)((lds_cu / 2 + 1024 + 255) & ~255) : 0u;
+    // (a kernel whose own static LDS is already that large adds nothing)
+    const uint32_t iso = lds_cu > 0 ? (uint32_t)((lds_cu / 2 + 1024 + 255) & ~255) : 0u;
     const void* fns[] = {(const void*)k_async_read, (const void*)k_flush, (const void*)k_embbag<1>,
                          (const void*)k_embbag<2>, (const void*)k_embbag<4>, (const void*)k_bfs_front,
                          (const void*)k_bfs_edges, (const void*)k_spmv, (const void*)k_bwd_sgd<1>,
                          (const void*)k_bwd_sgd<2>, (const void*)k_bwd_sgd<4>, (const void*)k_serve<1>,
                          (const void*)k_serve<2>, (const void*)k_serve<4>, (const void*)k_trace};
-    for (const void* f : fns)
-      if (iso && hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)iso) != hipSuccess) {
-        (void)hipGetLastError();
-        iso = 0;
+    for (const void* f : fns) {
+      hipFuncAttributes fa;
+      memset(&fa, 0, sizeof(fa));
+      uint32_t dyn = 0;
+      if (iso && hipFuncGetAttributes(&fa, f) == hipSuccess) {
+        const uint32_t st = (uint32_t)fa.sharedSizeBytes;
+        dyn = st < iso ? iso - st : 0u;
+        if (dyn && hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn) != hipSuccess) dyn = 0;
       }
+      (void)hipGetLastError();
+      ctx->dyn_lds.emplace_back(f, dyn);
+    }
     ctx->iso_lds = iso;
   }
   ctx->n_ctrl = n_ctrl;
@@ -1670,6 +1986,8 @@ agile_status agile_init(const agile_config* cfg_in, agile_ctx* out) {
   if ((s = dalloc(ctx, &d.qp, (uint64_t)cfg.num_qp * sizeof(qp_t))) != AGILE_OK) return bail(s);
   if ((s = dalloc(ctx, &d.next_tok, 128)) != AGILE_OK) return bail(s);
   if ((s = dalloc(ctx, &d.cnt, (uint64_t)C_COUNT * CSTRIDE * 8)) != AGILE_OK) return bail(s);
+  ctx->defer_cap = 1ull << 20;  // bags per launch the resident-hit pass can take (4 MiB list)
+  if ((s = dalloc(ctx, &ctx->defer_list, ctx->defer_cap * 4)) != AGILE_OK) return bail(s);
   if ((s = dalloc(ctx, &d.err, 128)) != AGILE_OK) return bail(s);
   if ((s = dalloc(ctx, &d.err_info, 128)) != AGILE_OK) return bail(s);
   if ((s = dalloc(ctx, &d.abort_dev, 128)) != AGILE_OK) return bail(s);
@@ -1806,7 +2124,7 @@ agile_status agile_async_read(agile_ctx ctx, agile_store store, const uint64_t* 
   uint32_t uw = std::min<uint32_t>((n + 63) / 64, user_wave_cap(ctx, KIND_READ));
   uw = (uw + WPB - 1) / WPB * WPB;
   launch_t li = make_launch(ctx, uw, true);
-  hipLaunchKernelGGL(k_async_read, dim3(li.service_blocks + uw / WPB), dim3(WG), ctx->iso_lds, (hipStream_t)stream,
+  hipLaunchKernelGGL(k_async_read, dim3(li.service_blocks + uw / WPB), dim3(WG), lds_of(ctx, (const void*)k_async_read), (hipStream_t)stream,
                      ctx->d, li, d_blocks, n, d_tickets);
   HIPCHK(ctx, hipGetLastError());
   return AGILE_OK;
@@ -1854,7 +2172,7 @@ agile_status agile_flush(agile_ctx ctx, agile_store store, void* stream) {
   uint32_t uw = std::min<uint32_t>((ctx->d.num_lines + 63) / 64, user_wave_cap(ctx, KIND_FLUSH));
   uw = (uw + WPB - 1) / WPB * WPB;
   launch_t li = make_launch(ctx, uw, true);
-  hipLaunchKernelGGL(k_flush, dim3(li.service_blocks + uw / WPB), dim3(WG), ctx->iso_lds, hs, ctx->d, li);
+  hipLaunchKernelGGL(k_flush, dim3(li.service_blocks + uw / WPB), dim3(WG), lds_of(ctx, (const void*)k_flush), hs, ctx->d, li);
   HIPCHK(ctx, hipGetLastError());
   return sync_stream(ctx, hs);
 }
@@ -1882,7 +2200,9 @@ agile_status agile_get_stats(agile_ctx ctx, agile_stats* out, int reset) {
   out->rows_updated = g(C_WROWS);
   if (reset) {
     const uint32_t keep[] = {C_SUBMITTED, C_COMPLETED, C_USER_DONE, C_WORK, C_SVC_EXIT, C_IMG_EPOCH,
-                             C_WORK_P1, C_WORK_P2, C_WORK_P3, C_WORK_P4, C_WORK_P5, C_WORK_P6, C_WORK_P7};
+                             C_WORK_P1, C_WORK_P2, C_WORK_P3, C_WORK_P4, C_WORK_P5, C_WORK_P6, C_WORK_P7,
+                             C_DEFER, C_HWORK, C_HWORK_P1, C_HWORK_P2, C_HWORK_P3, C_HWORK_P4, C_HWORK_P5,
+                             C_HWORK_P6, C_HWORK_P7, C_EXH, C_HEXH};
     for (uint32_t i = 0; i < C_COUNT; ++i) {
       if (std::find(std::begin(keep), std::end(keep), i) != std::end(keep)) continue;
       HIPCHK(ctx, hipMemset(ctx->d.cnt + (size_t)i * CSTRIDE, 0, 8));
@@ -1912,7 +2232,14 @@ agile_status agile_get_info(agile_ctx ctx, agile_info* out) {
   out->max_user_waves = user_wave_cap(ctx, KIND_EMBBAG2);
   out->wallclock_hz = ctx->clock_hz;
   out->cache_base = (uint64_t)(uintptr_t)ctx->d.lines;
-  out->service_lds_bytes = ctx->iso_lds;
+  {
+    hipFuncAttributes fa;
+    memset(&fa, 0, sizeof(fa));
+    const void* f = (const void*)k_embbag<2>;
+    const uint32_t st = hipFuncGetAttributes(&fa, f) == hipSuccess ? (uint32_t)fa.sharedSizeBytes : 0u;
+    (void)hipGetLastError();
+    out->service_lds_bytes = st + lds_of(ctx, f);
+  }
   out->service_blocks = ctx->service_blocks;
   return AGILE_OK;
 }
@@ -1965,15 +2292,44 @@ static agile_status embbag_launch(agile_ctx ctx, agile_store store, const agile_
   }
   a.active_waves = active;
   const bool serial = (ctx->cfg.flags & AGILE_F_SERIALIZED) != 0;
+  hipStream_t hs = (hipStream_t)stream;
+  // the resident-hit pass first (see hit_wave), when the deferred list can hold every
+  // bag; the I/O launch then runs only the bags it deferred.  Both launches are stream
+  // ordered; the I/O launch's last service wavefront clears the pass's counters, so the
+  // pair can be captured in a graph and replayed.
+  if (!serial && a.nbags <= ctx->defer_cap) {
+    const int vi = kind == KIND_EMBBAG1 ? 0 : (kind == KIND_EMBBAG2 ? 1 : 2);
+    int& occ = ctx->hit_occ[vi];
+    const void* hf = vi == 0 ? (const void*)k_embbag_hit<1> : (vi == 1 ? (const void*)k_embbag_hit<2>
+                                                                       : (const void*)k_embbag_hit<4>);
+    if (occ <= 0) {
+      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, hf, WG, 0) != hipSuccess || occ <= 0) occ = 1;
+      (void)hipGetLastError();
+    }
+    uint64_t hw = (uint64_t)occ * ctx->cu_count * WPB;
+    if (ctx->cfg.max_user_waves) hw = std::min<uint64_t>(hw, ctx->cfg.max_user_waves);
+    hw = std::max<uint64_t>(1, std::min<uint64_t>(hw, a.nbags));
+    embbag_args h = a;
+    h.active_waves = (uint32_t)hw;
+    const uint32_t huw = (uint32_t)((hw + WPB - 1) / WPB * WPB);
+    const launch_t lh = make_launch(ctx, huw, false);
+    if (vi == 0)
+      hipLaunchKernelGGL(k_embbag_hit<1>, dim3(huw / WPB), dim3(WG), 0, hs, ctx->d, lh, h, ctx->defer_list);
+    else if (vi == 1)
+      hipLaunchKernelGGL(k_embbag_hit<2>, dim3(huw / WPB), dim3(WG), 0, hs, ctx->d, lh, h, ctx->defer_list);
+    else
+      hipLaunchKernelGGL(k_embbag_hit<4>, dim3(huw / WPB), dim3(WG), 0, hs, ctx->d, lh, h, ctx->defer_list);
+    HIPCHK(ctx, hipGetLastError());
+    a.list = ctx->defer_list;
+  }
   launch_t li = make_launch(ctx, uw, true);
   const dim3 grid(li.service_blocks + uw / WPB);
-  hipStream_t hs = (hipStream_t)stream;
   if (kind == KIND_EMBBAG1)
-    hipLaunchKernelGGL(k_embbag<1>, grid, dim3(WG), ctx->iso_lds, hs, ctx->d, li, a);
+    hipLaunchKernelGGL(k_embbag<1>, grid, dim3(WG), lds_of(ctx, (const void*)k_embbag<1>), hs, ctx->d, li, a);
   else if (kind == KIND_EMBBAG2)
-    hipLaunchKernelGGL(k_embbag<2>, grid, dim3(WG), ctx->iso_lds, hs, ctx->d, li, a);
+    hipLaunchKernelGGL(k_embbag<2>, grid, dim3(WG), lds_of(ctx, (const void*)k_embbag<2>), hs, ctx->d, li, a);
   else
-    hipLaunchKernelGGL(k_embbag<4>, grid, dim3(WG), ctx->iso_lds, hs, ctx->d, li, a);
+    hipLaunchKernelGGL(k_embbag<4>, grid, dim3(WG), lds_of(ctx, (const void*)k_embbag<4>), hs, ctx->d, li, a);
   HIPCHK(ctx, hipGetLastError());
   return AGILE_OK;
 }
@@ -2005,14 +2361,14 @@ static agile_status ensure_scratch(agile_ctx ctx, size_t need, hipStream_t hs) {
   return AGILE_OK;
 }
 
-static agile_status check_csr(agile_ctx ctx, agile_store store, const agile_csr* g, bool need_val) {
+static agile_status check_csr(agile_ctx ctx, uint64_t bytes, const agile_csr* g, bool need_val) {
   if (!g) return fail(ctx, AGILE_EINVAL, "graph: null csr");
   if (g->num_vertices == 0 || g->num_vertices >= (1ull << 31))
     return fail(ctx, AGILE_EINVAL, "graph: vertex count must be 1..2^31-1");
   if (g->row_ptr_offset % 8 || g->col_offset % 4 || g->val_offset % 4)
     return fail(ctx, AGILE_EINVAL, "graph: misaligned arrays");
-  if (g->row_ptr_offset + 8 * (g->num_vertices + 1) > store->bytes || g->col_offset + 4 * g->num_edges > store->bytes ||
-      (need_val && g->val_offset + 4 * g->num_edges > store->bytes))
+  if (g->row_ptr_offset + 8 * (g->num_vertices + 1) > bytes || g->col_offset + 4 * g->num_edges > bytes ||
+      (need_val && g->val_offset + 4 * g->num_edges > bytes))
     return fail(ctx, AGILE_EINVAL, "graph: arrays exceed the store");
   return AGILE_OK;
 }
@@ -2039,14 +2395,33 @@ __global__ void k_bfs_init(int32_t* level, uint64_t V, uint64_t src, int32_t* F)
   if (i == 0) F[0] = (int32_t)src;
 }
 
+static agile_status bfs_run(agile_ctx ctx, const agile_csr* g, uint64_t src, int32_t* d_level, uint32_t* out_levels,
+                            hipStream_t hs, const uint8_t* img);
+
 agile_status agile_bfs(agile_ctx ctx, agile_store store, const agile_csr* g, uint64_t src, int32_t* d_level,
                        uint32_t* out_levels, void* stream) {
   agile_status s = check_usable(ctx);
   if (s) return s;
   if (store != ctx->store) return fail(ctx, AGILE_EINVAL, "bfs: store is not open on this context");
-  if ((s = check_csr(ctx, store, g, false)) != AGILE_OK) return s;
+  if ((s = check_csr(ctx, store->bytes, g, false)) != AGILE_OK) return s;
   if (!d_level || src >= g->num_vertices) return fail(ctx, AGILE_EINVAL, "bfs: bad level array or source");
-  hipStream_t hs = (hipStream_t)stream;
+  return bfs_run(ctx, g, src, d_level, out_levels, (hipStream_t)stream, nullptr);
+}
+
+agile_status agile_bfs_resident(agile_ctx ctx, const void* d_image, uint64_t image_bytes, const agile_csr* g,
+                                uint64_t src, int32_t* d_level, uint32_t* out_levels, void* stream) {
+  agile_status s = check_usable(ctx);
+  if (s) return s;
+  if (!d_image) return fail(ctx, AGILE_EINVAL, "bfs_resident: null image");
+  if ((s = check_csr(ctx, image_bytes, g, false)) != AGILE_OK) return s;
+  if (!d_level || src >= g->num_vertices) return fail(ctx, AGILE_EINVAL, "bfs: bad level array or source");
+  return bfs_run(ctx, g, src, d_level, out_levels, (hipStream_t)stream, (const uint8_t*)d_image);
+}
+
+static agile_status bfs_run(agile_ctx ctx, const agile_csr* g, uint64_t src, int32_t* d_level, uint32_t* out_levels,
+                            hipStream_t hs, const uint8_t* img) {
+  agile_status s = AGILE_OK;
+  const bool svc = img == nullptr;  // a resident image needs no service wavefronts
   const uint64_t V = g->num_vertices;
   const size_t scan_bytes = 8 * sort::scan_work_elems(V);
   auto al = [](size_t v) { return (v + 255) & ~(size_t)255; };
@@ -2056,6 +2431,7 @@ agile_status agile_bfs(agile_ctx ctx, agile_store store, const agile_csr* g, uin
   uint8_t* sb = (uint8_t*)ctx->scratch;
   bfs_args a{};
   a.g = to_csr(g);
+  a.img = img;
   a.cs = (uint64_t*)(sb + ocs);
   a.cd = (uint64_t*)(sb + ocd);
   a.co = (uint64_t*)(sb + oco);
@@ -2082,8 +2458,8 @@ agile_status agile_bfs(agile_ctx ctx, agile_store store, const agile_csr* g, uin
     hipLaunchKernelGGL(k_zero32, dim3(1), dim3(64), 0, hs, a.ctr, 64u);
     uint32_t uw = (uint32_t)std::min<uint64_t>({(nF + 63) / 64, (uint64_t)user_wave_cap(ctx, KIND_READ), by_cache});
     uw = (uw + WPB - 1) / WPB * WPB;
-    launch_t li = make_launch(ctx, uw, true);
-    hipLaunchKernelGGL(k_bfs_front, dim3(li.service_blocks + uw / WPB), dim3(WG), ctx->iso_lds, hs, ctx->d, li, a);
+    launch_t li = make_launch(ctx, uw, svc);
+    hipLaunchKernelGGL(k_bfs_front, dim3(li.service_blocks + uw / WPB), dim3(WG), lds_of(ctx, (const void*)k_bfs_front), hs, ctx->d, li, a);
     HIPCHK(ctx, hipGetLastError());
     uint32_t nC = 0;
     HIPCHK(ctx, hipMemcpyAsync(&nC, a.ctr, 4, hipMemcpyDeviceToHost, hs));
@@ -2099,8 +2475,8 @@ agile_status agile_bfs(agile_ctx ctx, agile_store store, const agile_csr* g, uin
     a.Et = last[0] + last[1];
     uw = (uint32_t)std::min<uint64_t>({(a.Et + 1023) / 1024, (uint64_t)user_wave_cap(ctx, KIND_READ), by_cache});
     uw = (uw + WPB - 1) / WPB * WPB;
-    li = make_launch(ctx, uw, true);
-    hipLaunchKernelGGL(k_bfs_edges, dim3(li.service_blocks + uw / WPB), dim3(WG), ctx->iso_lds, hs, ctx->d, li, a);
+    li = make_launch(ctx, uw, svc);
+    hipLaunchKernelGGL(k_bfs_edges, dim3(li.service_blocks + uw / WPB), dim3(WG), lds_of(ctx, (const void*)k_bfs_edges), hs, ctx->d, li, a);
     HIPCHK(ctx, hipGetLastError());
     HIPCHK(ctx, hipMemcpyAsync(&nF, a.ctr + 1, 4, hipMemcpyDeviceToHost, hs));
     if ((s = sync_stream(ctx, hs)) != AGILE_OK) return s;
@@ -2112,17 +2488,34 @@ agile_status agile_bfs(agile_ctx ctx, agile_store store, const agile_csr* g, uin
   return AGILE_OK;
 }
 
+static agile_status spmv_run(agile_ctx ctx, const agile_csr* g, const float* d_x, float* d_y, hipStream_t hs,
+                             const uint8_t* img);
+
 agile_status agile_spmv(agile_ctx ctx, agile_store store, const agile_csr* g, const float* d_x, float* d_y,
                         void* stream) {
   agile_status s = check_usable(ctx);
   if (s) return s;
   if (store != ctx->store) return fail(ctx, AGILE_EINVAL, "spmv: store is not open on this context");
-  if ((s = check_csr(ctx, store, g, true)) != AGILE_OK) return s;
+  if ((s = check_csr(ctx, store->bytes, g, true)) != AGILE_OK) return s;
   if (!d_x || !d_y) return fail(ctx, AGILE_EINVAL, "spmv: null vector");
-  if (ctx->cfg.line_bytes < 4096) return fail(ctx, AGILE_EINVAL, "spmv: line too small");
-  hipStream_t hs = (hipStream_t)stream;
+  return spmv_run(ctx, g, d_x, d_y, (hipStream_t)stream, nullptr);
+}
+
+agile_status agile_spmv_resident(agile_ctx ctx, const void* d_image, uint64_t image_bytes, const agile_csr* g,
+                                 const float* d_x, float* d_y, void* stream) {
+  agile_status s = check_usable(ctx);
+  if (s) return s;
+  if (!d_image) return fail(ctx, AGILE_EINVAL, "spmv_resident: null image");
+  if ((s = check_csr(ctx, image_bytes, g, true)) != AGILE_OK) return s;
+  if (!d_x || !d_y) return fail(ctx, AGILE_EINVAL, "spmv: null vector");
+  return spmv_run(ctx, g, d_x, d_y, (hipStream_t)stream, (const uint8_t*)d_image);
+}
+
+static agile_status spmv_run(agile_ctx ctx, const agile_csr* g, const float* d_x, float* d_y, hipStream_t hs,
+                             const uint8_t* img) {
   spmv_args a{};
   a.g = to_csr(g);
+  a.img = img;
   a.x = d_x;
   a.y = d_y;
   const uint64_t by_cache = std::max<uint64_t>(1, ctx->d.num_lines / 32);
@@ -2131,9 +2524,14 @@ agile_status agile_spmv(agile_ctx ctx, agile_store store, const agile_csr* g, co
       {(g->num_vertices + 64 * SPMV_RUN - 1) / (64 * SPMV_RUN), (uint64_t)user_wave_cap(ctx, KIND_READ), by_cache});
   a.active = std::max<uint32_t>(1, active);
   const uint32_t uw = (a.active + WPB - 1) / WPB * WPB;
-  launch_t li = make_launch(ctx, uw, true);
-  hipLaunchKernelGGL(k_spmv, dim3(li.service_blocks + uw / WPB), dim3(WG), ctx->iso_lds, hs, ctx->d, li, a);
+  // without service wavefronts nobody clears the launch's work counter on exit: clear it
+  // before and after the launch
+  uint32_t* work = reinterpret_cast<uint32_t*>(ctx->d.cnt + (size_t)C_WORK * CSTRIDE);
+  if (img) hipLaunchKernelGGL(k_zero32, dim3(1), dim3(64), 0, hs, work, 2u);
+  launch_t li = make_launch(ctx, uw, img == nullptr);
+  hipLaunchKernelGGL(k_spmv, dim3(li.service_blocks + uw / WPB), dim3(WG), lds_of(ctx, (const void*)k_spmv), hs, ctx->d, li, a);
   HIPCHK(ctx, hipGetLastError());
+  if (img) hipLaunchKernelGGL(k_zero32, dim3(1), dim3(64), 0, hs, work, 2u);
   return AGILE_OK;
 }
 
@@ -2228,11 +2626,11 @@ static agile_status bwd_launch(agile_ctx ctx, const agile_tables* tb, const int6
   launch_t li = make_launch(ctx, uw, true);
   const dim3 grid(li.service_blocks + uw / WPB);
   if (kind == KIND_BWD1)
-    hipLaunchKernelGGL(k_bwd_sgd<1>, grid, dim3(WG), ctx->iso_lds, hs, ctx->d, li, a);
+    hipLaunchKernelGGL(k_bwd_sgd<1>, grid, dim3(WG), lds_of(ctx, (const void*)k_bwd_sgd<1>), hs, ctx->d, li, a);
   else if (kind == KIND_BWD2)
-    hipLaunchKernelGGL(k_bwd_sgd<2>, grid, dim3(WG), ctx->iso_lds, hs, ctx->d, li, a);
+    hipLaunchKernelGGL(k_bwd_sgd<2>, grid, dim3(WG), lds_of(ctx, (const void*)k_bwd_sgd<2>), hs, ctx->d, li, a);
   else
-    hipLaunchKernelGGL(k_bwd_sgd<4>, grid, dim3(WG), ctx->iso_lds, hs, ctx->d, li, a);
+    hipLaunchKernelGGL(k_bwd_sgd<4>, grid, dim3(WG), lds_of(ctx, (const void*)k_bwd_sgd<4>), hs, ctx->d, li, a);
   HIPCHK(ctx, hipGetLastError());
   return AGILE_OK;
 }
@@ -2361,11 +2759,11 @@ agile_status agile_serve(agile_ctx ctx, agile_store store, const agile_tables* t
   li.service_blocks = svc_blocks;
   const dim3 grid(li.service_blocks + uw / WPB);
   if (kind == KIND_SERVE1)
-    hipLaunchKernelGGL(k_serve<1>, grid, dim3(WG), ctx->iso_lds, hs, ctx->d, li, a, (uint32_t)nreq, (uint32_t*)(sb + o_pub));
+    hipLaunchKernelGGL(k_serve<1>, grid, dim3(WG), lds_of(ctx, (const void*)k_serve<1>), hs, ctx->d, li, a, (uint32_t)nreq, (uint32_t*)(sb + o_pub));
   else if (kind == KIND_SERVE2)
-    hipLaunchKernelGGL(k_serve<2>, grid, dim3(WG), ctx->iso_lds, hs, ctx->d, li, a, (uint32_t)nreq, (uint32_t*)(sb + o_pub));
+    hipLaunchKernelGGL(k_serve<2>, grid, dim3(WG), lds_of(ctx, (const void*)k_serve<2>), hs, ctx->d, li, a, (uint32_t)nreq, (uint32_t*)(sb + o_pub));
   else
-    hipLaunchKernelGGL(k_serve<4>, grid, dim3(WG), ctx->iso_lds, hs, ctx->d, li, a, (uint32_t)nreq, (uint32_t*)(sb + o_pub));
+    hipLaunchKernelGGL(k_serve<4>, grid, dim3(WG), lds_of(ctx, (const void*)k_serve<4>), hs, ctx->d, li, a, (uint32_t)nreq, (uint32_t*)(sb + o_pub));
   HIPCHK(ctx, hipGetLastError());
   // ---- host loop: publish arrivals in real time, admit by queue and cache budget, and
   //      record when each request's outputs become visible
@@ -2454,7 +2852,7 @@ agile_status agile_debug_trace(agile_ctx ctx, agile_store store, const uint64_t*
   if (n == 0) return AGILE_OK;
   if (!d_lines || !d_hit || !d_way) return fail(ctx, AGILE_EINVAL, "trace: null pointer");
   launch_t li = make_launch(ctx, WPB, true);
-  hipLaunchKernelGGL(k_trace, dim3(li.service_blocks + 1), dim3(WG), ctx->iso_lds, (hipStream_t)stream, ctx->d, li, d_lines,
+  hipLaunchKernelGGL(k_trace, dim3(li.service_blocks + 1), dim3(WG), lds_of(ctx, (const void*)k_trace), (hipStream_t)stream, ctx->d, li, d_lines,
                      d_writes, n, d_hit, d_way);
   HIPCHK(ctx, hipGetLastError());
   return sync_stream(ctx, (hipStream_t)stream);

@@ -155,7 +155,10 @@ enum : uint32_t {
   P_CQ_IDLE, P_U_ISSUE, P_U_SUBMIT, P_U_WAIT, P_U_CONSUME, P_TOK_LEAD, P_TOK_N, P_U_DESC,
   P_U_LIFE, C_SVC_EXIT, C_IMG_EPOCH,
   // work counters of partitions 1..7 (partition 0 is C_WORK)
-  C_WORK_P1, C_WORK_P2, C_WORK_P3, C_WORK_P4, C_WORK_P5, C_WORK_P6, C_WORK_P7, C_COUNT
+  C_WORK_P1, C_WORK_P2, C_WORK_P3, C_WORK_P4, C_WORK_P5, C_WORK_P6, C_WORK_P7,
+  // resident-hit pass: bags it deferred to the I/O pass, its work counters (partitions)
+  C_DEFER, C_HWORK, C_HWORK_P1, C_HWORK_P2, C_HWORK_P3, C_HWORK_P4, C_HWORK_P5, C_HWORK_P6,
+  C_HWORK_P7, C_EXH, C_HEXH, C_COUNT
 };
 constexpr uint32_t CSTRIDE = 16;  // u64 per counter
 
@@ -862,6 +865,11 @@ __device__ __forceinline__ void run_service(const dev_ctx& c, const launch_t& li
     if (n == (uint64_t)li.n_ctrl + li.n_cq) {
       st_rlx(counter(c, C_USER_DONE), 0ull);
       for (uint32_t p = 0; p < WORK_PARTS; ++p) st_rlx(counter(c, work_counter(p)), 0ull);
+      // and those of the resident-hit pass that ran before this launch, if any
+      st_rlx(counter(c, C_DEFER), 0ull);
+      st_rlx(counter(c, C_EXH), 0ull);
+      st_rlx(counter(c, C_HEXH), 0ull);
+      for (uint32_t p = 0; p < WORK_PARTS; ++p) st_rlx(counter(c, C_HWORK + p), 0ull);
       st_rel(counter(c, C_SVC_EXIT), 0ull);
     }
   }
@@ -990,6 +998,93 @@ __device__ __forceinline__ int probe_set(const dev_ctx& c, uint32_t base, uint32
     if (f >= 0) return f;
   }
   return -1;
+}
+
+// LDS-staged probe of a whole wave's sets (level-2 coalescing, Sec. 3.3.2 / Sec. 3.4).
+// A lane-per-lookup probe reads its set with one load per way, so one wave instruction
+// touches 64 different metadata lines; here the wave instead copies the sets of its
+// lookups into LDS with 16-byte global-to-LDS loads, each instruction moving 64 / (A/2)
+// whole sets of A 8-byte words (A = assoc) as contiguous bytes: one request per
+// metadata line instead of one per word.  Then every lane compares its own set's words
+// in LDS.  The loads bypass registers (LDS DMA) and are device-coherent.  The copies land
+// set-major (set t of the pass at 8A * t), and a lane reads its set's 16-byte pairs in an
+// order rotated by its slot, so that the eight lanes the LDS serves together read eight
+// different 16-byte columns of the 128-byte bank row.
+constexpr uint32_t PROBE_LDS = 8192;  // bytes of LDS per wavefront
+struct alignas(16) probe_lds_t {
+  uint8_t b[WPB][PROBE_LDS];
+};
+__device__ __forceinline__ uint8_t* probe_area() {
+  __shared__ probe_lds_t s;
+  return s.b[threadIdx.x / 64];
+}
+// Sets of one load pass: 8 KiB of LDS per wave holds 1024 / A sets.
+__host__ __device__ constexpr bool probe_staged_ok(uint32_t assoc) {
+  return assoc >= 2 && assoc <= 64 && (assoc & (assoc - 1)) == 0;
+}
+typedef __attribute__((address_space(3))) void lds_void;
+typedef unsigned int lds_u32x4_t __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(3))) lds_u32x4_t lds_u32x4;
+
+// Lanes with `want` probe the set starting at line index `base` for `tag`; returns the
+// way (or -1) and the word seen.  Every lane of the wave must call it.
+__device__ __forceinline__ int probe_staged(const dev_ctx& c, bool want, uint32_t base, uint32_t tag,
+                                            uint64_t& seen) {
+  const uint32_t A = c.assoc;
+  const uint32_t P = A / 2;                            // 16-byte pairs per set
+  const uint32_t pl = (uint32_t)__builtin_ctz(P);      // log2 P
+  const uint32_t per = A <= 16 ? 64u : 1024u / A;      // sets per pass
+  const uint32_t spi = 64u >> pl;                      // sets per load instruction
+  const uint32_t rl = P >= 8 ? 0u : 3u - pl;           // log2 of the slots per rotation step
+  const uint32_t me = lane();
+  const uint64_t wm = ballot(want);
+  uint8_t* lds = probe_area();
+  int way = -1;
+  for (uint32_t s0 = 0; s0 < 64; s0 += per) {
+    if (!((wm >> s0) & (per == 64 ? ~0ull : ((1ull << per) - 1ull)))) continue;
+    const uint32_t ninstr = per / spi;
+    for (uint32_t i = 0; i < ninstr; ++i) {
+      const uint32_t t = i * spi + (me >> pl);  // slot within the pass
+      const uint32_t sb = shfl32(base, s0 + t);
+      if ((wm >> (s0 + t)) & 1ull) {
+        const uint64_t* src = c.meta + sb + 2 * (me & (P - 1));
+        __builtin_amdgcn_global_load_lds((const void*)src, (lds_void*)(lds + i * 1024u), 16, 0,
+                                         16 /* sc1: device-coherent */);
+      }
+    }
+    // the LDS copies have landed once this wave's vector memory counter drains; the
+    // empty asm keeps the compiler from moving the LDS reads above the wait
+    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
+    asm volatile("" ::: "memory");
+    const uint32_t t = me - s0;
+    if (want && me >= s0 && me < s0 + per) {
+      const uint32_t rot = t >> rl;
+      const uint8_t* row = lds + t * 8u * A;
+      for (uint32_t j0 = 0; j0 < P && way < 0; j0 += 4) {
+        lds_u32x4_t v[4];
+#pragma unroll
+        for (uint32_t u = 0; u < 4; ++u)
+          if (j0 + u < P) v[u] = *(const lds_u32x4*)(row + 16u * ((j0 + u + rot) & (P - 1)));
+#pragma unroll
+        for (uint32_t u = 0; u < 4; ++u) {
+          if (j0 + u >= P || way >= 0) continue;
+          const uint32_t p = (j0 + u + rot) & (P - 1);
+          const uint64_t w0 = ((uint64_t)v[u].y << 32) | v[u].x;
+          const uint64_t w1 = ((uint64_t)v[u].w << 32) | v[u].z;
+          if (m_tag(w0) == tag && m_state(w0) != ST_INVALID) {
+            way = (int)(2 * p);
+            seen = w0;
+          } else if (m_tag(w1) == tag && m_state(w1) != ST_INVALID) {
+            way = (int)(2 * p + 1);
+            seen = w1;
+          }
+        }
+      }
+    }
+  }
+  // the next staged probe of this wave overwrites the area: its reads above are done
+  // (their values were used), and no other wave touches it
+  return way;
 }
 
 // `cnt` == 0 asks for an unpinned hit: a resident or in-flight line is reported with its
@@ -1161,17 +1256,19 @@ __device__ __forceinline__ bool chunk_issue(const dev_ctx& c, chunk_t& ch, uint3
   if (pin_mode == PIN_NONE && probe_first) {
     // optimistic readers: every lane first probes its own set; a resident or in-flight
     // line is taken unpinned on the spot, and only the lanes left over elect leaders
-    if (ch.act) {
-      const uint32_t base = set_of(c, ch.line_id) * c.assoc;
-      uint64_t m = 0;
-      const int w = probe_set(c, base, ch.line_id, m);
-      if (w >= 0) {
-        st = (m_state(m) == ST_FETCHING) ? A_JOIN : A_HIT;
-        idx = base + (uint32_t)w;
-        gen = m_gen(m);
-        if (!(m & M_REF)) or_rlx(c.meta + idx, M_REF);
-        part = false;
-      }
+    const uint32_t base = ch.act ? set_of(c, ch.line_id) * c.assoc : 0u;
+    uint64_t m = 0;
+    int w = -1;
+    if (probe_staged_ok(c.assoc))
+      w = probe_staged(c, ch.act, base, ch.line_id, m);
+    else if (ch.act)
+      w = probe_set(c, base, ch.line_id, m);
+    if (ch.act && w >= 0) {
+      st = (m_state(m) == ST_FETCHING) ? A_JOIN : A_HIT;
+      idx = base + (uint32_t)w;
+      gen = m_gen(m);
+      if (!(m & M_REF)) or_rlx(c.meta + idx, M_REF);
+      part = false;
     }
   }
   dedup(ch, part);

@@ -83,3 +83,38 @@ def test_bfs_from_isolated_and_leaf_sources():
         ctx.close_store()
         ctx.shutdown()
         buf.free()
+
+
+@pytest.mark.parametrize("scale", [12, 18])
+def test_resident_kernels_equal_oracle_and_cached(scale):
+    """The kernel-only baselines (the same BFS and SpMV kernels over a copy of the store
+    image resident in HBM, no cache) give the oracle's levels and fold bit for bit, and
+    leave the context usable for cached runs afterwards."""
+    import torch
+    buf, g, row_ptr, col, val = _graph(scale, 16)
+    ctx = agile.Context(cache_bytes=1 << 20, line_bytes=4096, assoc=8, num_qp=4, qp_depth=256,
+                        timeout_ns=int(10e9))
+    try:
+        ctx.open_store(buf)
+        dimg = torch.from_numpy(buf.array.view(np.uint8)).cuda()
+        src = gen.bfs_source(0, row_ptr)
+        level = torch.empty(g.num_vertices, dtype=torch.int32, device="cuda")
+        nl = ctx.bfs_resident(dimg, buf.nbytes, g, src, level)
+        ref = oracle.bfs(row_ptr, col, src)
+        assert np.array_equal(level.cpu().numpy(), ref) and nl == int(ref.max()) + 1
+        x = gen.uniform_f32(1, gen.S_X, g.num_vertices, -1.0, 1.0)
+        y = torch.empty(g.num_vertices, dtype=torch.float32, device="cuda")
+        ctx.spmv_resident(dimg, buf.nbytes, g, cuda(x), y)
+        ctx.sync()
+        exp = oracle.spmv(row_ptr, col, val, x, 0, g.num_vertices)
+        assert np.array_equal(y.cpu().numpy().view(np.uint32), exp.view(np.uint32))
+        # the cached kernels still run after the resident ones (work counters cleared)
+        y2 = torch.empty_like(y)
+        ctx.spmv(g, cuda(x), y2)
+        ctx.sync()
+        assert torch.equal(y, y2)
+        check_quiescent_invariants(ctx, 8)
+    finally:
+        ctx.close_store()
+        ctx.shutdown()
+        buf.free()
