@@ -42,7 +42,8 @@ typedef enum agile_status {
   AGILE_ENOMEM = -2,    /* device or pinned host allocation failed */
   AGILE_EHIP = -3,      /* a HIP runtime call failed */
   AGILE_ETIMEDOUT = -4, /* a device wait exceeded timeout_ns (watchdog) */
-  AGILE_EAGAIN = -5,    /* a ticket found no evictable way in its set; retry later */
+  AGILE_EAGAIN = -5,    /* no room yet (a ticket found no evictable way in its set; a session
+                           is full, or a request has not completed); retry later */
   AGILE_EIO = -6,       /* a command completed with an error status */
   AGILE_EPROTO = -7,    /* queue-protocol violation detected on the device */
   AGILE_ESTATE = -8     /* call not allowed in the current state */
@@ -357,14 +358,55 @@ typedef struct agile_serve_report {
   uint64_t user_waves;
 } agile_serve_report;
 
-/* Continuous-batching serving session (embedding-bag lookups).  One persistent kernel
- * serves the whole request stream: its wavefronts claim bags in request order, so the
- * bags of requests that arrive while others are on the GPU are picked up as waves free
- * up and their I/O overlaps on the device.  The host publishes request r once
- * arrival_s[r] (seconds from the start, non-decreasing) has passed and the requests in
- * flight leave room in the queue budget (lookups in flight, every lookup may miss) and
- * the cache budget (lines one chunk of each request in flight can pin); a request that
- * does not fit waits, and so do the ones behind it.  Request r owns bags
+/* Serving session (embedding-bag lookups; Sec. 3.2's asynchronous, GPU-initiated reads
+ * applied to requests that arrive while the kernel runs).  agile_session_open launches
+ * one persistent kernel on a stream of its own; its wavefronts claim bags in submission
+ * order, wait for a bag until the host has published it, and run it through the cache
+ * and queues as agile_embbag_forward does, so the bags of requests submitted while
+ * others are on the GPU are picked up as waves free up and their I/O overlaps on the
+ * device.  While a session is open the context accepts no other call (AGILE_ESTATE)
+ * except the session calls, agile_get_info, agile_last_error and agile_shutdown (which
+ * closes the session first).  One session per context at a time.
+ *
+ * Requests travel through rings in pinned host memory that the session owns: the host
+ * writes a request's bag descriptors and lookups into the next free slots, then
+ * publishes the new count of bags with a release store; the kernel writes each bag's
+ * output into the bag's ring slot and raises the request's done flag (system scope)
+ * after its last bag.  Slots are reused in submission order once requests are polled.
+ *
+ * tb, K, mode: as agile_embbag_forward (dim <= 256, 4096 % (4*dim) == 0).
+ * opts: admission budgets and the wave count (NULL = defaults, see agile_serve_opts).
+ * Returns AGILE_ENOMEM when the rings cannot be allocated. */
+typedef struct agile_session_s* agile_session;
+agile_status agile_session_open(agile_ctx ctx, agile_store store, const agile_tables* tb, uint32_t K,
+                                uint32_t mode, const agile_serve_opts* opts, agile_session* out);
+
+/* Submits one request of nbags bags (1 <= nbags, and at most 65,536 lookups and bags):
+ * bag k owns lookups [bag_off[k], bag_off[k+1]) of idx (host memory, bag_off[0] == 0,
+ * non-decreasing; rows in [0, rows)) and reads table k % num_tables.  The caller's
+ * arrays are copied before the call returns.  *out_req receives the request's number
+ * (0, 1, 2, ... in submission order).  AGILE_EAGAIN: the requests in flight leave no
+ * room in a budget (queue: lookups in flight; cache: the lines one chunk of each
+ * request can pin, min(lookups, 64, budget / 2); requests in flight) or in a ring; poll
+ * and retry.  A request is always admitted when none is in flight. */
+agile_status agile_session_submit(agile_session s, uint32_t nbags, const int64_t* bag_off,
+                                  const int64_t* idx, uint64_t* out_req);
+
+/* Non-blocking: AGILE_OK once request req has completed, with its nbags*dim pooled
+ * outputs copied to out (host memory; NULL discards them); AGILE_EAGAIN while it runs.
+ * Each request is collected once (AGILE_EINVAL after that, or for an unknown number).
+ * AGILE_ETIMEDOUT if the kernel was aborted (the context is then poisoned). */
+agile_status agile_session_poll(agile_session s, uint64_t req, float* out);
+
+/* Waits for every submitted request to complete (outputs not yet polled are dropped),
+ * stops the kernel, frees the rings and releases the context.  The handle is invalid
+ * afterwards.  AGILE_ETIMEDOUT when requests do not complete within the watchdog. */
+agile_status agile_session_close(agile_session s);
+
+/* Replay harness, a client of the session calls above: it submits request r once
+ * arrival_s[r] (seconds from the start, non-decreasing) has passed and the session
+ * admits it (a request that does not fit waits, and so do the ones behind it), polls
+ * the requests in flight, and closes the session at the end.  Request r owns bags
  * [req_bag0[r], req_bag0[r+1]); bag b owns lookups [bag_off[b], bag_off[b+1]) of idx and
  * reads table (b - req_bag0[r]) % num_tables.  Outputs (pooled, K as in
  * agile_embbag_forward) go to out[b*dim ...]; latency_s[r] is the time from arrival to

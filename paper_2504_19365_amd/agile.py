@@ -135,6 +135,11 @@ def lib():
             "agile_embbag_backward_sgd_noalloc": (st, [vp, vp, C.POINTER(Tables), vp, vp, u64, u64,
                                                        vp, C.c_float, vp]),
             "agile_debug_radix_sort_u64": (st, [vp, u64, u32, u32, vp]),
+            "agile_session_open": (st, [vp, vp, C.POINTER(Tables), u32, u32, C.POINTER(ServeOpts),
+                                        C.POINTER(vp)]),
+            "agile_session_submit": (st, [vp, u32, vp, vp, C.POINTER(C.c_uint64)]),
+            "agile_session_poll": (st, [vp, u64, vp]),
+            "agile_session_close": (st, [vp]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -230,6 +235,46 @@ class Store:
         self.ctx, self.handle, self.image, self.nbytes = ctx, handle, image, nbytes
 
 
+class Session:
+    """An open serving session: submit requests, poll for their outputs, close."""
+
+    def __init__(self, ctx: "Context", h: int, dim: int):
+        self.ctx, self.h, self.dim = ctx, h, dim
+
+    def submit(self, bag_off, idx):
+        """Submits one request (bag k = lookups [bag_off[k], bag_off[k+1]) of idx).
+        Returns its number, or None when the session has no room for it yet."""
+        bag_off = np.ascontiguousarray(bag_off, dtype=np.int64)
+        idx = np.ascontiguousarray(idx, dtype=np.int64)
+        r = C.c_uint64()
+        s = lib().agile_session_submit(self.h, bag_off.size - 1, _ptr(bag_off),
+                                       _ptr(idx) if idx.size else 0, C.byref(r))
+        if s == EAGAIN:
+            return None
+        self.ctx._check(s, "agile_session_submit")
+        return int(r.value)
+
+    def poll(self, req: int, nbags: int):
+        """The [nbags, dim] outputs of request req once it has completed, else None."""
+        out = np.empty((nbags, self.dim), dtype=np.float32)
+        s = lib().agile_session_poll(self.h, req, _ptr(out))
+        if s == EAGAIN:
+            return None
+        self.ctx._check(s, "agile_session_poll")
+        return out
+
+    def close(self):
+        if self.h:
+            h, self.h = self.h, None
+            self.ctx._check(lib().agile_session_close(h), "agile_session_close")
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
 class Context:
     def __init__(self, cfg: Config | None = None, **kw):
         cfg = cfg if cfg is not None else default_config(**kw)
@@ -269,7 +314,8 @@ class Context:
     def close_store(self, store: Store | None = None) -> int:
         store = store or self.store
         s = lib().agile_close_store(self.h, store.handle)
-        self.store = None
+        if s != ESTATE:  # (ESTATE: a serving session is open; the store stays open)
+            self.store = None
         return s
 
     def shutdown(self):
@@ -398,6 +444,19 @@ class Context:
                                       C.byref(opts), C.byref(rep)), "agile_serve")
         return out, lat, rep.as_dict()
 
+    def open_session(self, tb: Tables, K: int, mode: int = MODE_ASYNC,
+                     max_inflight_lookups: int = 0, max_inflight_requests: int = 0,
+                     user_waves: int = 0, max_inflight_lines: int = 0, store=None) -> "Session":
+        """Starts a serving session (agile_session_open): a persistent kernel that takes
+        requests as they are submitted."""
+        store = store or self.store
+        opts = ServeOpts(max_inflight_lookups, max_inflight_requests, user_waves,
+                         max_inflight_lines)
+        h = C.c_void_p()
+        self._check(lib().agile_session_open(self.h, store.handle, C.byref(tb), K, mode,
+                                             C.byref(opts), C.byref(h)), "agile_session_open")
+        return Session(self, h.value, tb.dim)
+
     # ---- diagnostics
     def debug_trace(self, lines, writes, hit, way, stream=None, store=None):
         store = store or self.store
@@ -414,7 +473,7 @@ class Context:
                      "tok_n", "t_u_desc", "t_u_life", "svc_exit", "img_epoch", "work_p1",
                      "work_p2", "work_p3", "work_p4", "work_p5", "work_p6", "work_p7", "defer",
                      "hwork", "hwork_p1", "hwork_p2", "hwork_p3", "hwork_p4", "hwork_p5",
-                     "hwork_p6", "hwork_p7", "exh", "hexh")
+                     "hwork_p6", "hwork_p7")
 
     def debug_counters(self) -> dict:
         n = len(self.COUNTER_NAMES)

@@ -10,6 +10,7 @@
 #include <chrono>
 #include <cstdio>
 #include <cstring>
+#include <deque>
 #include <mutex>
 #include <string>
 #include <thread>
@@ -37,14 +38,22 @@ struct embbag_args {
   uint64_t table_bytes;
   uint32_t T, dim, row_bytes, K;
   uint32_t mode, gather, active_waves, serve;
-  // continuous batching (serve != 0): bags of many requests, published over time
-  const uint32_t* bag_req;    // request of each bag
-  const uint32_t* bag_tab;    // table of each bag
-  const uint32_t* req_nbags;  // bags per request
-  uint32_t* req_cnt;          // bags finished per request (device, zeroed)
-  const uint32_t* pub_dev;    // device mirror of the number of published requests
-  const uint32_t* pub_host;   // pinned: [0] published requests, [1] stop
-  uint32_t* done;             // pinned: done[r] = 1 once request r's outputs are visible
+  // continuous batching (serve != 0): an unbounded stream of bags from requests that the
+  // host publishes over time, held in rings: bag b in slot b & bag_mask, lookup j (a
+  // position in the stream of lookups) in slot j & look_mask, request r in slot
+  // r & req_mask.  idx and out are rings too.  The ring arrays live in pinned host
+  // memory, written by the host before it publishes.
+  const uint64_t* bag_j0;     // lookups [bag_j0, bag_j1) of the bag
+  const uint64_t* bag_j1;
+  const uint64_t* bag_req;    // request of the bag
+  const uint32_t* bag_tab;    // table of the bag
+  const uint32_t* req_nbags;  // bags of the request
+  uint32_t* req_cnt;          // bags finished per request slot (device; the request's last
+                              // bag returns its slot to zero)
+  uint32_t* done;             // done[r & req_mask] = 1 once the request's outputs are visible
+  const uint64_t* pub_dev;    // device mirror: [0] bags published, [1] stop
+  const uint64_t* pub_host;   // pinned: [0] bags published, [1] stop
+  uint64_t bag_mask, look_mask, req_mask;
   // the resident-hit launch before this one defers bags to this list, and this launch
   // runs only them; their number is the device counter C_DEFER, read by every wave when
   // it starts.  NULL: this launch runs every bag.
@@ -70,7 +79,6 @@ struct src_state {
   uint32_t dealt;  // static bags looked at so far (0..STATIC_ROUNDS)
   uint32_t tried;  // partitions found used up so far
   int64_t nb;      // bags of the launch: a.nbags, or the deferred count for a list
-  uint32_t skip;   // partitions known to be used up (read once the wave's own one is)
 };
 constexpr uint32_t STATIC_ROUNDS = 2;
 
@@ -87,35 +95,48 @@ struct desc_t {
   bool valid, last;
 };
 
+// A ring entry in pinned host memory, read at system scope: the host rewrites a slot
+// for every lap of the ring, so no cached copy of an older lap may be used.
+template <typename T>
+__device__ __forceinline__ T ring_ld(const T* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
 template <int VPL>
 __device__ __forceinline__ void write_bag(const dev_ctx& c, const embbag_args& a, int64_t g,
                                           const float (&acc)[VPL]) {
   const uint32_t d0 = lane() * VPL;
-  float* o = a.out + (uint64_t)g * a.dim + d0;
+  const uint64_t slot = a.serve ? ((uint64_t)g & a.bag_mask) : (uint64_t)g;
+  float* o = a.out + slot * a.dim + d0;
 #pragma unroll
   for (int v = 0; v < VPL; ++v)
     if (d0 + v < a.dim) o[v] = acc[v];
   if (a.serve) {
     // the request is done when its last bag is written: push the outputs to host memory
-    // first, then count the bag, then raise the request's flag (system scope)
+    // first, then count the bag, then return the count to zero for the slot's next
+    // request and raise the request's flag (system scope)
+    // (the request's size is read before the bag is counted: once the count is complete
+    // the host may hand the slot to a later request)
     fence_rel_sys();
     if (lane() == 0) {
-      const uint32_t r = a.bag_req[g];
-      const uint32_t k = add_rlx(a.req_cnt + r, 1u) + 1;
-      if (k == a.req_nbags[r]) {
+      const uint64_t rs = ring_ld(a.bag_req + slot) & a.req_mask;
+      const uint32_t nb = ring_ld(a.req_nbags + rs);
+      const uint32_t k = add_rlx(a.req_cnt + rs, 1u) + 1;
+      if (k == nb) {
+        st_rlx(a.req_cnt + rs, 0u);
         fence_rel_sys();
-        __hip_atomic_store(a.done + r, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+        __hip_atomic_store(a.done + rs, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
       }
     }
   }
 }
 
-// Serving: waits until request r is published (the device mirror holds the count).
-// Returns false when the session is stopped or aborted.  No device deadline: requests
-// may arrive seconds apart; the host watchdog bounds the session.
-__device__ __forceinline__ bool wait_published(const dev_ctx& c, const embbag_args& a, uint32_t r) {
+// Serving: waits until bag b is published (the device mirror holds the count).  Returns
+// false when the session is stopped or aborted.  No device deadline: requests may arrive
+// seconds apart; the host watchdog bounds the session.
+__device__ __forceinline__ bool wait_published(const dev_ctx& c, const embbag_args& a, uint64_t b) {
   uint32_t n = 0;
-  while (uni(ld_rlx(a.pub_dev)) <= r) {
+  while (uni64(ld_rlx(a.pub_dev)) <= b) {
     if ((++n & 63) == 0) {
       if (aborted(c)) return false;
       if (uni(ld_rlx(a.pub_dev + 1))) return false;  // stop, mirrored from the host
@@ -149,24 +170,14 @@ __device__ __forceinline__ void hold_next(const dev_ctx& c, const launch_t& li, 
   if (nb <= dealt) ss.tried = parts;  // every bag was dealt: no counter to visit
   while (g < 0 && ss.tried < parts) {
     const uint32_t p = (ss.uw + ss.tried) % parts;
-    // once its own partition is used up, a wave reads which partitions others have found
-    // used up and skips them, so the last searches of a launch cost one read each
-    // instead of an atomic per partition
-    if (ss.tried == 1) ss.skip = uni((uint32_t)ld_rlx(counter(c, C_EXH)));
-    if (ss.tried > 0 && ((ss.skip >> p) & 1u)) {
-      ++ss.tried;
-      continue;
-    }
     uint64_t v = 0;
     if (lane() == 0) v = add_rlx(counter(c, work_counter(p)), 1ull);
     v = rdlane64(v, 0);
     const int64_t b = dealt + (int64_t)v * parts + p;
-    if (b < nb) {
+    if (b < nb)
       g = b;
-    } else {
-      if (lane() == 0) or_rlx(counter(c, C_EXH), 1ull << p);
+    else
       ++ss.tried;
-    }
   }
   if (g < 0) {
     ss.exhausted = true;
@@ -179,7 +190,7 @@ __device__ __forceinline__ void hold_next(const dev_ctx& c, const launch_t& li, 
   if (a.gather) {
     ss.j0 = bag * 64;
     ss.j1 = ((int64_t)a.n < ss.j0 + 64) ? (int64_t)a.n : ss.j0 + 64;
-  } else {
+  } else if (!a.serve) {
     ss.j0 = a.off[bag];
     ss.j1 = a.off[bag + 1];
   }
@@ -205,11 +216,13 @@ __device__ __forceinline__ desc_t next_desc(const dev_ctx& c, const launch_t& li
         if (ss.g < 0) return r;
       }
       const int64_t g = ss.g, bag = ss.bag;
+      int64_t j0 = ss.j0, j1 = ss.j1;
       if (a.serve) {
-        const uint32_t rq = a.bag_req[bag];
-        if (uni(ld_rlx(a.pub_dev)) <= rq) {
+        // a claimed bag is read only once it is published (its ring slot may still hold
+        // an older bag's entry until then)
+        if (uni64(ld_rlx(a.pub_dev)) <= (uint64_t)bag) {
           if (!may_wait) return r;  // keep holding it
-          if (!wait_published(c, a, rq)) {
+          if (!wait_published(c, a, (uint64_t)bag)) {
             ss.exhausted = true;
             ss.g = -1;
             return r;
@@ -217,8 +230,10 @@ __device__ __forceinline__ desc_t next_desc(const dev_ctx& c, const launch_t& li
         } else {
           fence_acq();
         }
+        const uint64_t slot = (uint64_t)bag & a.bag_mask;
+        j0 = (int64_t)ring_ld(a.bag_j0 + slot);
+        j1 = (int64_t)ring_ld(a.bag_j1 + slot);
       }
-      const int64_t j0 = ss.j0, j1 = ss.j1;
       // hold the next bag now, except near the end of the work: a held bag cannot go to
       // a wave that runs out, so the last bags are taken only when needed
       ss.g = -1;
@@ -249,12 +264,13 @@ __device__ __forceinline__ void make_chunk(const dev_ctx& c, const embbag_args& 
   ch.act = d.valid && lane() < d.n;
   ch.st = A_NONE;
   if (ch.act) {
-    const int64_t row = a.idx[d.j + lane()];
+    const uint64_t jl = (uint64_t)(d.j + lane());
+    const int64_t row = a.serve ? ring_ld(a.idx + (jl & a.look_mask)) : a.idx[jl];
     uint64_t byte;
     if (a.gather) {
       byte = a.base_off + (uint64_t)row * a.row_bytes;
     } else {
-      const uint32_t t = a.serve ? a.bag_tab[d.g] : (uint32_t)(d.g % a.T);
+      const uint32_t t = a.serve ? ring_ld(a.bag_tab + ((uint64_t)d.g & a.bag_mask)) : (uint32_t)(d.g % a.T);
       byte = a.base_off + (uint64_t)t * a.table_bytes + (uint64_t)row * a.row_bytes;
     }
     ch.line_id = (uint32_t)(byte >> c.line_shift);
@@ -479,7 +495,7 @@ __device__ __forceinline__ void embbag_wave(const dev_ctx& c, const launch_t& li
   none.valid = false;
   // a list launch runs the bags the resident-hit pass before it deferred
   const int64_t nb = a.list ? (int64_t)uni64(ld_rlx(counter(c, C_DEFER))) : (int64_t)a.nbags;
-  src_state ss{-1, -1, 0, 0, false, uw, 0, 0, nb, 0u};
+  src_state ss{-1, -1, 0, 0, false, uw, 0, 0, nb};
   chunk_t cc, cn;
   if (!async) {
     desc_t dc = next_desc<VPL>(c, li, a, none, ss, true);
@@ -658,7 +674,7 @@ __device__ __forceinline__ bool hit_wave(const dev_ctx& c, const embbag_args& a,
   // from P = min(8, A) partition counters (bag 2A + v*P + p in partition p), a wave
   // starting at partition u mod P and moving on once it is used up
   const uint32_t parts = A < WORK_PARTS ? A : WORK_PARTS;
-  uint32_t tried = 0, skip = 0;
+  uint32_t tried = 0;
   for (uint32_t round = 0;; ++round) {
     uint64_t g;
     if (round < 2) {
@@ -667,17 +683,10 @@ __device__ __forceinline__ bool hit_wave(const dev_ctx& c, const embbag_args& a,
     } else {
       if (nb <= 2ull * A || tried >= parts) break;
       const uint32_t p = (uw + tried) % parts;
-      // past its own partition a wave skips the ones others found used up
-      if (tried == 1) skip = uni((uint32_t)ld_rlx(counter(c, C_HEXH)));
-      if (tried > 0 && ((skip >> p) & 1u)) {
-        ++tried;
-        continue;
-      }
       uint64_t v = 0;
       if (lane() == 0) v = add_rlx(counter(c, C_HWORK + p), 1ull);
       g = 2ull * A + rdlane64(v, 0) * parts + p;
       if (g >= nb) {
-        if (lane() == 0) or_rlx(counter(c, C_HEXH), 1ull << p);
         ++tried;
         continue;
       }
@@ -796,17 +805,19 @@ __global__ __launch_bounds__(WG) void k_embbag(dev_ctx c, launch_t li, embbag_ar
 // service wavefront mirrors the host's count of published requests, its stop flag and
 // its abort flag into device memory, so that waiting waves poll HBM instead of sending
 // PCIe reads.
-__device__ __forceinline__ void mirror_published(const dev_ctx& c, const embbag_args& a, uint32_t nreq, uint32_t* pub_dev) {
-  uint32_t last = 0;
+// The host's release of the count orders its ring writes before it; the mirror takes it
+// with acquire and passes it on with release, and the waves read it with acquire.
+__device__ __forceinline__ void mirror_published(const dev_ctx& c, const embbag_args& a, uint64_t* pub_dev) {
+  uint64_t last = 0;
   for (;;) {
-    const uint32_t v = uni(__hip_atomic_load(a.pub_host, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM));
+    const uint64_t v = uni64(__hip_atomic_load(a.pub_host, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM));
     if (v != last) {
       last = v;
-      if (lane() == 0) st_rlx(pub_dev, v);
+      if (lane() == 0) __hip_atomic_store(pub_dev, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     }
-    if (last >= nreq || aborted(c) || host_abort_poll(c)) break;
-    if (uni(__hip_atomic_load(a.pub_host + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM))) {
-      if (lane() == 0) st_rlx(pub_dev + 1, 1u);
+    if (aborted(c) || host_abort_poll(c)) break;
+    if (uni64(__hip_atomic_load(a.pub_host + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM))) {
+      if (lane() == 0) st_rlx(pub_dev + 1, 1ull);
       break;
     }
     __builtin_amdgcn_s_sleep(16);
@@ -814,11 +825,10 @@ __device__ __forceinline__ void mirror_published(const dev_ctx& c, const embbag_
 }
 
 template <int VPL>
-__global__ __launch_bounds__(WG) void k_serve(dev_ctx c, launch_t li, embbag_args a, uint32_t nreq,
-                                              uint32_t* pub_dev) {
+__global__ __launch_bounds__(WG) void k_serve(dev_ctx c, launch_t li, embbag_args a, uint64_t* pub_dev) {
   if (blockIdx.x < li.service_blocks) {
     if (service_role(li) == li.n_ctrl + li.n_cq) {
-      mirror_published(c, a, nreq, pub_dev);
+      mirror_published(c, a, pub_dev);
       return;
     }
     run_service(c, li);
@@ -1653,8 +1663,36 @@ struct agile_store_s {
   uint64_t blocks;
 };
 
+struct session_req {
+  uint64_t id, bag0, nb, look0, nl, lines;
+  bool polled;
+};
+// Largest request a session accepts (lookups, and bags).
+constexpr uint64_t SESSION_MAX_LOOKUPS = 1ull << 16;
+
+struct agile_session_s {
+  agile_ctx ctx = nullptr;
+  agile_tables tb{};
+  uint64_t bag_cap = 0, look_cap = 0, req_cap = 0;  // ring sizes (powers of two)
+  uint64_t cap_look = 0, cap_lines = 0, cap_req = 0;  // admission budgets
+  void* host = nullptr;  // pinned, mapped, coherent: control words and rings
+  void* dev = nullptr;   // per-request-slot bag counters, device mirror of the control words
+  hipStream_t hs = nullptr;
+  uint64_t* ctl = nullptr;  // [0] bags published, [1] stop
+  uint64_t *bag_j0 = nullptr, *bag_j1 = nullptr, *bag_req = nullptr;
+  uint32_t* bag_tab = nullptr;
+  int64_t* idx = nullptr;
+  uint32_t *req_nbags = nullptr, *done = nullptr;
+  float* out = nullptr;
+  uint64_t next_req = 0, next_bag = 0, next_look = 0;
+  uint64_t in_look = 0, in_lines = 0;
+  uint64_t user_waves = 0;
+  std::deque<session_req> live;  // submitted and not yet collected, in submission order
+};
+
 struct agile_ctx_s {
   agile_config cfg;
+  agile_session_s* session = nullptr;  // an open serving session owns the device
   dev_ctx d;
   uint32_t n_ctrl, n_cq, service_blocks;
   uint32_t cu_count;
@@ -1760,6 +1798,7 @@ uint32_t user_wave_cap(agile_ctx ctx, int kind) { return user_wave_cap(ctx, kind
 agile_status check_usable(agile_ctx ctx) {
   if (!ctx) return AGILE_EINVAL;
   if (ctx->poisoned) return fail(ctx, AGILE_ESTATE, "context has a sticky device error");
+  if (ctx->session) return fail(ctx, AGILE_ESTATE, "a serving session is open on this context");
   return AGILE_OK;
 }
 
@@ -2020,6 +2059,7 @@ agile_status agile_init(const agile_config* cfg_in, agile_ctx* out) {
 
 agile_status agile_shutdown(agile_ctx ctx) {
   if (!ctx) return AGILE_EINVAL;
+  if (ctx->session) (void)agile_session_close(ctx->session);
   (void)hipDeviceSynchronize();
   for (void* p : ctx->dev_allocs) (void)hipFree(p);
   if (ctx->abort_host) (void)hipHostFree(ctx->abort_host);
@@ -2097,6 +2137,7 @@ agile_status agile_invalidate(agile_ctx ctx, agile_store store, void* stream) {
 
 agile_status agile_close_store(agile_ctx ctx, agile_store store) {
   if (!ctx || !store || store != ctx->store) return fail(ctx, AGILE_EINVAL, "close_store: unknown store");
+  if (ctx->session) return fail(ctx, AGILE_ESTATE, "close_store: a serving session is open");
   agile_status s = AGILE_OK;
   if (!ctx->poisoned) {
     s = sync_stream(ctx, nullptr);
@@ -2179,6 +2220,7 @@ agile_status agile_flush(agile_ctx ctx, agile_store store, void* stream) {
 
 agile_status agile_get_stats(agile_ctx ctx, agile_stats* out, int reset) {
   if (!ctx || !out) return AGILE_EINVAL;
+  if (ctx->session) return fail(ctx, AGILE_ESTATE, "get_stats: a serving session is open");
   std::vector<uint64_t> c((size_t)C_COUNT * CSTRIDE);
   HIPCHK(ctx, hipDeviceSynchronize());
   HIPCHK(ctx, hipMemcpy(c.data(), ctx->d.cnt, c.size() * 8, hipMemcpyDeviceToHost));
@@ -2202,7 +2244,7 @@ agile_status agile_get_stats(agile_ctx ctx, agile_stats* out, int reset) {
     const uint32_t keep[] = {C_SUBMITTED, C_COMPLETED, C_USER_DONE, C_WORK, C_SVC_EXIT, C_IMG_EPOCH,
                              C_WORK_P1, C_WORK_P2, C_WORK_P3, C_WORK_P4, C_WORK_P5, C_WORK_P6, C_WORK_P7,
                              C_DEFER, C_HWORK, C_HWORK_P1, C_HWORK_P2, C_HWORK_P3, C_HWORK_P4, C_HWORK_P5,
-                             C_HWORK_P6, C_HWORK_P7, C_EXH, C_HEXH};
+                             C_HWORK_P6, C_HWORK_P7};
     for (uint32_t i = 0; i < C_COUNT; ++i) {
       if (std::find(std::begin(keep), std::end(keep), i) != std::end(keep)) continue;
       HIPCHK(ctx, hipMemset(ctx->d.cnt + (size_t)i * CSTRIDE, 0, 8));
@@ -2448,8 +2490,10 @@ static agile_status bfs_run(agile_ctx ctx, const agile_csr* g, uint64_t src, int
   // more waves walking the edges while the controllers copy make every memory access of
   // the level slower than the extra latency hiding gains: measured on RMAT scale 24 and
   // 26 with 4 and 16 KiB lines, 1536 waves beat both 1024 and the full grid)
+  // (a resident image pins no lines: only the cap applies)
   constexpr uint64_t BFS_MAX_WAVES = 1536;
-  const uint64_t by_cache = std::max<uint64_t>(1, std::min<uint64_t>(ctx->d.num_lines / 128, BFS_MAX_WAVES));
+  const uint64_t by_cache =
+      img ? BFS_MAX_WAVES : std::max<uint64_t>(1, std::min<uint64_t>(ctx->d.num_lines / 128, BFS_MAX_WAVES));
   while (nF > 0) {
     a.F = F;
     a.N = N;
@@ -2518,8 +2562,9 @@ static agile_status spmv_run(agile_ctx ctx, const agile_csr* g, const float* d_x
   a.img = img;
   a.x = d_x;
   a.y = d_y;
-  const uint64_t by_cache = std::max<uint64_t>(1, ctx->d.num_lines / 32);
-  // a wave pins at most two windows (the current one and the prefetch) of 2 x 8 lines
+  // a wave pins at most two windows (the current one and the prefetch) of 2 x 8 lines; a
+  // resident image pins none
+  const uint64_t by_cache = img ? UINT64_MAX : std::max<uint64_t>(1, ctx->d.num_lines / 32);
   const uint32_t active = (uint32_t)std::min<uint64_t>(
       {(g->num_vertices + 64 * SPMV_RUN - 1) / (64 * SPMV_RUN), (uint64_t)user_wave_cap(ctx, KIND_READ), by_cache});
   a.active = std::max<uint32_t>(1, active);
@@ -2651,83 +2696,86 @@ agile_status agile_probe_copy(const void* src, const uint64_t* d_list, uint64_t 
   return hipGetLastError() == hipSuccess ? AGILE_OK : AGILE_EHIP;
 }
 
-agile_status agile_serve(agile_ctx ctx, agile_store store, const agile_tables* tb, uint32_t K, uint32_t mode,
-                         uint64_t nreq, const double* arrival_s, const int64_t* req_bag0, const int64_t* bag_off,
-                         const int64_t* idx, float* out, double* latency_s, const agile_serve_opts* opts,
-                         agile_serve_report* report) {
+// ---- serving sessions: one persistent kernel fed through rings in pinned host memory
+static uint64_t pow2_at_least(uint64_t v) {
+  uint64_t p = 1;
+  while (p < v) p <<= 1;
+  return p;
+}
+
+agile_status agile_session_open(agile_ctx ctx, agile_store store, const agile_tables* tb, uint32_t K, uint32_t mode,
+                                const agile_serve_opts* opts, agile_session* out) {
   agile_status s = check_usable(ctx);
   if (s) return s;
-  if (store != ctx->store) return fail(ctx, AGILE_EINVAL, "serve: store is not open on this context");
-  if (!tb || !arrival_s || !req_bag0 || !bag_off || !out || !latency_s)
-    return fail(ctx, AGILE_EINVAL, "serve: null pointer");
-  if (nreq == 0) return AGILE_OK;
-  if (tb->dim == 0 || tb->dim > 256 || 4096 % (tb->dim * 4) || tb->num_tables == 0 || tb->rows == 0)
-    return fail(ctx, AGILE_EINVAL, "serve: bad tables");
+  if (!out) return fail(ctx, AGILE_EINVAL, "session: null handle");
+  *out = nullptr;
+  if (ctx->session) return fail(ctx, AGILE_ESTATE, "session: one session per context at a time");
+  if (store != ctx->store) return fail(ctx, AGILE_EINVAL, "session: store is not open on this context");
+  if (!tb || tb->dim == 0 || tb->dim > 256 || 4096 % (tb->dim * 4) || tb->num_tables == 0 || tb->rows == 0)
+    return fail(ctx, AGILE_EINVAL, "session: bad tables");
+  if (mode > AGILE_MODE_ASYNC) return fail(ctx, AGILE_EINVAL, "session: bad mode");
   const uint64_t row_bytes = (uint64_t)tb->dim * 4, table_bytes = tb->rows * row_bytes;
   if (tb->base_offset % row_bytes || tb->base_offset + table_bytes * tb->num_tables > store->bytes)
-    return fail(ctx, AGILE_EINVAL, "serve: tables exceed the store");
-  const uint64_t nbags = (uint64_t)req_bag0[nreq];
-  const uint64_t nlook = (uint64_t)bag_off[nbags];
-  if (nbags == 0 || nbags >= (1ull << 32) || nreq >= (1ull << 32)) return fail(ctx, AGILE_EINVAL, "serve: sizes");
-  for (uint64_t r = 0; r < nreq; ++r)
-    if (req_bag0[r + 1] <= req_bag0[r] || (r && arrival_s[r] < arrival_s[r - 1]))
-      return fail(ctx, AGILE_EINVAL, "serve: every request needs >= 1 bag; arrivals must not decrease");
-  // ---- per-bag and per-request tables in HBM (copied before the session starts)
-  std::vector<uint32_t> bag_req(nbags), bag_tab(nbags), req_nb(nreq);
-  uint64_t max_req_look = 0;
-  for (uint64_t r = 0; r < nreq; ++r) {
-    req_nb[r] = (uint32_t)(req_bag0[r + 1] - req_bag0[r]);
-    for (int64_t b = req_bag0[r]; b < req_bag0[r + 1]; ++b) {
-      bag_req[b] = (uint32_t)r;
-      bag_tab[b] = (uint32_t)((b - req_bag0[r]) % tb->num_tables);
-    }
-    max_req_look = std::max<uint64_t>(max_req_look, (uint64_t)(bag_off[req_bag0[r + 1]] - bag_off[req_bag0[r]]));
-  }
+    return fail(ctx, AGILE_EINVAL, "session: tables exceed the store");
+  agile_session_s* se = new agile_session_s();
+  se->ctx = ctx;
+  se->tb = *tb;
+  const uint64_t sq_slots = (uint64_t)ctx->d.num_qp * ctx->d.depth;
+  se->cap_look = opts && opts->max_inflight_lookups ? opts->max_inflight_lookups : sq_slots;
+  se->cap_lines = opts && opts->max_inflight_lines ? opts->max_inflight_lines : std::max<uint64_t>(1, ctx->d.num_lines);
+  se->cap_req = opts && opts->max_inflight_requests ? opts->max_inflight_requests : 4096;
+  // rings: room for what the budgets admit, plus one request of the largest size
+  // (ring sizes are bounded; budgets beyond them are limited by ring room instead)
+  const uint64_t ring_look = std::min<uint64_t>(std::max<uint64_t>(se->cap_look, 1), 1ull << 22);
+  se->look_cap = pow2_at_least(ring_look + SESSION_MAX_LOOKUPS);
+  se->bag_cap = pow2_at_least(ring_look + SESSION_MAX_LOOKUPS);
+  se->req_cap = pow2_at_least(std::min<uint64_t>(se->cap_req, 1ull << 20) + 1);
   auto al = [](size_t v) { return (v + 255) & ~(size_t)255; };
-  const size_t o_idx = 0, o_off = o_idx + al(8 * std::max<uint64_t>(nlook, 1)), o_breq = o_off + al(8 * (nbags + 1)),
-               o_btab = o_breq + al(4 * nbags), o_rnb = o_btab + al(4 * nbags), o_rcnt = o_rnb + al(4 * nreq),
-               o_pub = o_rcnt + al(4 * nreq), need = o_pub + 256;
-  hipStream_t hs = nullptr;
-  HIPCHK(ctx, hipStreamCreateWithFlags(&hs, hipStreamNonBlocking));
-  struct stream_guard {
-    hipStream_t h;
-    ~stream_guard() { (void)hipStreamDestroy(h); }
-  } sg{hs};
-  if ((s = ensure_scratch(ctx, need, hs)) != AGILE_OK) return s;
-  uint8_t* sb = (uint8_t*)ctx->scratch;
-  if (nlook) HIPCHK(ctx, hipMemcpy(sb + o_idx, idx, 8 * nlook, hipMemcpyHostToDevice));
-  HIPCHK(ctx, hipMemcpy(sb + o_off, bag_off, 8 * (nbags + 1), hipMemcpyHostToDevice));
-  HIPCHK(ctx, hipMemcpy(sb + o_breq, bag_req.data(), 4 * nbags, hipMemcpyHostToDevice));
-  HIPCHK(ctx, hipMemcpy(sb + o_btab, bag_tab.data(), 4 * nbags, hipMemcpyHostToDevice));
-  HIPCHK(ctx, hipMemcpy(sb + o_rnb, req_nb.data(), 4 * nreq, hipMemcpyHostToDevice));
-  HIPCHK(ctx, hipMemset(sb + o_rcnt, 0, 4 * nreq));
-  HIPCHK(ctx, hipMemset(sb + o_pub, 0, 256));
-  // ---- pinned, coherent host memory: publication count + stop, done flags, outputs
-  void* hp = nullptr;
-  const size_t hbytes = al(8) + al(4 * nreq) + al(4 * nbags * tb->dim);
-  if (hipHostMalloc(&hp, hbytes, hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess) {
+  const size_t o_ctl = 0, o_j0 = o_ctl + 256, o_j1 = o_j0 + al(8 * se->bag_cap), o_breq = o_j1 + al(8 * se->bag_cap),
+               o_btab = o_breq + al(8 * se->bag_cap), o_idx = o_btab + al(4 * se->bag_cap),
+               o_rnb = o_idx + al(8 * se->look_cap), o_done = o_rnb + al(4 * se->req_cap),
+               o_out = o_done + al(4 * se->req_cap), hbytes = o_out + al(4 * se->bag_cap * tb->dim);
+  auto cleanup = [&](agile_status st, const std::string& msg) {
+    if (se->host) (void)hipHostFree(se->host);
+    if (se->dev) (void)hipFree(se->dev);
+    if (se->hs) (void)hipStreamDestroy(se->hs);
+    delete se;
+    return fail(ctx, st, msg);
+  };
+  if (hipHostMalloc(&se->host, hbytes, hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess) {
     (void)hipGetLastError();
-    return fail(ctx, AGILE_ENOMEM, "serve: pinned allocation failed");
+    se->host = nullptr;
+    return cleanup(AGILE_ENOMEM, "session: pinned ring allocation failed");
   }
-  struct host_guard {
-    void* p;
-    ~host_guard() { (void)hipHostFree(p); }
-  } hg{hp};
-  memset(hp, 0, hbytes);
-  volatile uint32_t* pub = (volatile uint32_t*)hp;
-  volatile uint32_t* done = (volatile uint32_t*)((uint8_t*)hp + al(8));
-  float* hout = (float*)((uint8_t*)hp + al(8) + al(4 * nreq));
-  void *d_pub = nullptr, *d_done = nullptr, *d_out = nullptr;
-  HIPCHK(ctx, hipHostGetDevicePointer(&d_pub, (void*)pub, 0));
-  HIPCHK(ctx, hipHostGetDevicePointer(&d_done, (void*)done, 0));
-  HIPCHK(ctx, hipHostGetDevicePointer(&d_out, (void*)hout, 0));
-  // ---- kernel
+  memset(se->host, 0, hbytes);
+  uint8_t* hb = (uint8_t*)se->host;
+  se->ctl = (uint64_t*)(hb + o_ctl);
+  se->bag_j0 = (uint64_t*)(hb + o_j0);
+  se->bag_j1 = (uint64_t*)(hb + o_j1);
+  se->bag_req = (uint64_t*)(hb + o_breq);
+  se->bag_tab = (uint32_t*)(hb + o_btab);
+  se->idx = (int64_t*)(hb + o_idx);
+  se->req_nbags = (uint32_t*)(hb + o_rnb);
+  se->done = (uint32_t*)(hb + o_done);
+  se->out = (float*)(hb + o_out);
+  void* dhb = nullptr;
+  if (hipHostGetDevicePointer(&dhb, se->host, 0) != hipSuccess) return cleanup(AGILE_EHIP, "session: mapping");
+  uint8_t* dh = (uint8_t*)dhb;
+  const size_t dbytes = al(4 * se->req_cap) + 256;
+  if (hipMalloc(&se->dev, dbytes) != hipSuccess) {
+    (void)hipGetLastError();
+    se->dev = nullptr;
+    return cleanup(AGILE_ENOMEM, "session: device allocation failed");
+  }
+  if (hipMemset(se->dev, 0, dbytes) != hipSuccess) return cleanup(AGILE_EHIP, "session: memset");
+  if (hipStreamCreateWithFlags(&se->hs, hipStreamNonBlocking) != hipSuccess) {
+    se->hs = nullptr;
+    return cleanup(AGILE_EHIP, "session: stream");
+  }
   embbag_args a{};
-  a.idx = (const int64_t*)(sb + o_idx);
-  a.off = (const int64_t*)(sb + o_off);
-  a.out = (float*)d_out;
-  a.nbags = nbags;
-  a.n = nlook;
+  a.idx = (const int64_t*)(dh + o_idx);
+  a.out = (float*)(dh + o_out);
+  a.nbags = (uint64_t)INT64_MAX;  // an unbounded stream: the session ends on the stop flag
   a.rows = tb->rows;
   a.base_off = tb->base_offset;
   a.table_bytes = table_bytes;
@@ -2736,15 +2784,20 @@ agile_status agile_serve(agile_ctx ctx, agile_store store, const agile_tables* t
   a.row_bytes = (uint32_t)row_bytes;
   a.K = K;
   a.mode = mode;
-  a.gather = 0;
   a.serve = 1;
-  a.bag_req = (const uint32_t*)(sb + o_breq);
-  a.bag_tab = (const uint32_t*)(sb + o_btab);
-  a.req_nbags = (const uint32_t*)(sb + o_rnb);
-  a.req_cnt = (uint32_t*)(sb + o_rcnt);
-  a.pub_dev = (const uint32_t*)(sb + o_pub);
-  a.pub_host = (const uint32_t*)d_pub;
-  a.done = (uint32_t*)d_done;
+  a.bag_j0 = (const uint64_t*)(dh + o_j0);
+  a.bag_j1 = (const uint64_t*)(dh + o_j1);
+  a.bag_req = (const uint64_t*)(dh + o_breq);
+  a.bag_tab = (const uint32_t*)(dh + o_btab);
+  a.req_nbags = (const uint32_t*)(dh + o_rnb);
+  a.done = (uint32_t*)(dh + o_done);
+  a.req_cnt = (uint32_t*)se->dev;
+  uint64_t* pub_dev = (uint64_t*)((uint8_t*)se->dev + al(4 * se->req_cap));
+  a.pub_dev = pub_dev;
+  a.pub_host = (const uint64_t*)(dh + o_ctl);
+  a.bag_mask = se->bag_cap - 1;
+  a.look_mask = se->look_cap - 1;
+  a.req_mask = se->req_cap - 1;
   const int kind = tb->dim <= 64 ? KIND_SERVE1 : (tb->dim <= 128 ? KIND_SERVE2 : KIND_SERVE4);
   // default: a sixteenth of the lines in waves; an explicit count overrides that (the
   // EAGAIN drain keeps an over-subscribed cache deadlock-free, only slower)
@@ -2755,33 +2808,151 @@ agile_status agile_serve(agile_ctx ctx, agile_store store, const agile_tables* t
       (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(want, (uint64_t)user_wave_cap(ctx, kind, svc_blocks)));
   const uint32_t uw = (active + WPB - 1) / WPB * WPB;
   a.active_waves = active;
+  se->user_waves = active;
   launch_t li = make_launch(ctx, uw, true);
   li.service_blocks = svc_blocks;
   const dim3 grid(li.service_blocks + uw / WPB);
   if (kind == KIND_SERVE1)
-    hipLaunchKernelGGL(k_serve<1>, grid, dim3(WG), lds_of(ctx, (const void*)k_serve<1>), hs, ctx->d, li, a, (uint32_t)nreq, (uint32_t*)(sb + o_pub));
+    hipLaunchKernelGGL(k_serve<1>, grid, dim3(WG), lds_of(ctx, (const void*)k_serve<1>), se->hs, ctx->d, li, a, pub_dev);
   else if (kind == KIND_SERVE2)
-    hipLaunchKernelGGL(k_serve<2>, grid, dim3(WG), lds_of(ctx, (const void*)k_serve<2>), hs, ctx->d, li, a, (uint32_t)nreq, (uint32_t*)(sb + o_pub));
+    hipLaunchKernelGGL(k_serve<2>, grid, dim3(WG), lds_of(ctx, (const void*)k_serve<2>), se->hs, ctx->d, li, a, pub_dev);
   else
-    hipLaunchKernelGGL(k_serve<4>, grid, dim3(WG), lds_of(ctx, (const void*)k_serve<4>), hs, ctx->d, li, a, (uint32_t)nreq, (uint32_t*)(sb + o_pub));
-  HIPCHK(ctx, hipGetLastError());
-  // ---- host loop: publish arrivals in real time, admit by queue and cache budget, and
-  //      record when each request's outputs become visible
-  const uint64_t sq_slots = (uint64_t)ctx->d.num_qp * ctx->d.depth;
-  const uint64_t cap_look = opts && opts->max_inflight_lookups ? opts->max_inflight_lookups
-                                                               : std::max<uint64_t>(sq_slots, max_req_look);
-  const uint64_t cap_lines = opts && opts->max_inflight_lines ? opts->max_inflight_lines
-                                                             : std::max<uint64_t>(1, ctx->d.num_lines);
-  const uint64_t cap_req = opts && opts->max_inflight_requests ? opts->max_inflight_requests : 4096;
-  std::vector<uint64_t> inflight;
-  std::vector<double> t_pub(nreq, 0.0);
-  uint64_t next = 0, completed = 0, in_look = 0, in_lines = 0, max_in = 0;
-  auto look_of = [&](uint64_t r) { return (uint64_t)(bag_off[req_bag0[r + 1]] - bag_off[req_bag0[r]]); };
-  // a request's cache reservation: the lines one chunk of it can pin (a wave holds at
-  // most one chunk's misses of a bag while it waits), never more than half the budget
-  auto lines_of = [&](uint64_t r) {
-    return std::min<uint64_t>({look_of(r), (uint64_t)64, std::max<uint64_t>(1, cap_lines / 2)});
-  };
+    hipLaunchKernelGGL(k_serve<4>, grid, dim3(WG), lds_of(ctx, (const void*)k_serve<4>), se->hs, ctx->d, li, a, pub_dev);
+  if (hipGetLastError() != hipSuccess) return cleanup(AGILE_EHIP, "session: launch failed");
+  ctx->session = se;
+  *out = se;
+  return AGILE_OK;
+}
+
+agile_status agile_session_submit(agile_session se, uint32_t nbags, const int64_t* bag_off, const int64_t* idx,
+                                  uint64_t* out_req) {
+  if (!se) return AGILE_EINVAL;
+  agile_ctx ctx = se->ctx;
+  if (ctx->poisoned || *ctx->abort_host) return map_device_error(ctx) ? map_device_error(ctx) : AGILE_ETIMEDOUT;
+  if (!bag_off || !out_req || nbags == 0 || bag_off[0] != 0)
+    return fail(ctx, AGILE_EINVAL, "submit: a request needs >= 1 bag and offsets from 0");
+  for (uint32_t k = 0; k < nbags; ++k)
+    if (bag_off[k + 1] < bag_off[k]) return fail(ctx, AGILE_EINVAL, "submit: bag offsets must not decrease");
+  const uint64_t L = (uint64_t)bag_off[nbags];
+  if (L && !idx) return fail(ctx, AGILE_EINVAL, "submit: null lookups");
+  if (L > SESSION_MAX_LOOKUPS || nbags > SESSION_MAX_LOOKUPS)
+    return fail(ctx, AGILE_EINVAL, "submit: request larger than the session's maximum");
+  for (uint64_t j = 0; j < L; ++j)
+    if (idx[j] < 0 || (uint64_t)idx[j] >= se->tb.rows) return fail(ctx, AGILE_EINVAL, "submit: row out of range");
+  // admission: the queue budget (lookups in flight, each may miss), the cache budget (the
+  // lines one chunk of each request in flight can pin), the request budget, ring room
+  const uint64_t lines = std::min<uint64_t>({std::max<uint64_t>(L, 1), (uint64_t)64,
+                                             std::max<uint64_t>(1, se->cap_lines / 2)});
+  const bool empty = se->live.empty();
+  if (!empty && (se->in_look + L > se->cap_look || se->in_lines + lines > se->cap_lines ||
+                 se->live.size() >= se->cap_req))
+    return AGILE_EAGAIN;
+  const uint64_t bag_tail = empty ? se->next_bag : se->live.front().bag0;
+  const uint64_t look_tail = empty ? se->next_look : se->live.front().look0;
+  const uint64_t req_tail = empty ? se->next_req : se->live.front().id;
+  if (se->next_bag + nbags - bag_tail > se->bag_cap || se->next_look + L - look_tail > se->look_cap ||
+      se->next_req + 1 - req_tail > se->req_cap)
+    return AGILE_EAGAIN;
+  const uint64_t r = se->next_req, b0 = se->next_bag, j0 = se->next_look;
+  for (uint32_t k = 0; k < nbags; ++k) {
+    const uint64_t slot = (b0 + k) & (se->bag_cap - 1);
+    se->bag_j0[slot] = j0 + (uint64_t)bag_off[k];
+    se->bag_j1[slot] = j0 + (uint64_t)bag_off[k + 1];
+    se->bag_req[slot] = r;
+    se->bag_tab[slot] = k % se->tb.num_tables;
+  }
+  for (uint64_t j = 0; j < L; ++j) se->idx[(j0 + j) & (se->look_cap - 1)] = idx[j];
+  const uint64_t rs = r & (se->req_cap - 1);
+  se->req_nbags[rs] = nbags;
+  __atomic_store_n(&se->done[rs], 0u, __ATOMIC_RELAXED);
+  // publication: every entry above is written before the count that makes it visible
+  __atomic_store_n(&se->ctl[0], b0 + nbags, __ATOMIC_RELEASE);
+  se->live.push_back({r, b0, nbags, j0, L, lines, false});
+  se->next_req = r + 1;
+  se->next_bag = b0 + nbags;
+  se->next_look = j0 + L;
+  se->in_look += L;
+  se->in_lines += lines;
+  *out_req = r;
+  return AGILE_OK;
+}
+
+agile_status agile_session_poll(agile_session se, uint64_t req, float* out) {
+  if (!se) return AGILE_EINVAL;
+  agile_ctx ctx = se->ctx;
+  if (se->live.empty() || req < se->live.front().id || req >= se->next_req)
+    return fail(ctx, AGILE_EINVAL, "poll: unknown or already collected request");
+  session_req& e = se->live[req - se->live.front().id];
+  if (e.polled) return fail(ctx, AGILE_EINVAL, "poll: request already collected");
+  if (!__atomic_load_n(&se->done[req & (se->req_cap - 1)], __ATOMIC_ACQUIRE)) {
+    if (*ctx->abort_host) {
+      ctx->poisoned = true;
+      return fail(ctx, AGILE_ETIMEDOUT, "poll: the session was aborted on the device");
+    }
+    return AGILE_EAGAIN;
+  }
+  const uint32_t dim = se->tb.dim;
+  if (out)
+    for (uint64_t k = 0; k < e.nb; ++k)
+      memcpy(out + k * dim, se->out + ((e.bag0 + k) & (se->bag_cap - 1)) * dim, 4ull * dim);
+  e.polled = true;
+  se->in_look -= e.nl;
+  se->in_lines -= e.lines;
+  while (!se->live.empty() && se->live.front().polled) se->live.pop_front();
+  return AGILE_OK;
+}
+
+agile_status agile_session_close(agile_session se) {
+  if (!se) return AGILE_EINVAL;
+  agile_ctx ctx = se->ctx;
+  // every request already submitted completes first (outputs not collected are dropped)
+  const double limit_s = 4.0 * (double)ctx->cfg.timeout_ns * 1e-9 + 30.0;
+  const auto t0 = std::chrono::steady_clock::now();
+  agile_status st = AGILE_OK;
+  for (const session_req& e : se->live) {
+    while (!e.polled && !__atomic_load_n(&se->done[e.id & (se->req_cap - 1)], __ATOMIC_ACQUIRE)) {
+      if (*ctx->abort_host ||
+          std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count() > limit_s) {
+        __atomic_store_n(ctx->abort_host, 1u, __ATOMIC_SEQ_CST);
+        st = fail(ctx, AGILE_ETIMEDOUT, "session close: requests did not complete");
+        break;
+      }
+      std::this_thread::sleep_for(std::chrono::microseconds(50));
+    }
+    if (st != AGILE_OK) break;
+  }
+  __atomic_store_n(&se->ctl[1], 1ull, __ATOMIC_RELEASE);  // stop
+  const agile_status s2 = sync_stream(ctx, se->hs);
+  (void)hipStreamDestroy(se->hs);
+  (void)hipFree(se->dev);
+  (void)hipHostFree(se->host);
+  ctx->session = nullptr;
+  delete se;
+  return st != AGILE_OK ? st : s2;
+}
+
+agile_status agile_serve(agile_ctx ctx, agile_store store, const agile_tables* tb, uint32_t K, uint32_t mode,
+                         uint64_t nreq, const double* arrival_s, const int64_t* req_bag0, const int64_t* bag_off,
+                         const int64_t* idx, float* out, double* latency_s, const agile_serve_opts* opts,
+                         agile_serve_report* report) {
+  agile_status s = check_usable(ctx);
+  if (s) return s;
+  if (!tb || !arrival_s || !req_bag0 || !bag_off || !out || !latency_s)
+    return fail(ctx, AGILE_EINVAL, "serve: null pointer");
+  if (nreq == 0) return AGILE_OK;
+  for (uint64_t r = 0; r < nreq; ++r)
+    if (req_bag0[r + 1] <= req_bag0[r] || (r && arrival_s[r] < arrival_s[r - 1]))
+      return fail(ctx, AGILE_EINVAL, "serve: every request needs >= 1 bag; arrivals must not decrease");
+  // the replay harness is one client of the session: it submits each request once it has
+  // arrived and the session admits it, and collects outputs as they complete
+  agile_session se = nullptr;
+  if ((s = agile_session_open(ctx, store, tb, K, mode, opts, &se)) != AGILE_OK) return s;
+  const uint32_t dim = tb->dim;
+  uint64_t nlook = 0;
+  std::vector<int64_t> rel;
+  std::vector<uint64_t> ids(nreq, 0);
+  std::vector<uint64_t> pending;  // submitted, not yet collected (request numbers)
+  uint64_t next = 0, completed = 0, max_in = 0;
   const auto t0 = std::chrono::steady_clock::now();
   auto since = [&]() { return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count(); };
   double last_progress = 0.0;
@@ -2791,54 +2962,59 @@ agile_status agile_serve(agile_ctx ctx, agile_store store, const agile_tables* t
     const double now = since();
     bool moved = false;
     while (next < nreq && arrival_s[next] <= now) {
-      const uint64_t L = look_of(next), Ln = lines_of(next);
-      const bool empty = inflight.empty();
-      if (!empty && (in_look + L > cap_look || in_lines + Ln > cap_lines || inflight.size() >= cap_req)) break;
-      in_look += L;
-      in_lines += Ln;
-      inflight.push_back(next);
-      max_in = std::max<uint64_t>(max_in, inflight.size());
-      t_pub[next] = now;
+      const int64_t b0 = req_bag0[next], b1 = req_bag0[next + 1];
+      rel.resize((size_t)(b1 - b0 + 1));
+      for (int64_t b = b0; b <= b1; ++b) rel[b - b0] = bag_off[b] - bag_off[b0];
+      const agile_status r = agile_session_submit(se, (uint32_t)(b1 - b0), rel.data(), idx + bag_off[b0], &ids[next]);
+      if (r == AGILE_EAGAIN) break;  // no room yet: it waits, and so do the ones behind it
+      if (r != AGILE_OK) {
+        st_loop = r;
+        break;
+      }
+      nlook += (uint64_t)(bag_off[b1] - bag_off[b0]);
+      pending.push_back(next);
+      max_in = std::max<uint64_t>(max_in, pending.size());
       ++next;
-      __atomic_store_n((uint32_t*)&pub[0], (uint32_t)next, __ATOMIC_RELEASE);
       moved = true;
     }
-    for (size_t i = 0; i < inflight.size();) {
-      const uint64_t r = inflight[i];
-      if (__atomic_load_n((uint32_t*)&done[r], __ATOMIC_ACQUIRE)) {
-        const double tn = since();
-        latency_s[r] = tn - arrival_s[r];
-        in_look -= look_of(r);
-        in_lines -= lines_of(r);
-        inflight[i] = inflight.back();
-        inflight.pop_back();
+    if (st_loop != AGILE_OK) break;
+    for (size_t i = 0; i < pending.size();) {
+      const uint64_t q = pending[i];
+      const agile_status r = agile_session_poll(se, ids[q], out + (uint64_t)req_bag0[q] * dim);
+      if (r == AGILE_OK) {
+        latency_s[q] = since() - arrival_s[q];
+        pending[i] = pending.back();
+        pending.pop_back();
         ++completed;
         moved = true;
-      } else {
+      } else if (r == AGILE_EAGAIN) {
         ++i;
+      } else {
+        st_loop = r;
+        break;
       }
     }
+    if (st_loop != AGILE_OK) break;
     if (moved) {
       last_progress = now;
-    } else if (now - last_progress > limit_s || *ctx->abort_host) {
-      __atomic_store_n((uint32_t*)&pub[1], 1u, __ATOMIC_RELEASE);
+    } else if (now - last_progress > limit_s) {
       __atomic_store_n(ctx->abort_host, 1u, __ATOMIC_SEQ_CST);
       st_loop = fail(ctx, AGILE_ETIMEDOUT, "serve: no progress");
       break;
     }
   }
   const double elapsed = since();
-  s = sync_stream(ctx, hs);
+  const uint64_t waves = se->user_waves;
+  s = agile_session_close(se);
   if (st_loop != AGILE_OK) return st_loop;
   if (s != AGILE_OK) return s;
-  memcpy(out, hout, 4 * nbags * tb->dim);
   if (report) {
     report->elapsed_s = elapsed;
     report->requests = nreq;
-    report->bags = nbags;
+    report->bags = (uint64_t)req_bag0[nreq];
     report->lookups = nlook;
     report->max_inflight_requests = max_in;
-    report->user_waves = active;
+    report->user_waves = waves;
   }
   return AGILE_OK;
 }

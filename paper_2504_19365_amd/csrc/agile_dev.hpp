@@ -158,7 +158,7 @@ enum : uint32_t {
   C_WORK_P1, C_WORK_P2, C_WORK_P3, C_WORK_P4, C_WORK_P5, C_WORK_P6, C_WORK_P7,
   // resident-hit pass: bags it deferred to the I/O pass, its work counters (partitions)
   C_DEFER, C_HWORK, C_HWORK_P1, C_HWORK_P2, C_HWORK_P3, C_HWORK_P4, C_HWORK_P5, C_HWORK_P6,
-  C_HWORK_P7, C_EXH, C_HEXH, C_COUNT
+  C_HWORK_P7, C_COUNT
 };
 constexpr uint32_t CSTRIDE = 16;  // u64 per counter
 
@@ -831,8 +831,14 @@ __device__ __forceinline__ void completion(const dev_ctx& c, const launch_t& li,
       for (uint32_t r = 0; r < reps; ++r) __builtin_amdgcn_s_sleep(1);
     }
     if (now() - idle_since > 4 * c.timeout_ticks) {
-      raise_error(c, E_TIMEDOUT, 0xC2000000ull | w);
-      break;
+      // with every command completed this is an idle serving session (requests may come
+      // far apart), not a lost completion
+      if (uni64(ld_rlx(counter(c, C_SUBMITTED))) == uni64(ld_rlx(counter(c, C_COMPLETED)))) {
+        idle_since = now();
+      } else {
+        raise_error(c, E_TIMEDOUT, 0xC2000000ull | w);
+        break;
+      }
     }
   }
   if (lane() < nmy) {
@@ -867,8 +873,6 @@ __device__ __forceinline__ void run_service(const dev_ctx& c, const launch_t& li
       for (uint32_t p = 0; p < WORK_PARTS; ++p) st_rlx(counter(c, work_counter(p)), 0ull);
       // and those of the resident-hit pass that ran before this launch, if any
       st_rlx(counter(c, C_DEFER), 0ull);
-      st_rlx(counter(c, C_EXH), 0ull);
-      st_rlx(counter(c, C_HEXH), 0ull);
       for (uint32_t p = 0; p < WORK_PARTS; ++p) st_rlx(counter(c, C_HWORK + p), 0ull);
       st_rel(counter(c, C_SVC_EXIT), 0ull);
     }
