@@ -78,12 +78,12 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--profile-only", nargs="?", const="step", default=None,
-                    choices=("step", "hit", "bwd", "randread", "graph"),
+                    choices=("step", "hit", "bwd", "randread", "devices", "graph"),
                     help="for profilers: 'step' runs the warm-up and timed steps only, 'hit' "
-                         "the hit-path replay only, 'bwd' / 'randread' / 'graph' that "
+                         "the hit-path replay only, 'bwd' / 'randread' / 'devices' / 'graph' that "
                          "measurement only")
-    ap.add_argument("--extras", default="serve,randread,bwd,graph",
-                    help="comma list of extra measurements: serve, bwd, graph, randread "
+    ap.add_argument("--extras", default="serve,randread,devices,bwd,graph",
+                    help="comma list of extra measurements: serve, bwd, graph, randread, devices "
                          "('' = none)")
     ap.add_argument("--cpu-child", default="", choices=("", "single", "par"),
                     help=argparse.SUPPRESS)
@@ -197,6 +197,76 @@ def measure_randread(agile, gen, buf, nblocks: int, cfg: dict, log):
         ctx.close_store()
         ctx.shutdown()
     res["sampled_blocks_equal_image"] = checked
+    return res
+
+
+def measure_devices(agile, gen, buf, nbytes: int, log, reps: int = 3):
+    """Sec. 4.3 (Fig. 5 and Fig. 6): 4 KiB random reads (ticket calls) and random writes
+    (write-through of whole 4 KiB lines) over 1, 2, 3 and 4 emulated devices, each with
+    80 us per command and a 1.5M IOPS cap, at a swept number of outstanding commands.
+    The devices are disjoint slices of the pinned store image, striped line by line
+    (line l on device l mod n).  Cold cache for every call; time of the launch from HIP
+    events on the launch's stream.  Each write carries the bytes its line already holds,
+    so the image is unchanged (the parity of writes is the tests' business); 64 sampled
+    read tickets per device count are compared with the image byte for byte."""
+    import torch
+    res = {"reads": [], "writes": [], "qp": 48, "qp_depth": 1024}
+    checked = True
+    stream = torch.cuda.current_stream()
+    for n in (1, 2, 3, 4):
+        each = nbytes // n // 4096 * 4096
+        slices = buf.array[:n * each].reshape(n, each // 4096, 4096)
+        ctx = agile.Context(cache_bytes=2 << 30, line_bytes=4096, assoc=16, num_qp=48,
+                            qp_depth=1024, latency_ns=80_000, iops_cap=1_500_000,
+                            timeout_ns=int(20e9))
+        ctx.open_store_striped([buf.ptr + d * each for d in range(n)], each)
+        nlines = n * (each // 4096)
+        for count in (1024, 8192, 65536, 262144):
+            lines = gen.uniform_blocks(17 + n, count, nlines)
+            d_lines = torch.from_numpy(lines.view(np.int64)).cuda()
+            tickets = torch.empty(count, dtype=torch.int64, device="cuda")
+            ptrs = torch.empty(count, dtype=torch.int64, device="cuda")
+            rms, wms = [], []
+            for r in range(reps):
+                ctx.invalidate()
+                ctx.stats(reset=True)
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                ctx.async_read(d_lines, tickets)
+                e1.record(stream)
+                ctx.wait(tickets, ptrs)
+                if r == 0 and count == 65536:
+                    pv = ptrs.cpu().numpy()
+                    for i in np.random.default_rng(9).choice(count, 64, replace=False):
+                        l = int(lines[i])
+                        got = torch.as_tensor(_DeviceBytes(int(pv[i]), 4096), device="cuda")
+                        checked &= bool(np.array_equal(got.cpu().numpy(), slices[l % n, l // n]))
+                ctx.release(tickets)
+                ctx.sync()
+                rms.append(e0.elapsed_time(e1))
+                rcmds = ctx.stats()["read_cmds"]
+            src = torch.from_numpy(slices[lines % n, lines // n]).cuda()
+            for r in range(reps):
+                ctx.invalidate()
+                ctx.stats(reset=True)
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                ctx.write(d_lines, src)
+                e1.record(stream)
+                ctx.sync()
+                wms.append(e0.elapsed_time(e1))
+                wcmds = ctx.stats()["write_cmds"]
+            del src
+            for key, ms, cmds in (("reads", rms, rcmds), ("writes", wms, wcmds)):
+                m = float(np.median(ms[1:] if len(ms) > 1 else ms))
+                row = {"devices": n, "outstanding": count, "cmds": int(cmds), "ms": round(m, 4),
+                       "iops": round(cmds / (m * 1e-3), 1),
+                       "gbs": round(cmds * 4096 / (m * 1e-3) / 1e9, 3)}
+                res[key].append(row)
+                log(f"devices {key}: {row}")
+        ctx.close_store()
+        ctx.shutdown()
+    res["sampled_reads_equal_image"] = checked
     return res
 
 
@@ -565,6 +635,34 @@ def main():
         res = measure_randread(agile, gen, buf, T * table_bytes // 4096, cfg, log)
         print(json.dumps({"profile_only": "randread", **res}))
         return
+    if args.profile_only == "devices":
+        res = measure_devices(agile, gen, buf, T * table_bytes, log)
+        print(json.dumps({"profile_only": "devices", **res}))
+        return
+
+    def resident_forward(c, off_b, idx_b, expect, reps=5):
+        """The same batch through the kernel-only forward over a copy of the whole store
+        image in HBM (no cache): the ceiling of the hit path at this batch.  Returns the
+        median launch time (HIP events) and whether its outputs equal `expect`."""
+        img = torch.empty(buf.nbytes, dtype=torch.uint8, device="cuda")
+        img.copy_(torch.from_numpy(buf.array))
+        rout = torch.empty_like(expect)
+        tbr = c.tables(rows, dim, T)
+        c.embbag_forward_resident(img, buf.nbytes, tbr, idx_b, off_b, B, args.K, rout)
+        c.sync()
+        ms_r = []
+        for _ in range(reps):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            c.embbag_forward_resident(img, buf.nbytes, tbr, idx_b, off_b, B, args.K, rout)
+            e1.record(stream)
+            c.sync()
+            ms_r.append(e0.elapsed_time(e1))
+        same_r = bool(torch.equal(rout, expect))
+        del img, rout
+        torch.cuda.empty_cache()
+        return float(np.median(ms_r)), same_r
 
     if args.profile_only == "hit":
         last = nb - 1
@@ -586,8 +684,9 @@ def main():
             hctx.sync()
             ms.append(e0.elapsed_time(e1))
         h1 = hctx.stats()
+        res_ms, res_same = resident_forward(hctx, off_b, idx_b, hout)
         print(json.dumps({"profile_only": "hit", "ms": ms, "misses": h1["misses"] - h0["misses"],
-                          "lookups": n_b}))
+                          "lookups": n_b, "resident_ms": res_ms, "resident_same": res_same}))
         hctx.close_store()
         hctx.shutdown()
         return
@@ -664,6 +763,10 @@ def main():
     hit_gbs = hit_bytes / (ms_hit * 1e-3) / 1e9
     log(f"hit replay ({args.hit_cache_gib} GiB cache): {ms_hit:.3f} ms, misses {hit_misses}, "
         f"{hit_gbs:.0f} GB/s, same output as the timed step: {hit_same}")
+    ms_res, res_same = resident_forward(hctx, batches[last][0], batches[last][1], hout)
+    res_gbs = hit_bytes / (ms_res * 1e-3) / 1e9
+    log(f"kernel-only forward (tables resident in HBM): {ms_res:.3f} ms, {res_gbs:.0f} GB/s, "
+        f"same output: {res_same}")
 
     # ---- compute sweep at full occupancy: async vs sync at identical outputs
     def t_hit(K, ids=(last,), waves=0):
@@ -785,6 +888,8 @@ def main():
     wanted = [e for e in args.extras.split(",") if e]
     if "randread" in wanted:
         extras["randread_4k"] = measure_randread(agile, gen, buf, T * table_bytes // 4096, cfg, log)
+    if "devices" in wanted:
+        extras["devices_4k"] = measure_devices(agile, gen, buf, T * table_bytes, log)
     if wanted:
         ctx.close_store()
         ctx.shutdown()
@@ -838,6 +943,12 @@ def main():
         "hit_path": {"gbs": round(hit_gbs, 1), "frac_hbm_peak": round(hit_gbs / HBM_PEAK_GBS, 4),
                      "ms": round(ms_hit, 4), "misses_in_replay": hit_misses, "lookups": n_last,
                      "cache_gib": args.hit_cache_gib, "same_output_as_step": hit_same},
+        # Sec. 4.5-style breakdown of the same batch: kernel only (tables resident in HBM,
+        # no cache), every lookup a cache hit, and the timed step through the store
+        "dlrm_breakdown": {"kernel_only_ms": round(ms_res, 4), "kernel_only_gbs": round(res_gbs, 1),
+                           "kernel_only_same_output": res_same,
+                           "cache_hit_ms": round(ms_hit, 4), "full_io_ms": round(ms_step, 3),
+                           "hit_over_kernel_only": round(ms_hit / ms_res, 3)},
         "k_bal": k_bal,
         "compute_sweep_full_gpu": sweep,
         "overlap_1024_threads": overlap,
@@ -859,7 +970,10 @@ def main():
                          "unit": "GB/s", "frac": round(hit_gbs / HBM_PEAK_GBS, 4),
                          "traffic": committed_traffic(HIT_TRAFFIC_PROFILE) if default_workload else None,
                          "algorithmic_bytes_per_launch": int(hit_bytes),
-                         "kernel": "k_embbag<2> (hit-only replay, 8 GiB cache)"},
+                         "kernel": "k_embbag_hit<2> + the empty k_embbag<2> pass (hit-only "
+                                   "replay, 8 GiB cache)",
+                         "kernel_only_gbs": round(res_gbs, 1),
+                         "frac_of_kernel_only": round(ms_res / ms_hit, 4)},
         "cpu_baseline": cpu,
         **extras,
         "device": {"cus": info["cu_count"], "wallclock_hz": info["wallclock_hz"],

@@ -109,6 +109,20 @@ agile_status agile_host_free(void* p);
 agile_status agile_open_store(agile_ctx ctx, void* host_image, uint64_t bytes,
                               uint32_t block_bytes, uint32_t flags, agile_store* out);
 
+/* Several emulated devices behind one store (Sec. 4.3's multi-SSD setup: request i goes
+ * to device i mod n).  The store is striped one cache line at a time: line l of the
+ * store (bytes [l*line_bytes, (l+1)*line_bytes)) is line l / n of device l mod n, whose
+ * image is host_images[l mod n] (each pinned as for agile_open_store, bytes_each bytes,
+ * a multiple of the context's line_bytes when n > 1).  The store holds n * bytes_each
+ * bytes.  Each device has its own emulated latency and its own IOPS cap (the config's
+ * latency_ns and iops_cap apply per device), and owns the queue pairs q with
+ * q mod n == its number (num_qp must be a multiple of n).  1 <= n <= AGILE_MAX_DEVICES;
+ * agile_open_store is the case n = 1.  Same ownership and errors as agile_open_store. */
+#define AGILE_MAX_DEVICES 8
+agile_status agile_open_store_striped(agile_ctx ctx, void* const* host_images, uint32_t n,
+                                      uint64_t bytes_each, uint32_t block_bytes, uint32_t flags,
+                                      agile_store* out);
+
 /* Roughly closeNvme: blocks until idle, invalidates the cache (dirty lines are NOT
  * written back; call agile_flush first) and detaches the store.  Returns the sticky
  * error, if any. */
@@ -151,6 +165,18 @@ agile_status agile_release(agile_ctx ctx, const agile_ticket* d_tickets, uint32_
  * (Sec. 3.4 case d).  Requires that no line is pinned.  Blocks until done and returns
  * the sticky error, if any. */
 agile_status agile_flush(agile_ctx ctx, agile_store store, void* stream);
+
+/* The write of Sec. 3.5's API (asyncWrite: through the cache; the caller's buffer may
+ * be reused once the call is done), for whole lines: line d_lines[i] (device uint64,
+ * a line id < the store's lines) takes line_bytes bytes from d_src + i * line_bytes
+ * (device memory).  Each line is found in the cache or allocated without a read (a
+ * dirty victim is written back first), filled, and written to its device by one WRITE
+ * command before the call returns (write-through); the cached copy stays, clean.  Of
+ * entries that name the same line, the one at the highest i within a wavefront's 64 is
+ * written; across wavefronts the order is unspecified.  The store must hold whole
+ * lines.  Blocks until done; returns the sticky error, if any. */
+agile_status agile_write(agile_ctx ctx, agile_store store, const uint64_t* d_lines, uint32_t n,
+                         const void* d_src, void* stream);
 
 /* Drops every clean, unpinned line (cold cache).  Dirty lines make it fail with
  * AGILE_ESTATE (flush first).  Blocks until done. */
@@ -341,6 +367,18 @@ agile_status agile_bfs_resident(agile_ctx ctx, const void* d_image, uint64_t ima
                                 uint32_t* out_levels, void* stream);
 agile_status agile_spmv_resident(agile_ctx ctx, const void* d_image, uint64_t image_bytes,
                                  const agile_csr* g, const float* d_x, float* d_y, void* stream);
+
+/* The same kernel-only baseline for the embedding-bag forward (Sec. 4.4's DLRM lookups):
+ * the tables read straight from a copy of the store image resident in device memory
+ * (d_image, image_bytes; tb, d_idx, d_off, B, K and d_out as in agile_embbag_forward),
+ * with no cache, queue or service wavefront; the outputs are bit-identical to the cached
+ * forward's.  A row index outside [0, rows) contributes nothing and raises the sticky
+ * error (AGILE_ESTATE from the next blocking call).  No store needs to be open.
+ * Stream-ordered. */
+agile_status agile_embbag_forward_resident(agile_ctx ctx, const void* d_image, uint64_t image_bytes,
+                                           const agile_tables* tb, const int64_t* d_idx,
+                                           const int64_t* d_off, uint64_t B, uint32_t K,
+                                           float* d_out, void* stream);
 
 /* ---------------------------------------------------------------- serving --------- */
 typedef struct agile_serve_opts {

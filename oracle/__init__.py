@@ -57,6 +57,8 @@ def lib():
         L.oracle_clock_access.restype = C.c_int
         L.oracle_clock_access.argtypes = [vp, u64, C.c_int, C.POINTER(C.c_int32)]
         L.oracle_clock_run.argtypes = [vp, vp, vp, u64, vp, vp]
+        L.oracle_stripe_split.argtypes = [vp, u64, u64, u32, vp]
+        L.oracle_write_units.argtypes = [vp, u64, vp, u64, vp]
         L.oracle_clock_flush.restype = u64
         L.oracle_clock_flush.argtypes = [vp]
         L.oracle_clock_counters.argtypes = [vp, vp]
@@ -188,3 +190,24 @@ class Clock:
 
 def eq1(ctc: float) -> float:
     return float(lib().oracle_eq1(ctc))
+
+
+def stripe_split(logical: np.ndarray, n: int, unit_bytes: int) -> list:
+    """Device images of a logical image interleaved unit by unit over n devices."""
+    logical = np.ascontiguousarray(logical).view(np.uint8).ravel()
+    units = logical.size // unit_bytes
+    assert units * unit_bytes == logical.size and units % n == 0
+    devs = [np.empty(units // n * unit_bytes, dtype=np.uint8) for _ in range(n)]
+    ptrs = (C.c_void_p * n)(*[d.ctypes.data for d in devs])
+    lib().oracle_stripe_split(_p(logical), units, unit_bytes, n, ptrs)
+    return devs
+
+
+def write_units(image: np.ndarray, unit_bytes: int, lines, src) -> np.ndarray:
+    """A copy of image after writing src[i] to unit lines[i], in order."""
+    out = np.array(np.ascontiguousarray(image).view(np.uint8).ravel())
+    lines = np.ascontiguousarray(lines, dtype=np.uint64)
+    src = np.ascontiguousarray(src).view(np.uint8).ravel()
+    assert src.size == lines.size * unit_bytes and (lines.size == 0 or int(lines.max()) < out.size // unit_bytes)
+    lib().oracle_write_units(_p(out), unit_bytes, _p(lines), lines.size, _p(src))
+    return out

@@ -259,3 +259,18 @@ double oracle_eq1(double ctc) {
   if (ctc < 0.0) return NAN;
   return ctc <= 1.0 ? 1.0 + ctc : 1.0 + 1.0 / ctc;
 }
+
+/* ---- interleaving over several devices (Sec. 4.3) */
+void oracle_stripe_split(const uint8_t* logical, uint64_t units, uint64_t unit_bytes, uint32_t n,
+                         uint8_t* const* devs) {
+  for (uint64_t u = 0; u < units; ++u) {
+    const uint32_t d = (uint32_t)(u % n);
+    const uint64_t k = u / n;
+    memcpy(devs[d] + k * unit_bytes, logical + u * unit_bytes, unit_bytes);
+  }
+}
+
+void oracle_write_units(uint8_t* image, uint64_t unit_bytes, const uint64_t* lines, uint64_t k,
+                        const uint8_t* src) {
+  for (uint64_t i = 0; i < k; ++i) memcpy(image + lines[i] * unit_bytes, src + i * unit_bytes, unit_bytes);
+}

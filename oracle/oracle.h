@@ -109,6 +109,21 @@ void oracle_clock_state(const oracle_clock* c, int64_t* tags, uint8_t* dirty);
 /* Ideal overlap speedup, Eq. 1 (Sec. 4.2): 1 + CTC for 0 <= CTC <= 1, 1 + 1/CTC above. */
 double oracle_eq1(double ctc);
 
+/* Interleaving over several devices (Sec. 4.3: request i goes to device i mod n), one
+ * unit of unit_bytes at a time.  Unit u of the logical image is unit u / n of device
+ * u mod n.  split: logical (units * unit_bytes bytes, units a multiple of n) ->
+ * devs[d] (units / n units each).  Pins: a hand-worked 3-device example, n = 1 is the
+ * identity, and every unit lands once (test_oracle_stripe). */
+void oracle_stripe_split(const uint8_t* logical, uint64_t units, uint64_t unit_bytes, uint32_t n,
+                         uint8_t* const* devs);
+
+/* Writes of whole units in the given order (a later write of a unit replaces an earlier
+ * one): unit lines[i] of image takes src + i * unit_bytes.  The write of Sec. 3.5's
+ * API as seen in the store once it is done.  Pins: hand-worked overwrite order and
+ * untouched units unchanged (test_oracle_stripe). */
+void oracle_write_units(uint8_t* image, uint64_t unit_bytes, const uint64_t* lines, uint64_t k,
+                        const uint8_t* src);
+
 #ifdef __cplusplus
 }
 #endif

@@ -140,6 +140,11 @@ def lib():
             "agile_session_submit": (st, [vp, u32, vp, vp, C.POINTER(C.c_uint64)]),
             "agile_session_poll": (st, [vp, u64, vp]),
             "agile_session_close": (st, [vp]),
+            "agile_open_store_striped": (st, [vp, C.POINTER(vp), u32, u64, u32, u32,
+                                              C.POINTER(vp)]),
+            "agile_write": (st, [vp, vp, vp, u32, vp, vp]),
+            "agile_embbag_forward_resident": (st, [vp, vp, u64, C.POINTER(Tables), vp, vp, u64, u32,
+                                                   vp, vp]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -311,6 +316,26 @@ class Context:
                            nbytes)
         return self.store
 
+    def open_store_striped(self, images, nbytes_each: int | None = None) -> Store:
+        """A store striped line by line over several emulated devices, one image each
+        (agile_open_store_striped): store line l is line l // n of images[l % n]."""
+        ptrs = [im.ptr if isinstance(im, PinnedBuffer) else int(im) for im in images]
+        if nbytes_each is None:
+            nbytes_each = images[0].nbytes
+        arr = (C.c_void_p * len(ptrs))(*ptrs)
+        h = C.c_void_p()
+        self._check(lib().agile_open_store_striped(self.h, arr, len(ptrs), nbytes_each, 4096, 0,
+                                                   C.byref(h)), "agile_open_store_striped")
+        self.store = Store(self, h.value, None, nbytes_each * len(ptrs))
+        self.store.images = list(images)
+        return self.store
+
+    def write(self, lines, src, stream=None, store=None):
+        """Write-through of whole lines (agile_write): lines[i] gets src[i] (line_bytes)."""
+        store = store or self.store
+        self._check(lib().agile_write(self.h, store.handle, _ptr(lines), lines.numel(), _ptr(src),
+                                      _stream(stream)), "agile_write")
+
     def close_store(self, store: Store | None = None) -> int:
         store = store or self.store
         s = lib().agile_close_store(self.h, store.handle)
@@ -415,6 +440,15 @@ class Context:
                                              _ptr(level), C.byref(nl), _stream(stream)),
                     "agile_bfs_resident")
         return int(nl.value)
+
+    def embbag_forward_resident(self, image, nbytes: int, tb: Tables, idx, off, B: int, K: int,
+                                out, stream=None):
+        """Embedding-bag forward over a copy of the tables resident in device memory (no
+        cache); bit-identical to embbag_forward."""
+        self._check(lib().agile_embbag_forward_resident(self.h, _ptr(image), nbytes, C.byref(tb),
+                                                        _ptr(idx), _ptr(off), B, K, _ptr(out),
+                                                        _stream(stream)),
+                    "agile_embbag_forward_resident")
 
     def spmv_resident(self, image, nbytes: int, g: CSR, x, y, stream=None):
         """SpMV over a copy of the store image resident in device memory (no cache)."""

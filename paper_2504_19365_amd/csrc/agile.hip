@@ -785,6 +785,72 @@ __global__ __launch_bounds__(WG) void k_embbag_hit(dev_ctx c, launch_t li, embba
   user_wave_done(c, li);
 }
 
+// Embedding-bag forward over a copy of the tables resident in device memory: no cache,
+// queues or service wavefronts (the kernel-only side of a Sec. 4.5-style breakdown, and
+// the ceiling the cached hit path is measured against).  One wavefront per bag, four per
+// workgroup, so the hardware's dispatch of workgroups balances bags of uneven length.
+// Lane l holds elements [l*VPL, l*VPL + VPL) of the row; a bag's indices are loaded 64
+// at a time (one per lane) and its rows R at a time, all R loads in flight together.
+// The same arithmetic, in the same order, as the cached path: out = sum over the bag's
+// lookups, in order, of f_K(row), from +0.0f.
+constexpr uint32_t RES_WAVES = 4;
+template <int VPL>
+__global__ __launch_bounds__(64 * RES_WAVES) void k_embbag_resident(dev_ctx c, const uint8_t* img, embbag_args a) {
+  constexpr uint32_t R = 8;
+  const uint64_t bag = (uint64_t)blockIdx.x * RES_WAVES + threadIdx.x / 64;
+  if (bag >= a.nbags) return;
+  const int64_t j0 = a.off[bag], j1 = a.off[bag + 1];
+  const uint8_t* tab = img + a.base_off + (uint64_t)(bag % a.T) * a.table_bytes;
+  const uint32_t d0 = lane() * VPL;
+  const bool mine = d0 < a.dim;
+  float acc[VPL];
+#pragma unroll
+  for (int e = 0; e < VPL; ++e) acc[e] = 0.0f;
+  for (int64_t j = j0; j < j1; j += 64) {
+    const uint32_t n = (uint32_t)(j1 - j < 64 ? j1 - j : 64);
+    int64_t row = 0;
+    if (lane() < n) {
+      row = a.idx[j + lane()];
+      if ((uint64_t)row >= a.rows) {
+        raise_error(c, E_STATE, (uint64_t)row);
+        row = -1;  // contributes nothing
+      }
+    }
+    for (uint32_t u = 0; u < n; u += R) {
+      float v[R][VPL];
+#pragma unroll
+      for (uint32_t k = 0; k < R; ++k) {
+        const int64_t r = (int64_t)rdlane64((uint64_t)row, u + k < n ? u + k : 0);
+        const bool ok = u + k < n && r >= 0 && mine;
+        const float* p = reinterpret_cast<const float*>(tab + (uint64_t)(ok ? r : 0) * a.row_bytes) + d0;
+        if constexpr (VPL == 1) {
+          v[k][0] = ok ? p[0] : 0.0f;
+        } else {
+#pragma unroll
+          for (int h = 0; h < VPL / 2; ++h) {
+            float2 w = make_float2(0.0f, 0.0f);
+            if (ok) w = reinterpret_cast<const float2*>(p)[h];
+            v[k][2 * h] = w.x;
+            v[k][2 * h + 1] = w.y;
+          }
+        }
+      }
+#pragma unroll
+      for (uint32_t k = 0; k < R; ++k) {
+        const int64_t r = (int64_t)rdlane64((uint64_t)row, u + k < n ? u + k : 0);
+        if (u + k < n && r >= 0) {
+#pragma unroll
+          for (int e = 0; e < VPL; ++e) acc[e] += fK(v[k][e], a.K);
+        }
+      }
+    }
+  }
+  float* o = a.out + bag * a.dim + d0;
+#pragma unroll
+  for (int e = 0; e < VPL; ++e)
+    if (d0 + e < a.dim) o[e] = acc[e];
+}
+
 template <int VPL>
 __global__ __launch_bounds__(WG) void k_embbag(dev_ctx c, launch_t li, embbag_args a) {
   if (blockIdx.x < li.service_blocks) {
@@ -945,8 +1011,7 @@ __global__ __launch_bounds__(WG) void k_flush(dev_ctx c, launch_t li) {
   for (uint64_t base = (uint64_t)uw * 64; base < c.num_lines; base += (uint64_t)li.user_waves * 64) {
     const uint64_t i = base + lane();
     bool wb = false;
-    uint64_t slba = 0;
-    uint32_t nblk = c.blocks_per_line;
+    uint32_t tag = 0;
     if (i < c.num_lines) {
       uint64_t m = ld_rlx(c.meta + i);
       if (m_state(m) == ST_DIRTY) {
@@ -954,8 +1019,7 @@ __global__ __launch_bounds__(WG) void k_flush(dev_ctx c, launch_t li) {
           raise_error(c, E_STATE, i);
         } else if (cas(c.meta + i, m, (m & ~M_STATE) | ST_WRITEBACK)) {
           wb = true;
-          slba = (uint64_t)m_tag(m) * c.blocks_per_line;
-          if (slba + nblk > c.store_blocks) nblk = (uint32_t)(c.store_blocks - slba);
+          tag = m_tag(m);
         } else {
           raise_error(c, E_STATE, i);
         }
@@ -963,8 +1027,104 @@ __global__ __launch_bounds__(WG) void k_flush(dev_ctx c, launch_t li) {
     }
     const uint64_t nw = __popcll(ballot(wb));
     if (lane() == 0) count(c, C_WB_FLUSH, nw);
-    if (!submit(c, q, wb, OPC_WRITE, (uint32_t)i, slba, nblk)) break;
+    if (!submit_line(c, q, wb, OPC_WRITE, (uint32_t)i, tag)) break;
   }
+  user_wave_done(c, li);
+}
+
+// Write-through of whole lines (Sec. 3.5's write through the cache: the caller's buffer
+// may be reused once the call is done).  Lane i of a chunk takes lines[i]: the line is
+// found or allocated without a READ (its whole content is replaced; a dirty victim is
+// written back first), claimed by turning it WRITEBACK, filled from src by the whole
+// wave and sent to its device as one WRITE; the completion leaves it READY (clean) with
+// the new data.  A resident line is claimed only while no other write of it is in
+// flight, and a wave never holds a claimed line while it waits for another one: each
+// line is filled and submitted in the round that claimed it.  Lanes that found no
+// evictable way retry once the wave's other writes are out.  Of lanes that name the
+// same line, the highest writes it.
+__global__ __launch_bounds__(WG) void k_write_lines(dev_ctx c, launch_t li, const uint64_t* lines, uint32_t n,
+                                                    const uint8_t* src) {
+  if (blockIdx.x < li.service_blocks) {
+    run_service(c, li);
+    return;
+  }
+  user_wave_begin();
+  const uint32_t uw = (blockIdx.x - li.service_blocks) * WPB + threadIdx.x / 64;
+  const uint32_t q = uw % c.num_qp;
+  const uint64_t line_bytes = 1ull << c.line_shift;
+  const uint64_t nlines = (c.store_blocks + c.blocks_per_line - 1) / c.blocks_per_line;
+  for (uint64_t base = (uint64_t)uw * 64; base < n; base += (uint64_t)li.user_waves * 64) {
+    const uint64_t i = base + lane();
+    bool todo = i < n;
+    uint32_t lid = 0;
+    if (todo) {
+      const uint64_t l = lines[i];
+      if (l >= nlines) {
+        raise_error(c, E_STATE, l);
+        todo = false;
+      }
+      lid = (uint32_t)l;
+    }
+    spin_t sp;
+    while (ballot(todo)) {
+      chunk_t ch;
+      ch.act = todo;
+      ch.line_id = lid;
+      ch.off = 0;
+      if (!chunk_issue(c, ch, q, true, PIN_LINE, false, false)) goto out;
+      const bool ok = ch.act && st_ok(ch.st);
+      // source lane of each line: the highest lane of its leader's group
+      uint32_t from = lane();
+      for (uint64_t t = ballot(ok); t;) {
+        const uint32_t ld = rdlane(ch.leader, ffs64(t));
+        const uint64_t g = ballot(ok && ch.leader == ld);
+        if (lane() == ld) from = 63 - __builtin_clzll(g);
+        t &= ~g;
+      }
+      const bool lead = ok && ch.leader == lane();
+      // claim READY / DIRTY (resident) or our own FETCHING (just allocated) ->
+      // WRITEBACK; fill and submit what each round claimed
+      bool claiming = lead;
+      spin_t sc;
+      while (ballot(claiming)) {
+        bool got = false;
+        if (claiming) {
+          uint64_t m = ld_rlx(c.meta + ch.idx);
+          const uint32_t st = m_state(m);
+          const bool mine = st == ST_FETCHING && ch.st == A_MISS && m_gen(m) == ch.gen;
+          if (m_tag(m) != ch.line_id) {
+            raise_error(c, E_STATE, ch.idx);
+            add_rel(c.meta + ch.idx, (uint64_t)0 - RC_ONE);
+            claiming = false;
+          } else if ((st == ST_READY || st == ST_DIRTY || mine) &&
+                     cas(c.meta + ch.idx, m, (m & ~M_STATE) | ST_WRITEBACK)) {
+            got = true;
+            claiming = false;
+          }
+        }
+        const uint64_t gm = ballot(got);
+        if (gm) {
+          // the last reader of the line's old content (the WRITE before ours) is done
+          fence_acq();
+          for (uint64_t t = gm; t; t &= t - 1) {
+            const uint32_t l = ffs64(t);
+            const uint64_t si = base + rdlane(from, l);
+            const uint4* s4 = reinterpret_cast<const uint4*>(src + si * line_bytes);
+            uint4* d4 = reinterpret_cast<uint4*>(line_ptr(c, rdlane(ch.idx, l)));
+            for (uint64_t o = lane(); o < line_bytes / 16; o += 64) d4[o] = s4[o];
+          }
+          fence_rel();  // the line's data before the command that copies it out
+          if (!submit_line(c, q, got, OPC_WRITE, ch.idx, ch.line_id)) goto out;
+          // the WRITE is queued: the pin can go (a WRITEBACK line is never evicted)
+          if (got) add_rel(c.meta + ch.idx, (uint64_t)0 - RC_ONE);
+        }
+        if (ballot(claiming) && !sc.step(c, 0xF0000000ull | ch.idx)) goto out;
+      }
+      if (ch.act && ch.st != A_EAGAIN) todo = false;
+      if (ballot(todo) && !sp.step(c, 0xF1000000ull | lid)) goto out;
+    }
+  }
+out:
   user_wave_done(c, li);
 }
 
@@ -1657,10 +1817,12 @@ static void* scratch_dev[MAX_DEVICES];
 static std::mutex scratch_mu;
 
 struct agile_store_s {
-  void* host;
-  uint8_t* dev;
-  uint64_t bytes;
+  void* host[AGILE_MAX_DEVICES];
+  uint8_t* dev[AGILE_MAX_DEVICES];  // device addresses of the pinned images
+  uint32_t n_dev;
+  uint64_t bytes;       // logical store
   uint64_t blocks;
+  uint64_t dev_bytes;   // per device
 };
 
 struct session_req {
@@ -1717,7 +1879,7 @@ namespace {
 
 constexpr int KIND_EMBBAG1 = 0, KIND_EMBBAG2 = 1, KIND_EMBBAG4 = 2, KIND_READ = 3, KIND_FLUSH = 4,
               KIND_TRACE = 5, KIND_BWD1 = 6, KIND_BWD2 = 7, KIND_BWD4 = 8, KIND_SERVE1 = 9,
-              KIND_SERVE2 = 10, KIND_SERVE4 = 11, KIND_N = 12;
+              KIND_SERVE2 = 10, KIND_SERVE4 = 11, KIND_WRITE = 12, KIND_N = 13;
 
 agile_status fail(agile_ctx ctx, agile_status s, const std::string& msg) {
   if (ctx) ctx->last_error = msg;
@@ -1770,6 +1932,7 @@ int occupancy(agile_ctx ctx, int kind) {
     case KIND_EMBBAG4: f = (const void*)k_embbag<4>; break;
     case KIND_READ: f = (const void*)k_async_read; break;
     case KIND_FLUSH: f = (const void*)k_flush; break;
+    case KIND_WRITE: f = (const void*)k_write_lines; break;
     case KIND_BWD1: f = (const void*)k_bwd_sgd<1>; break;
     case KIND_BWD2: f = (const void*)k_bwd_sgd<2>; break;
     case KIND_BWD4: f = (const void*)k_bwd_sgd<4>; break;
@@ -1814,14 +1977,23 @@ launch_t make_launch(agile_ctx ctx, uint32_t user_waves, bool service) {
   return li;
 }
 
-void bind_store(agile_ctx ctx) {
+agile_status bind_store(agile_ctx ctx) {
   if (ctx->store) {
-    ctx->d.image = ctx->store->dev;
-    ctx->d.store_blocks = ctx->store->blocks;
+    const agile_store_s* st = ctx->store;
+    uint64_t tab[AGILE_MAX_DEVICES] = {};
+    for (uint32_t d = 0; d < st->n_dev; ++d) tab[d] = (uint64_t)(uintptr_t)st->dev[d];
+    HIPCHK(ctx, hipMemcpy((void*)ctx->d.dev_image, tab, sizeof(tab), hipMemcpyHostToDevice));
+    ctx->d.image = st->dev[0];
+    ctx->d.store_blocks = st->blocks;
+    ctx->d.dev_blocks = st->dev_bytes / 4096;
+    ctx->d.n_dev = st->n_dev;
   } else {
     ctx->d.image = nullptr;
     ctx->d.store_blocks = 0;
+    ctx->d.dev_blocks = 0;
+    ctx->d.n_dev = 1;
   }
+  return AGILE_OK;
 }
 
 agile_status map_device_error(agile_ctx ctx) {
@@ -1973,7 +2145,8 @@ agile_status agile_init(const agile_config* cfg_in, agile_ctx* out) {
                          (const void*)k_embbag<2>, (const void*)k_embbag<4>, (const void*)k_bfs_front,
                          (const void*)k_bfs_edges, (const void*)k_spmv, (const void*)k_bwd_sgd<1>,
                          (const void*)k_bwd_sgd<2>, (const void*)k_bwd_sgd<4>, (const void*)k_serve<1>,
-                         (const void*)k_serve<2>, (const void*)k_serve<4>, (const void*)k_trace};
+                         (const void*)k_serve<2>, (const void*)k_serve<4>, (const void*)k_trace,
+                         (const void*)k_write_lines};
     for (const void* f : fns) {
       hipFuncAttributes fa;
       memset(&fa, 0, sizeof(fa));
@@ -2023,7 +2196,11 @@ agile_status agile_init(const agile_config* cfg_in, agile_ctx* out) {
   if ((s = dalloc(ctx, &d.cq, nq * sizeof(cqe_t))) != AGILE_OK) return bail(s);
   if ((s = dalloc(ctx, &d.slot, nq * 4)) != AGILE_OK) return bail(s);
   if ((s = dalloc(ctx, &d.qp, (uint64_t)cfg.num_qp * sizeof(qp_t))) != AGILE_OK) return bail(s);
-  if ((s = dalloc(ctx, &d.next_tok, 128)) != AGILE_OK) return bail(s);
+  if ((s = dalloc(ctx, &d.next_tok, 128 * AGILE_MAX_DEVICES)) != AGILE_OK) return bail(s);
+  uint64_t* dev_tab = nullptr;
+  if ((s = dalloc(ctx, &dev_tab, 8 * AGILE_MAX_DEVICES)) != AGILE_OK) return bail(s);
+  d.dev_image = dev_tab;
+  d.n_dev = 1;
   if ((s = dalloc(ctx, &d.cnt, (uint64_t)C_COUNT * CSTRIDE * 8)) != AGILE_OK) return bail(s);
   ctx->defer_cap = 1ull << 20;  // bags per launch the resident-hit pass can take (4 MiB list)
   if ((s = dalloc(ctx, &ctx->defer_list, ctx->defer_cap * 4)) != AGILE_OK) return bail(s);
@@ -2045,7 +2222,7 @@ agile_status agile_init(const agile_config* cfg_in, agile_ctx* out) {
   if (hipMemset(d.meta, 0, lines * 8) != hipSuccess || hipMemset(d.hand, 0, (uint64_t)d.num_sets * 4) != hipSuccess ||
       hipMemset(d.set_lock, 0, (uint64_t)d.num_sets * 4) != hipSuccess ||
       hipMemset(d.sq, 0, nq * sizeof(sqe_t)) != hipSuccess || hipMemset(d.cq, 0, nq * sizeof(cqe_t)) != hipSuccess ||
-      hipMemset(d.qp, 0, (uint64_t)cfg.num_qp * sizeof(qp_t)) != hipSuccess || hipMemset(d.next_tok, 0, 128) != hipSuccess ||
+      hipMemset(d.qp, 0, (uint64_t)cfg.num_qp * sizeof(qp_t)) != hipSuccess || hipMemset(d.next_tok, 0, 128 * AGILE_MAX_DEVICES) != hipSuccess ||
       hipMemset(d.cnt, 0, (uint64_t)C_COUNT * CSTRIDE * 8) != hipSuccess || hipMemset(d.err, 0, 128) != hipSuccess ||
       hipMemset(d.err_info, 0, 128) != hipSuccess || hipMemset(d.abort_dev, 0, 128) != hipSuccess)
     return bail(AGILE_EHIP);
@@ -2090,31 +2267,73 @@ agile_status agile_host_free(void* p) {
 
 agile_status agile_open_store(agile_ctx ctx, void* host_image, uint64_t bytes, uint32_t block_bytes,
                               uint32_t flags, agile_store* out) {
+  void* const images[1] = {host_image};
+  return agile_open_store_striped(ctx, images, 1, bytes, block_bytes, flags, out);
+}
+
+agile_status agile_open_store_striped(agile_ctx ctx, void* const* host_images, uint32_t n, uint64_t bytes_each,
+                                      uint32_t block_bytes, uint32_t flags, agile_store* out) {
   agile_status s = check_usable(ctx);
   if (s) return s;
-  if (!host_image || !out || block_bytes != 4096 || bytes == 0 || bytes % block_bytes)
-    return fail(ctx, AGILE_EINVAL, "open_store: image must be non-null, block_bytes 4096, bytes a multiple of it");
+  if (!host_images || !out || block_bytes != 4096 || bytes_each == 0 || bytes_each % block_bytes)
+    return fail(ctx, AGILE_EINVAL, "open_store: images must be non-null, block_bytes 4096, bytes a multiple of it");
+  if (n == 0 || n > AGILE_MAX_DEVICES) return fail(ctx, AGILE_EINVAL, "open_store: 1..AGILE_MAX_DEVICES devices");
   (void)flags;
   if (ctx->store) return fail(ctx, AGILE_ESTATE, "open_store: a store is already open on this context");
-  if ((bytes / 4096) / ctx->d.blocks_per_line >= 0xFFFFFFFFull)
+  const uint64_t line_bytes = 1ull << ctx->d.line_shift;
+  if (n > 1 && (bytes_each % line_bytes || ctx->d.num_qp % n))
+    return fail(ctx, AGILE_EINVAL,
+                "open_store: with several devices each holds whole lines and the queue pairs divide evenly");
+  const uint64_t bytes = bytes_each * n;
+  if ((bytes / 4096 + ctx->d.blocks_per_line - 1) / ctx->d.blocks_per_line >= 0xFFFFFFFFull)
     return fail(ctx, AGILE_EINVAL, "open_store: store too large for 32-bit line ids");
-  hipPointerAttribute_t attr;
-  memset(&attr, 0, sizeof(attr));
-  if (hipPointerGetAttributes(&attr, host_image) != hipSuccess || attr.type != hipMemoryTypeHost ||
-      attr.devicePointer == nullptr) {
-    (void)hipGetLastError();
-    return fail(ctx, AGILE_EINVAL, "open_store: image is not pinned, device-mapped host memory");
-  }
-  uint8_t* dev = (uint8_t*)attr.devicePointer + ((uint8_t*)host_image - (uint8_t*)attr.hostPointer);
   agile_store st = new agile_store_s();
-  st->host = host_image;
-  st->dev = dev;
+  for (uint32_t d = 0; d < n; ++d) {
+    hipPointerAttribute_t attr;
+    memset(&attr, 0, sizeof(attr));
+    if (!host_images[d] || hipPointerGetAttributes(&attr, host_images[d]) != hipSuccess ||
+        attr.type != hipMemoryTypeHost || attr.devicePointer == nullptr) {
+      (void)hipGetLastError();
+      delete st;
+      return fail(ctx, AGILE_EINVAL, "open_store: an image is not pinned, device-mapped host memory");
+    }
+    st->host[d] = host_images[d];
+    st->dev[d] = (uint8_t*)attr.devicePointer + ((uint8_t*)host_images[d] - (uint8_t*)attr.hostPointer);
+  }
+  st->n_dev = n;
   st->bytes = bytes;
   st->blocks = bytes / 4096;
+  st->dev_bytes = bytes_each;
   ctx->store = st;
-  bind_store(ctx);
+  if ((s = bind_store(ctx)) != AGILE_OK) {
+    ctx->store = nullptr;
+    delete st;
+    (void)bind_store(ctx);
+    return s;
+  }
   *out = st;
   return AGILE_OK;
+}
+
+agile_status agile_write(agile_ctx ctx, agile_store store, const uint64_t* d_lines, uint32_t n, const void* d_src,
+                         void* stream) {
+  agile_status s = check_usable(ctx);
+  if (s) return s;
+  if (store != ctx->store) return fail(ctx, AGILE_EINVAL, "write: store is not open on this context");
+  if (n == 0) return AGILE_OK;
+  if (!d_lines || !d_src) return fail(ctx, AGILE_EINVAL, "write: null pointer");
+  if (store->bytes % (1ull << ctx->d.line_shift))
+    return fail(ctx, AGILE_EINVAL, "write: the store must hold whole lines");
+  hipStream_t hs = (hipStream_t)stream;
+  // a wave pins at most one chunk (64 lines) at a time
+  const uint64_t by_cache = std::max<uint64_t>(1, ctx->d.num_lines / 64);
+  uint32_t uw = (uint32_t)std::min<uint64_t>({(n + 63) / 64, (uint64_t)user_wave_cap(ctx, KIND_WRITE), by_cache});
+  uw = (uw + WPB - 1) / WPB * WPB;
+  launch_t li = make_launch(ctx, uw, true);
+  hipLaunchKernelGGL(k_write_lines, dim3(li.service_blocks + uw / WPB), dim3(WG),
+                     lds_of(ctx, (const void*)k_write_lines), hs, ctx->d, li, d_lines, n, (const uint8_t*)d_src);
+  HIPCHK(ctx, hipGetLastError());
+  return sync_stream(ctx, hs);
 }
 
 agile_status agile_sync(agile_ctx ctx, void* stream) {
@@ -2387,6 +2606,47 @@ agile_status agile_embbag_forward(agile_ctx ctx, agile_store store, const agile_
                                   void* stream) {
   if (B == 0) return check_usable(ctx);
   return embbag_launch(ctx, store, tb, d_idx, d_off, B, 0, K, mode, d_out, stream, false);
+}
+
+agile_status agile_embbag_forward_resident(agile_ctx ctx, const void* d_image, uint64_t image_bytes,
+                                           const agile_tables* tb, const int64_t* d_idx, const int64_t* d_off,
+                                           uint64_t B, uint32_t K, float* d_out, void* stream) {
+  agile_status s = check_usable(ctx);
+  if (s) return s;
+  if (!tb || !d_image || !d_out || !d_off) return fail(ctx, AGILE_EINVAL, "resident forward: null pointer");
+  if (tb->dim == 0 || tb->dim > 256 || tb->num_tables == 0 || tb->rows == 0)
+    return fail(ctx, AGILE_EINVAL, "resident forward: dim must be 1..256, tables and rows non-zero");
+  const uint64_t row_bytes = (uint64_t)tb->dim * 4;
+  if (4096 % row_bytes || tb->base_offset % row_bytes)
+    return fail(ctx, AGILE_EINVAL, "resident forward: row bytes must divide 4096 and align base_offset");
+  const uint64_t table_bytes = tb->rows * row_bytes;
+  if (tb->base_offset + table_bytes * tb->num_tables > image_bytes)
+    return fail(ctx, AGILE_EINVAL, "resident forward: tables exceed the image");
+  embbag_args a{};
+  a.idx = d_idx;
+  a.off = d_off;
+  a.out = d_out;
+  a.nbags = B * tb->num_tables;
+  a.rows = tb->rows;
+  a.base_off = tb->base_offset;
+  a.table_bytes = table_bytes;
+  a.T = tb->num_tables;
+  a.dim = tb->dim;
+  a.row_bytes = (uint32_t)row_bytes;
+  a.K = K;
+  if (a.nbags == 0) return AGILE_OK;
+  if ((a.nbags + RES_WAVES - 1) / RES_WAVES >= (1ull << 31)) return fail(ctx, AGILE_EINVAL, "resident forward: too many bags");
+  const dim3 grid((uint32_t)((a.nbags + RES_WAVES - 1) / RES_WAVES)), blk(64 * RES_WAVES);
+  const hipStream_t hs = (hipStream_t)stream;
+  const uint8_t* img = (const uint8_t*)d_image;
+  if (tb->dim <= 64)
+    hipLaunchKernelGGL(k_embbag_resident<1>, grid, blk, 0, hs, ctx->d, img, a);
+  else if (tb->dim <= 128)
+    hipLaunchKernelGGL(k_embbag_resident<2>, grid, blk, 0, hs, ctx->d, img, a);
+  else
+    hipLaunchKernelGGL(k_embbag_resident<4>, grid, blk, 0, hs, ctx->d, img, a);
+  HIPCHK(ctx, hipGetLastError());
+  return AGILE_OK;
 }
 
 static agile_status ensure_scratch(agile_ctx ctx, size_t need, hipStream_t hs) {

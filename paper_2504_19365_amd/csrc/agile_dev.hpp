@@ -179,9 +179,15 @@ struct dev_ctx {
   uint32_t* slot;
   qp_t* qp;
   uint32_t num_qp, depth, depth_shift, _q0;
-  // store (4 KiB blocks)
-  uint8_t* image;
-  uint64_t store_blocks;
+  // store (4 KiB blocks), striped over n_dev emulated devices one cache line at a time
+  // (Sec. 4.3's interleaving, request i to device i mod n): line l lives on device
+  // l mod n_dev as that device's line l / n_dev.  Queue pair q belongs to device
+  // q mod n_dev, and so does its token bucket.
+  uint8_t* image;               // device 0's image (the only one when n_dev == 1)
+  const uint64_t* dev_image;    // [n_dev] base address of each device's image
+  uint64_t store_blocks;        // blocks of the whole (logical) store
+  uint64_t dev_blocks;          // blocks of each device
+  uint32_t n_dev, _s0;
   // emulator
   uint64_t lat_ticks;
   uint64_t tok_fp;  // ticks per command in TOK_FRAC-bit fixed point; 0 = no cap
@@ -404,6 +410,30 @@ __device__ __forceinline__ bool submit(const dev_ctx& c, uint32_t q, bool want, 
   return true;
 }
 
+// Submits one command per lane with `want` for a whole cache line of the store (a
+// line at a device's end may be short), each to the queue pair of the line's device in
+// the wave's group of queue pairs ((q / n_dev) * n_dev + device): one wave-wide
+// submission per device present among the lanes.
+__device__ __forceinline__ bool submit_line(const dev_ctx& c, uint32_t q, bool want, uint32_t opc,
+                                            uint32_t line_idx, uint32_t line_id) {
+  uint64_t todo = ballot(want);
+  if (!todo) return true;
+  const bool one = c.n_dev == 1;
+  const uint32_t d = one ? 0u : line_id % c.n_dev;
+  const uint32_t bpl = c.blocks_per_line;
+  const uint64_t slba = (uint64_t)(one ? line_id : line_id / c.n_dev) * bpl;
+  uint32_t nblk = bpl;
+  if (want && slba + nblk > c.dev_blocks) nblk = (uint32_t)(c.dev_blocks - slba);
+  const uint32_t qg = one ? q : q - q % c.n_dev;
+  do {
+    const uint32_t dd = rdlane(d, ffs64(todo));
+    const bool mine = want && d == dd;
+    if (!submit(c, qg + dd, mine, opc, line_idx, slba, nblk)) return false;
+    todo &= ~ballot(mine);
+  } while (todo);
+  return true;
+}
+
 // ------------------------------------------------------------------ service wavefronts
 __device__ __forceinline__ bool service_should_exit(const dev_ctx& c, const launch_t& li) {
   if (aborted(c)) return true;
@@ -459,7 +489,7 @@ __device__ __forceinline__ void copy_blocks(uint8_t* const (&dst)[4], const uint
   }
 }
 __device__ __forceinline__ void copy_cmds(const dev_ctx& c, uint64_t ready, uint32_t p_opc, uint32_t p_nblk,
-                          uint32_t p_status, uint64_t p_slba, uint64_t p_prp) {
+                          uint32_t p_status, uint64_t p_slba, uint64_t p_prp, uint32_t p_q) {
   // the block pointers are written at constant indices only, so they stay in registers
   uint8_t* dst[4] = {nullptr, nullptr, nullptr, nullptr};
   const uint8_t* src[4] = {nullptr, nullptr, nullptr, nullptr};
@@ -470,7 +500,9 @@ __device__ __forceinline__ void copy_cmds(const dev_ctx& c, uint64_t ready, uint
     const uint32_t nblk = rdlane(p_nblk, l);
     const bool rd = rdlane(p_opc, l) == OPC_READ;
     uint8_t* hbm = (uint8_t*)(uintptr_t)rdlane64(p_prp, l);
-    uint8_t* img = c.image + (rdlane64(p_slba, l) << 12);
+    uint8_t* base = c.image;
+    if (c.n_dev > 1) base = (uint8_t*)(uintptr_t)c.dev_image[rdlane(p_q, l) % c.n_dev];
+    uint8_t* img = base + (rdlane64(p_slba, l) << 12);
     for (uint32_t b = 0; b < nblk; ++b) {
       const uint64_t o = (uint64_t)b << 12;
 #pragma unroll
@@ -547,15 +579,16 @@ __device__ __forceinline__ void controller(const dev_ctx& c, const launch_t& li,
       // first one, relative to t
       uint64_t tok0 = 0;
       if (c.tok_fp) {
+        uint64_t* bucket = c.next_tok + (size_t)(q % c.n_dev) * 16;  // the device's own
         if (lane() == 0) {
           const uint64_t tn = t << TOK_FRAC;  // wraps; only differences are used
-          uint64_t old = ld_rlx(c.next_tok);
+          uint64_t old = ld_rlx(bucket);
           for (;;) {
             // a lead beyond what every queued command could account for is a bucket
             // that went idle (or was never used): it restarts at now
             const uint64_t lead = old - tn;
             const uint64_t first = ((int64_t)lead > 0 && lead <= c.tok_max) ? old : tn;
-            if (cas(c.next_tok, old, first + (uint64_t)k * c.tok_fp)) {
+            if (cas(bucket, old, first + (uint64_t)k * c.tok_fp)) {
               tok0 = first - tn;
               if (profiling(c)) {
                 count(c, P_TOK_LEAD, tok0 >> TOK_FRAC);
@@ -588,7 +621,7 @@ __device__ __forceinline__ void controller(const dev_ctx& c, const launch_t& li,
             p_prp < lo || p_prp + ((uint64_t)p_nblk << 12) > hi || p_nblk > c.blocks_per_line) {
           raise_error(c, E_PROTO, ((uint64_t)q << 32) | s);
           p_status = 0x4;  // invalid field
-        } else if (p_slba + p_nblk > c.store_blocks) {
+        } else if (p_slba + p_nblk > c.dev_blocks) {
           p_status = 0x80;  // LBA out of range
         }
         uint64_t dl = t + c.lat_ticks;
@@ -619,7 +652,7 @@ __device__ __forceinline__ void controller(const dev_ctx& c, const launch_t& li,
         fence_acq_sys();
         img_epoch = ep;
       }
-      copy_cmds(c, ready, p_opc, p_nblk, p_status, p_slba, p_prp);
+      copy_cmds(c, ready, p_opc, p_nblk, p_status, p_slba, p_prp, p_q);
       if (ballot(((ready >> lane()) & 1ull) && p_opc == OPC_WRITE && !p_status)) {
         fence_rel_sys();
         if (lane() == 0) add_rel(counter(c, C_IMG_EPOCH), 1ull);
@@ -1253,7 +1286,7 @@ __device__ __forceinline__ void dedup(chunk_t& ch, bool part) {
 // (embedding rows); readers whose lanes share lines (consecutive CSR entries) coalesce
 // first and probe once per distinct line.
 __device__ __forceinline__ bool chunk_issue(const dev_ctx& c, chunk_t& ch, uint32_t q, bool count_stats,
-                            uint32_t pin_mode = PIN_LINE, bool probe_first = true) {
+                            uint32_t pin_mode = PIN_LINE, bool probe_first = true, bool fetch = true) {
   const uint64_t t_issue = now();
   uint32_t st = A_NONE, idx = 0, gen = 0;
   bool part = ch.act;  // lanes that go through dedup and the acquire loop
@@ -1294,23 +1327,17 @@ __device__ __forceinline__ bool chunk_issue(const dev_ctx& c, chunk_t& ch, uint3
           retake = (int)a.idx;
         } else {
           pending = false;
-          rd = a.res == A_MISS;
+          rd = a.res == A_MISS && fetch;
         }
       }
     }
-    // one wave-wide submission per round; READs and WRITEs may share the queue pair
-    const uint32_t blk_per_line = c.blocks_per_line;
-    uint64_t slba = 0;
-    uint32_t nblk = blk_per_line;
-    if (rd || wb) {
-      uint32_t lid = ch.line_id;
-      if (wb) lid = m_tag(ld_rlx(c.meta + idx));
-      slba = (uint64_t)lid * blk_per_line;
-      if (slba + nblk > c.store_blocks) nblk = (uint32_t)(c.store_blocks - slba);
-    }
+    // one wave-wide submission per round and device; READs and WRITEs may share the
+    // queue pair
+    uint32_t lid = ch.line_id;
+    if (wb) lid = m_tag(ld_rlx(c.meta + idx));
     const uint64_t ts = now();
-    if (!submit(c, q, rd, OPC_READ, idx, slba, nblk)) return false;
-    if (!submit(c, q, wb, OPC_WRITE, idx, slba, nblk)) return false;
+    if (!submit_line(c, q, rd, OPC_READ, idx, lid)) return false;
+    if (!submit_line(c, q, wb, OPC_WRITE, idx, lid)) return false;
     wtick(c, WS_T_SUBMIT, ts);
     if (ballot(wb)) {
       const uint64_t nwb = __popcll(ballot(wb));

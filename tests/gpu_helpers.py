@@ -26,6 +26,23 @@ def table_store(rows: int, dim: int, seeds, extra_bytes: int = 0):
     return buf
 
 
+def striped_arrays(logical, n: int, unit_bytes: int):
+    """Device images of a logical image laid out unit by unit over n devices (unit u of
+    the logical image is unit u // n of device u % n), as host arrays."""
+    x = np.ascontiguousarray(logical).view(np.uint8).reshape(-1, n, unit_bytes)
+    return [np.ascontiguousarray(x[:, d, :]).ravel() for d in range(n)]
+
+
+def striped_store(logical, n: int, unit_bytes: int):
+    """Pinned device images (one PinnedBuffer each) of a logical image."""
+    bufs = []
+    for a in striped_arrays(logical, n, unit_bytes):
+        b = agile.PinnedBuffer(a.size)
+        b.array[:] = a
+        bufs.append(b)
+    return bufs
+
+
 def cuda(a, dtype=None):
     import torch
     t = torch.from_numpy(np.ascontiguousarray(a))
