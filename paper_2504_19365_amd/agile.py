@@ -506,8 +506,7 @@ class Context:
                      "t_u_issue", "t_u_submit", "t_u_wait", "t_u_consume", "tok_lead",
                      "tok_n", "t_u_desc", "t_u_life", "svc_exit", "img_epoch", "work_p1",
                      "work_p2", "work_p3", "work_p4", "work_p5", "work_p6", "work_p7", "defer",
-                     "hwork", "hwork_p1", "hwork_p2", "hwork_p3", "hwork_p4", "hwork_p5",
-                     "hwork_p6", "hwork_p7")
+                     "hit_total", "deflen")
 
     def debug_counters(self) -> dict:
         n = len(self.COUNTER_NAMES)

@@ -194,6 +194,9 @@ __device__ __forceinline__ void hold_next(const dev_ctx& c, const launch_t& li, 
     ss.j0 = a.off[bag];
     ss.j1 = a.off[bag + 1];
   }
+  // a deferred bag: the resident-hit pass counted it in its launch total but did not
+  // serve it
+  if (a.list && lane() == 0) wcount(WS_DEFLEN, (uint64_t)(ss.j1 - ss.j0));
 }
 
 // Next chunk after `d` (or the first one when !d.valid): continues the bag or takes the
@@ -661,128 +664,98 @@ __device__ __forceinline__ void hit_use(const embbag_args& a, int64_t j, uint32_
   }
 }
 
+// One wavefront per bag, HIT_WAVES to a workgroup, so the hardware's dispatch of
+// workgroups balances bags of uneven length and no wave waits on a work counter.  Each
+// wave has its own 8 KiB LDS area for the staged probe.  Four wavefronts per SIMD (up to
+// 128 registers): at five the loop spills, and the spills cost more than the fifth wave
+// gains (measured on the DLRM-style hit replay: 0.144 ms against 0.100 ms).
+constexpr uint32_t HIT_WAVES = 4;
+struct alignas(16) hit_lds_t {
+  uint8_t b[HIT_WAVES][PROBE_LDS];
+};
 template <int VPL>
-__device__ __forceinline__ bool hit_wave(const dev_ctx& c, const embbag_args& a, uint32_t uw, uint32_t* list) {
-  bool appended = false;
-  const uint32_t A = a.active_waves;
-  const uint64_t nb = a.nbags;
+__device__ __forceinline__ bool hit_bag(const dev_ctx& c, const embbag_args& a, uint64_t g, uint8_t* lds) {
   const uint32_t d0 = lane() * VPL;
   const bool mine = d0 < a.dim;
   constexpr uint32_t R = rows_per_round<VPL>();
   const uint64_t lmask = (1ull << c.line_shift) - 1;
-  // bags [0, 2A) are dealt statically (wave u takes u and u + A); the rest one at a time
-  // from P = min(8, A) partition counters (bag 2A + v*P + p in partition p), a wave
-  // starting at partition u mod P and moving on once it is used up
-  const uint32_t parts = A < WORK_PARTS ? A : WORK_PARTS;
-  uint32_t tried = 0;
-  for (uint32_t round = 0;; ++round) {
-    uint64_t g;
-    if (round < 2) {
-      g = (uint64_t)uw + (uint64_t)round * A;
-      if (g >= nb) continue;
-    } else {
-      if (nb <= 2ull * A || tried >= parts) break;
-      const uint32_t p = (uw + tried) % parts;
-      uint64_t v = 0;
-      if (lane() == 0) v = add_rlx(counter(c, C_HWORK + p), 1ull);
-      g = 2ull * A + rdlane64(v, 0) * parts + p;
-      if (g >= nb) {
-        ++tried;
-        continue;
-      }
-    }
-    int64_t j0, j1;
-    if (a.gather) {
-      j0 = (int64_t)g * 64;
-      j1 = ((int64_t)a.n < j0 + 64) ? (int64_t)a.n : j0 + 64;
-    } else {
-      j0 = a.off[g];
-      j1 = a.off[g + 1];
-    }
-    const uint32_t t = a.gather ? 0u : (uint32_t)(g % a.T);
-    float acc[VPL];
-#pragma unroll
-    for (int v = 0; v < VPL; ++v) acc[v] = 0.0f;
-    bool deferred = false;
-    for (int64_t j = j0; j < j1 && !deferred; j += 64) {
-      const uint32_t n = (uint32_t)((j1 - j) < 64 ? (j1 - j) : 64);
-      chunk_t ch;
-      ch.act = lane() < n;
-      ch.pinned = false;
-      ch.line_id = 0;
-      ch.off = 0;
-      if (ch.act) {
-        const int64_t row = a.idx[j + lane()];
-        const uint64_t byte = a.base_off + (uint64_t)t * a.table_bytes + (uint64_t)row * a.row_bytes;
-        ch.line_id = (uint32_t)(byte >> c.line_shift);
-        ch.off = (uint32_t)(byte & lmask);
-      }
-      const uint32_t base = ch.act ? set_of(c, ch.line_id) * c.assoc : 0u;
-      uint64_t m = 0;
-      int w = -1;
-      if (probe_staged_ok(c.assoc))
-        w = probe_staged(c, ch.act, base, ch.line_id, m);
-      else if (ch.act)
-        w = probe_set(c, base, ch.line_id, m);
-      const bool hit = ch.act && w >= 0 && m_valid_data(m_state(m));
-      if (ballot(ch.act && !hit)) {
-        deferred = true;
-        break;
-      }
-      ch.idx = base + (uint32_t)(w < 0 ? 0 : w);
-      ch.gen = m_gen(m);
-      ch.st = A_HIT;
-      if (ch.act && !(m & M_REF)) or_rlx(c.meta + ch.idx, M_REF);
-      // each lane's row address, so a row costs two lane reads and one load
-      const uint64_t raddr = (uint64_t)(uintptr_t)line_ptr(c, ch.idx) + ch.off;
-      // the rows in rounds of R, two rounds in flight, added as they arrive
-      float va[R][VPL], vb[R][VPL];
-      hit_load<VPL>(raddr, 0, n < R ? n : R, d0, mine, va);
-      for (uint32_t r = 0; r < n;) {
-        uint32_t gcur = (n - r) < R ? (n - r) : R;
-        uint32_t rn = r + gcur;
-        uint32_t gn = rn < n ? ((n - rn) < R ? (n - rn) : R) : 0;
-        if (gn) hit_load<VPL>(raddr, rn, gn, d0, mine, vb);
-        hit_use<VPL>(a, j + r, gcur, d0, mine, va, acc);
-        r = rn;
-        if (r >= n) break;
-        gcur = gn;
-        rn = r + gcur;
-        gn = rn < n ? ((n - rn) < R ? (n - rn) : R) : 0;
-        if (gn) hit_load<VPL>(raddr, rn, gn, d0, mine, va);
-        hit_use<VPL>(a, j + r, gcur, d0, mine, vb, acc);
-        r = rn;
-      }
-      // every row load of this wave has completed before the metadata is read again
-      __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
-      asm volatile("" ::: "memory");
-      const bool bad = ch.act && !line_still_valid(c, ch.idx, ch.line_id, ch.gen);
-      if (ballot(bad)) deferred = true;
-    }
-    if (deferred) {
-      if (lane() == 0) list[add_rlx(counter(c, C_DEFER), 1ull)] = (uint32_t)g;
-      appended = true;
-      continue;
-    }
-    if (!a.gather) write_bag<VPL>(c, a, (int64_t)g, acc);
-    if (lane() == 0) {
-      const uint64_t len = (uint64_t)(j1 - j0);
-      wcount(WS_REQUESTS, len);
-      wcount(WS_HITS, len);
-      wcount(WS_AUX1, len);
-    }
+  int64_t j0, j1;
+  if (a.gather) {
+    j0 = (int64_t)g * 64;
+    j1 = ((int64_t)a.n < j0 + 64) ? (int64_t)a.n : j0 + 64;
+  } else {
+    j0 = a.off[g];
+    j1 = a.off[g + 1];
   }
-  return appended;
+  const uint32_t t = a.gather ? 0u : (uint32_t)(g % a.T);
+  float acc[VPL];
+#pragma unroll
+  for (int v = 0; v < VPL; ++v) acc[v] = 0.0f;
+  for (int64_t j = j0; j < j1; j += 64) {
+    const uint32_t n = (uint32_t)((j1 - j) < 64 ? (j1 - j) : 64);
+    chunk_t ch;
+    ch.act = lane() < n;
+    ch.pinned = false;
+    ch.line_id = 0;
+    ch.off = 0;
+    if (ch.act) {
+      const int64_t row = a.idx[j + lane()];
+      const uint64_t byte = a.base_off + (uint64_t)t * a.table_bytes + (uint64_t)row * a.row_bytes;
+      ch.line_id = (uint32_t)(byte >> c.line_shift);
+      ch.off = (uint32_t)(byte & lmask);
+    }
+    const uint32_t base = ch.act ? set_of(c, ch.line_id) * c.assoc : 0u;
+    uint64_t m = 0;
+    int w = -1;
+    if (probe_staged_ok(c.assoc))
+      w = probe_staged(c, ch.act, base, ch.line_id, m, lds);
+    else if (ch.act)
+      w = probe_set(c, base, ch.line_id, m);
+    const bool hit = ch.act && w >= 0 && m_valid_data(m_state(m));
+    if (ballot(ch.act && !hit)) return false;
+    ch.idx = base + (uint32_t)(w < 0 ? 0 : w);
+    ch.gen = m_gen(m);
+    if (ch.act && !(m & M_REF)) or_rlx(c.meta + ch.idx, M_REF);
+    // each lane's row address, so a row costs two lane reads and one load
+    const uint64_t raddr = (uint64_t)(uintptr_t)line_ptr(c, ch.idx) + ch.off;
+    // the rows in rounds of R, two rounds in flight, added as they arrive
+    float va[R][VPL], vb[R][VPL];
+    hit_load<VPL>(raddr, 0, n < R ? n : R, d0, mine, va);
+    for (uint32_t r = 0; r < n;) {
+      uint32_t gcur = (n - r) < R ? (n - r) : R;
+      uint32_t rn = r + gcur;
+      uint32_t gn = rn < n ? ((n - rn) < R ? (n - rn) : R) : 0;
+      if (gn) hit_load<VPL>(raddr, rn, gn, d0, mine, vb);
+      hit_use<VPL>(a, j + r, gcur, d0, mine, va, acc);
+      r = rn;
+      if (r >= n) break;
+      gcur = gn;
+      rn = r + gcur;
+      gn = rn < n ? ((n - rn) < R ? (n - rn) : R) : 0;
+      if (gn) hit_load<VPL>(raddr, rn, gn, d0, mine, va);
+      hit_use<VPL>(a, j + r, gcur, d0, mine, vb, acc);
+      r = rn;
+    }
+    // every row load of this wave has completed before the metadata is read again
+    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
+    asm volatile("" ::: "memory");
+    const bool bad = ch.act && !line_still_valid(c, ch.idx, ch.line_id, ch.gen);
+    if (ballot(bad)) return false;
+  }
+  if (!a.gather) write_bag<VPL>(c, a, (int64_t)g, acc);
+  return true;
 }
 
-// The resident-hit pass as a kernel of its own: it carries no service wavefronts and none
-// of the I/O path's code, so its loop keeps to few registers.
+// The resident-hit pass: bag g = workgroup * HIT_WAVES + wave.  It carries no service
+// wavefronts and none of the I/O path's code; a bag it cannot serve goes to the
+// deferred list.
 template <int VPL>
-__global__ __launch_bounds__(WG) void k_embbag_hit(dev_ctx c, launch_t li, embbag_args a, uint32_t* list) {
-  user_wave_begin();
-  const uint32_t uw = blockIdx.x * WPB + threadIdx.x / 64;
-  if (uw < a.active_waves) hit_wave<VPL>(c, a, uw, list);
-  user_wave_done(c, li);
+__global__ __launch_bounds__(64 * HIT_WAVES, 4) void k_embbag_hit(dev_ctx c, embbag_args a, uint32_t* list) {
+  __shared__ hit_lds_t lds;
+  const uint64_t g = (uint64_t)blockIdx.x * HIT_WAVES + threadIdx.x / 64;
+  if (g >= a.nbags) return;
+  if (!hit_bag<VPL>(c, a, g, lds.b[threadIdx.x / 64]) && lane() == 0)
+    list[add_rlx(counter(c, C_DEFER), 1ull)] = (uint32_t)g;
 }
 
 // Embedding-bag forward over a copy of the tables resident in device memory: no cache,
@@ -859,6 +832,8 @@ __global__ __launch_bounds__(WG) void k_embbag(dev_ctx c, launch_t li, embbag_ar
   }
   user_wave_begin();
   const uint32_t uw = (blockIdx.x - li.service_blocks) * WPB + threadIdx.x / 64;
+  if (a.list && uw == 0 && lane() == 0)
+    add_rlx(counter(c, C_HIT_TOTAL), a.gather ? a.n : (uint64_t)(a.off[a.nbags] - a.off[0]));
   if (c.flags & AGILE_F_SERIALIZED) {
     if (uw == 0) embbag_serial<VPL>(c, li, a);
   } else if (uw < a.active_waves) {
@@ -1872,7 +1847,6 @@ struct agile_ctx_s {
   void* noalloc_scratch = nullptr;  // device address of `scratch` on this context's device
   uint32_t* defer_list = nullptr;   // bags the resident-hit pass leaves to the I/O pass
   uint64_t defer_cap = 0;
-  int hit_occ[3] = {0, 0, 0};       // resident workgroups per CU of k_embbag_hit<1, 2, 4>
 };
 
 namespace {
@@ -2444,8 +2418,11 @@ agile_status agile_get_stats(agile_ctx ctx, agile_stats* out, int reset) {
   HIPCHK(ctx, hipDeviceSynchronize());
   HIPCHK(ctx, hipMemcpy(c.data(), ctx->d.cnt, c.size() * 8, hipMemcpyDeviceToHost));
   auto g = [&](uint32_t i) { return c[(size_t)i * CSTRIDE]; };
-  out->requests = g(C_REQUESTS);
-  out->hits = g(C_HITS);
+  // the resident-hit pass counts nothing itself: its requests and hits are the lookups
+  // of its launches less those of the bags it deferred
+  const uint64_t hit_pass = g(C_HIT_TOTAL) - g(C_DEFLEN);
+  out->requests = g(C_REQUESTS) + hit_pass;
+  out->hits = g(C_HITS) + hit_pass;
   out->misses = g(C_MISSES);
   out->read_cmds = g(C_READS);
   out->write_cmds = g(C_WRITES);
@@ -2457,13 +2434,12 @@ agile_status agile_get_stats(agile_ctx ctx, agile_stats* out, int reset) {
   out->cq_entries = g(C_CQ_ENTRIES);
   out->submitted = g(C_SUBMITTED);
   out->completed = g(C_COMPLETED);
-  out->consumed = g(C_AUX1);
+  out->consumed = g(C_AUX1) + hit_pass;
   out->rows_updated = g(C_WROWS);
   if (reset) {
     const uint32_t keep[] = {C_SUBMITTED, C_COMPLETED, C_USER_DONE, C_WORK, C_SVC_EXIT, C_IMG_EPOCH,
                              C_WORK_P1, C_WORK_P2, C_WORK_P3, C_WORK_P4, C_WORK_P5, C_WORK_P6, C_WORK_P7,
-                             C_DEFER, C_HWORK, C_HWORK_P1, C_HWORK_P2, C_HWORK_P3, C_HWORK_P4, C_HWORK_P5,
-                             C_HWORK_P6, C_HWORK_P7};
+                             C_DEFER};
     for (uint32_t i = 0; i < C_COUNT; ++i) {
       if (std::find(std::begin(keep), std::end(keep), i) != std::end(keep)) continue;
       HIPCHK(ctx, hipMemset(ctx->d.cnt + (size_t)i * CSTRIDE, 0, 8));
@@ -2554,32 +2530,19 @@ static agile_status embbag_launch(agile_ctx ctx, agile_store store, const agile_
   a.active_waves = active;
   const bool serial = (ctx->cfg.flags & AGILE_F_SERIALIZED) != 0;
   hipStream_t hs = (hipStream_t)stream;
-  // the resident-hit pass first (see hit_wave), when the deferred list can hold every
-  // bag; the I/O launch then runs only the bags it deferred.  Both launches are stream
-  // ordered; the I/O launch's last service wavefront clears the pass's counters, so the
-  // pair can be captured in a graph and replayed.
-  if (!serial && a.nbags <= ctx->defer_cap) {
-    const int vi = kind == KIND_EMBBAG1 ? 0 : (kind == KIND_EMBBAG2 ? 1 : 2);
-    int& occ = ctx->hit_occ[vi];
-    const void* hf = vi == 0 ? (const void*)k_embbag_hit<1> : (vi == 1 ? (const void*)k_embbag_hit<2>
-                                                                       : (const void*)k_embbag_hit<4>);
-    if (occ <= 0) {
-      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, hf, WG, 0) != hipSuccess || occ <= 0) occ = 1;
-      (void)hipGetLastError();
-    }
-    uint64_t hw = (uint64_t)occ * ctx->cu_count * WPB;
-    if (ctx->cfg.max_user_waves) hw = std::min<uint64_t>(hw, ctx->cfg.max_user_waves);
-    hw = std::max<uint64_t>(1, std::min<uint64_t>(hw, a.nbags));
-    embbag_args h = a;
-    h.active_waves = (uint32_t)hw;
-    const uint32_t huw = (uint32_t)((hw + WPB - 1) / WPB * WPB);
-    const launch_t lh = make_launch(ctx, huw, false);
-    if (vi == 0)
-      hipLaunchKernelGGL(k_embbag_hit<1>, dim3(huw / WPB), dim3(WG), 0, hs, ctx->d, lh, h, ctx->defer_list);
-    else if (vi == 1)
-      hipLaunchKernelGGL(k_embbag_hit<2>, dim3(huw / WPB), dim3(WG), 0, hs, ctx->d, lh, h, ctx->defer_list);
+  // the resident-hit pass first (see hit_bag), when the deferred list can hold every
+  // bag and the wave count is not capped (a cap applies to the I/O launch, which then
+  // runs every bag); the I/O launch then runs only the bags the pass deferred.  Both
+  // launches are stream ordered; the I/O launch's last service wavefront clears the
+  // deferred count, so the pair can be captured in a graph and replayed.
+  if (!serial && !ctx->cfg.max_user_waves && a.nbags <= ctx->defer_cap) {
+    const dim3 hg((uint32_t)((a.nbags + HIT_WAVES - 1) / HIT_WAVES)), hb(64 * HIT_WAVES);
+    if (kind == KIND_EMBBAG1)
+      hipLaunchKernelGGL(k_embbag_hit<1>, hg, hb, 0, hs, ctx->d, a, ctx->defer_list);
+    else if (kind == KIND_EMBBAG2)
+      hipLaunchKernelGGL(k_embbag_hit<2>, hg, hb, 0, hs, ctx->d, a, ctx->defer_list);
     else
-      hipLaunchKernelGGL(k_embbag_hit<4>, dim3(huw / WPB), dim3(WG), 0, hs, ctx->d, lh, h, ctx->defer_list);
+      hipLaunchKernelGGL(k_embbag_hit<4>, hg, hb, 0, hs, ctx->d, a, ctx->defer_list);
     HIPCHK(ctx, hipGetLastError());
     a.list = ctx->defer_list;
   }

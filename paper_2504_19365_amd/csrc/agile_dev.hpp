@@ -156,9 +156,12 @@ enum : uint32_t {
   P_U_LIFE, C_SVC_EXIT, C_IMG_EPOCH,
   // work counters of partitions 1..7 (partition 0 is C_WORK)
   C_WORK_P1, C_WORK_P2, C_WORK_P3, C_WORK_P4, C_WORK_P5, C_WORK_P6, C_WORK_P7,
-  // resident-hit pass: bags it deferred to the I/O pass, its work counters (partitions)
-  C_DEFER, C_HWORK, C_HWORK_P1, C_HWORK_P2, C_HWORK_P3, C_HWORK_P4, C_HWORK_P5, C_HWORK_P6,
-  C_HWORK_P7, C_COUNT
+  // resident-hit pass: bags it deferred to the I/O pass
+  C_DEFER,
+  // lookups of a launch whose bags went through the resident-hit pass, and of the bags
+  // it deferred: the pass's own requests and hits are their difference (it counts
+  // nothing itself; agile_get_stats adds the difference)
+  C_HIT_TOTAL, C_DEFLEN, C_COUNT
 };
 constexpr uint32_t CSTRIDE = 16;  // u64 per counter
 
@@ -904,9 +907,8 @@ __device__ __forceinline__ void run_service(const dev_ctx& c, const launch_t& li
     if (n == (uint64_t)li.n_ctrl + li.n_cq) {
       st_rlx(counter(c, C_USER_DONE), 0ull);
       for (uint32_t p = 0; p < WORK_PARTS; ++p) st_rlx(counter(c, work_counter(p)), 0ull);
-      // and those of the resident-hit pass that ran before this launch, if any
+      // and the deferred count of the resident-hit pass that ran before this launch
       st_rlx(counter(c, C_DEFER), 0ull);
-      for (uint32_t p = 0; p < WORK_PARTS; ++p) st_rlx(counter(c, C_HWORK + p), 0ull);
       st_rel(counter(c, C_SVC_EXIT), 0ull);
     }
   }
@@ -918,11 +920,12 @@ __device__ __forceinline__ void run_service(const dev_ctx& c, const launch_t& li
 // The user-wave stage timers (profile flag only) are kept the same way.
 enum : uint32_t {
   WS_REQUESTS = 0, WS_HITS, WS_MISSES, WS_EAGAIN, WS_AUX1, WS_WROWS,
-  WS_T_ISSUE, WS_T_SUBMIT, WS_T_WAIT, WS_T_CONSUME, WS_T_DESC, WS_T_LIFE, WS_COUNT
+  WS_T_ISSUE, WS_T_SUBMIT, WS_T_WAIT, WS_T_CONSUME, WS_T_DESC, WS_T_LIFE, WS_DEFLEN, WS_COUNT
 };
 __device__ __forceinline__ uint32_t ws_counter(uint32_t k) {
   constexpr uint32_t map[WS_COUNT] = {C_REQUESTS, C_HITS, C_MISSES, C_EAGAIN, C_AUX1, C_WROWS,
-                                      P_U_ISSUE, P_U_SUBMIT, P_U_WAIT, P_U_CONSUME, P_U_DESC, P_U_LIFE};
+                                      P_U_ISSUE, P_U_SUBMIT, P_U_WAIT, P_U_CONSUME, P_U_DESC, P_U_LIFE,
+                                      C_DEFLEN};
   return map[k];
 }
 struct wg_stats_t {
@@ -1066,7 +1069,7 @@ typedef __attribute__((address_space(3))) lds_u32x4_t lds_u32x4;
 // Lanes with `want` probe the set starting at line index `base` for `tag`; returns the
 // way (or -1) and the word seen.  Every lane of the wave must call it.
 __device__ __forceinline__ int probe_staged(const dev_ctx& c, bool want, uint32_t base, uint32_t tag,
-                                            uint64_t& seen) {
+                                            uint64_t& seen, uint8_t* lds) {
   const uint32_t A = c.assoc;
   const uint32_t P = A / 2;                            // 16-byte pairs per set
   const uint32_t pl = (uint32_t)__builtin_ctz(P);      // log2 P
@@ -1075,7 +1078,6 @@ __device__ __forceinline__ int probe_staged(const dev_ctx& c, bool want, uint32_
   const uint32_t rl = P >= 8 ? 0u : 3u - pl;           // log2 of the slots per rotation step
   const uint32_t me = lane();
   const uint64_t wm = ballot(want);
-  uint8_t* lds = probe_area();
   int way = -1;
   for (uint32_t s0 = 0; s0 < 64; s0 += per) {
     if (!((wm >> s0) & (per == 64 ? ~0ull : ((1ull << per) - 1ull)))) continue;
@@ -1297,7 +1299,7 @@ __device__ __forceinline__ bool chunk_issue(const dev_ctx& c, chunk_t& ch, uint3
     uint64_t m = 0;
     int w = -1;
     if (probe_staged_ok(c.assoc))
-      w = probe_staged(c, ch.act, base, ch.line_id, m);
+      w = probe_staged(c, ch.act, base, ch.line_id, m, probe_area());
     else if (ch.act)
       w = probe_set(c, base, ch.line_id, m);
     if (ch.act && w >= 0) {
