@@ -225,7 +225,9 @@ typedef struct agile_info {
 agile_status agile_get_info(agile_ctx ctx, agile_info* out);
 
 /* Caps the user wavefronts of later workload launches (0 = fill the GPU), e.g. to run
- * the thread-level overlap experiment of Sec. 4.2 on one 1024-thread group. */
+ * the thread-level overlap experiment of Sec. 4.2 on one 1024-thread group.  While a cap
+ * is set the embedding-bag and gather calls skip their resident-hit pass, so the cap
+ * holds for hits too. */
 agile_status agile_set_max_user_waves(agile_ctx ctx, uint32_t n);
 
 /* ---------------------------------------------------------------- workloads --------
@@ -257,9 +259,13 @@ agile_status agile_gather(agile_ctx ctx, agile_store store, const agile_tables* 
  * K iterations of v = fmaf(v, 0.999f, 0.001f) (a compute loop that sets the
  * computation-to-communication ratio, Sec. 4.2); fp32 accumulator from +0.0f.
  * mode is AGILE_MODE_SYNC or AGILE_MODE_ASYNC; both give bit-identical output.
- * Stream-ordered, one kernel launch, no host synchronisation, allocation or memset: the
- * call may be captured in a HIP graph and the graph replayed, once an eager call with a
- * table of the same dim has been made on the context (it caches an occupancy query). */
+ * Stream-ordered, two kernel launches: a resident-hit pass (one wavefront per bag, no
+ * queue traffic) serves the bags whose lines are all cached and defers the others to
+ * the I/O launch, which runs them through the cache and queues (with a wave cap from
+ * agile_set_max_user_waves only the I/O launch runs, for every bag).  No host
+ * synchronisation, allocation or memset: the call may be captured in a HIP graph and the
+ * graph replayed, once an eager call with a table of the same dim has been made on the
+ * context (it caches an occupancy query). */
 agile_status agile_embbag_forward(agile_ctx ctx, agile_store store, const agile_tables* tb,
                                   const int64_t* d_idx, const int64_t* d_off, uint64_t B,
                                   uint32_t K, uint32_t mode, float* d_out, void* stream);
@@ -408,9 +414,11 @@ typedef struct agile_serve_report {
  *
  * Requests travel through rings in pinned host memory that the session owns: the host
  * writes a request's bag descriptors and lookups into the next free slots, then
- * publishes the new count of bags with a release store; the kernel writes each bag's
- * output into the bag's ring slot and raises the request's done flag (system scope)
- * after its last bag.  Slots are reused in submission order once requests are polled.
+ * publishes the new count of bags with a release store; one service wavefront of the
+ * kernel copies each published batch into HBM copies of the rings before the other
+ * wavefronts see it; the kernel writes each bag's output into the bag's ring slot (host
+ * memory) and raises the request's done flag (system scope) after its last bag.  Slots
+ * are reused in submission order once requests are polled.
  *
  * tb, K, mode: as agile_embbag_forward (dim <= 256, 4096 % (4*dim) == 0).
  * opts: admission budgets and the wave count (NULL = defaults, see agile_serve_opts).

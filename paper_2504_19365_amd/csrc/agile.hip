@@ -41,8 +41,9 @@ struct embbag_args {
   // continuous batching (serve != 0): an unbounded stream of bags from requests that the
   // host publishes over time, held in rings: bag b in slot b & bag_mask, lookup j (a
   // position in the stream of lookups) in slot j & look_mask, request r in slot
-  // r & req_mask.  idx and out are rings too.  The ring arrays live in pinned host
-  // memory, written by the host before it publishes.
+  // r & req_mask.  idx and out are rings too.  The waves read HBM copies of the host's
+  // rings, which the session's staging wave fills before it publishes; out and done
+  // live in pinned host memory.
   const uint64_t* bag_j0;     // lookups [bag_j0, bag_j1) of the bag
   const uint64_t* bag_j1;
   const uint64_t* bag_req;    // request of the bag
@@ -119,8 +120,8 @@ __device__ __forceinline__ void write_bag(const dev_ctx& c, const embbag_args& a
     // the host may hand the slot to a later request)
     fence_rel_sys();
     if (lane() == 0) {
-      const uint64_t rs = ring_ld(a.bag_req + slot) & a.req_mask;
-      const uint32_t nb = ring_ld(a.req_nbags + rs);
+      const uint64_t rs = a.bag_req[slot] & a.req_mask;
+      const uint32_t nb = a.req_nbags[rs];
       const uint32_t k = add_rlx(a.req_cnt + rs, 1u) + 1;
       if (k == nb) {
         st_rlx(a.req_cnt + rs, 0u);
@@ -234,8 +235,8 @@ __device__ __forceinline__ desc_t next_desc(const dev_ctx& c, const launch_t& li
           fence_acq();
         }
         const uint64_t slot = (uint64_t)bag & a.bag_mask;
-        j0 = (int64_t)ring_ld(a.bag_j0 + slot);
-        j1 = (int64_t)ring_ld(a.bag_j1 + slot);
+        j0 = (int64_t)a.bag_j0[slot];
+        j1 = (int64_t)a.bag_j1[slot];
       }
       // hold the next bag now, except near the end of the work: a held bag cannot go to
       // a wave that runs out, so the last bags are taken only when needed
@@ -268,12 +269,12 @@ __device__ __forceinline__ void make_chunk(const dev_ctx& c, const embbag_args& 
   ch.st = A_NONE;
   if (ch.act) {
     const uint64_t jl = (uint64_t)(d.j + lane());
-    const int64_t row = a.serve ? ring_ld(a.idx + (jl & a.look_mask)) : a.idx[jl];
+    const int64_t row = a.idx[a.serve ? (jl & a.look_mask) : jl];
     uint64_t byte;
     if (a.gather) {
       byte = a.base_off + (uint64_t)row * a.row_bytes;
     } else {
-      const uint32_t t = a.serve ? ring_ld(a.bag_tab + ((uint64_t)d.g & a.bag_mask)) : (uint32_t)(d.g % a.T);
+      const uint32_t t = a.serve ? a.bag_tab[(uint64_t)d.g & a.bag_mask] : (uint32_t)(d.g % a.T);
       byte = a.base_off + (uint64_t)t * a.table_bytes + (uint64_t)row * a.row_bytes;
     }
     ch.line_id = (uint32_t)(byte >> c.line_shift);
@@ -664,12 +665,15 @@ __device__ __forceinline__ void hit_use(const embbag_args& a, int64_t j, uint32_
   }
 }
 
-// One wavefront per bag, HIT_WAVES to a workgroup, so the hardware's dispatch of
-// workgroups balances bags of uneven length and no wave waits on a work counter.  Each
-// wave has its own 8 KiB LDS area for the staged probe.  Four wavefronts per SIMD (up to
-// 128 registers): at five the loop spills, and the spills cost more than the fifth wave
-// gains (measured on the DLRM-style hit replay: 0.144 ms against 0.100 ms).
-constexpr uint32_t HIT_WAVES = 4;
+// One wavefront per bag and per workgroup, so the hardware's dispatch of workgroups
+// balances bags of uneven length, no wave waits on a work counter, and a short bag's
+// slot is free as soon as the bag is done (with 4 or 2 bags to a workgroup the slot
+// waits for the workgroup's longest bag: the DLRM-style hit replay took 0.100 or
+// 0.090 ms against 0.087 ms, and 2.74 or 2.19 ms against 1.91 ms at K = 256).  Each wave
+// has its own 8 KiB LDS area for the staged probe.  Four wavefronts per SIMD (up to 128
+// registers): at five the loop spills, and the spills cost more than the fifth wave
+// gains (0.144 ms against 0.100 ms, 4 bags to a workgroup).
+constexpr uint32_t HIT_WAVES = 1;
 struct alignas(16) hit_lds_t {
   uint8_t b[HIT_WAVES][PROBE_LDS];
 };
@@ -843,22 +847,59 @@ __global__ __launch_bounds__(WG) void k_embbag(dev_ctx c, launch_t li, embbag_ar
 }
 
 // Serving kernel: the embedding-bag wave loop over a stream of requests.  One extra
-// service wavefront mirrors the host's count of published requests, its stop flag and
-// its abort flag into device memory, so that waiting waves poll HBM instead of sending
-// PCIe reads.
-// The host's release of the count orders its ring writes before it; the mirror takes it
-// with acquire and passes it on with release, and the waves read it with acquire.
-__device__ __forceinline__ void mirror_published(const dev_ctx& c, const embbag_args& a, uint64_t* pub_dev) {
+// service wavefront stages what the host publishes: it takes the host's count of bags
+// with acquire (system scope), copies the new bags' descriptors, their lookups and their
+// requests' sizes from the rings in pinned host memory into the same slots of HBM rings,
+// and passes the count on with release, so the waves read HBM, not PCIe.  It also
+// mirrors the stop flag and the host's abort flag.
+struct serve_stage {
+  const uint64_t *h_j0, *h_j1, *h_req;  // the host's rings (pinned, mapped)
+  const uint32_t *h_tab, *h_rnb;
+  const int64_t* h_idx;
+  uint64_t *d_j0, *d_j1, *d_req;        // their HBM copies, read by the waves
+  uint32_t *d_tab, *d_rnb;
+  int64_t* d_idx;
+  uint64_t* pub_dev;                    // [0] bags staged, [1] stop
+};
+__device__ __forceinline__ void stage_published(const dev_ctx& c, const embbag_args& a, const serve_stage& st) {
   uint64_t last = 0;
   for (;;) {
     const uint64_t v = uni64(__hip_atomic_load(a.pub_host, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM));
     if (v != last) {
+      for (uint64_t b = last + lane(); b < v; b += 64) {
+        const uint64_t sl = b & a.bag_mask;
+        st.d_j0[sl] = ring_ld(st.h_j0 + sl);
+        st.d_j1[sl] = ring_ld(st.h_j1 + sl);
+        st.d_req[sl] = ring_ld(st.h_req + sl);
+        st.d_tab[sl] = ring_ld(st.h_tab + sl);
+      }
+      // the new bags' lookups are one run of positions, their requests one run of
+      // numbers (the host publishes whole requests)
+      const uint64_t jl = uni64(ring_ld(st.h_j0 + (last & a.bag_mask)));
+      const uint64_t jh = uni64(ring_ld(st.h_j1 + ((v - 1) & a.bag_mask)));
+      for (uint64_t j0 = jl; j0 < jh; j0 += 8 * 64) {
+        int64_t x[8];
+#pragma unroll
+        for (uint32_t k = 0; k < 8; ++k) {
+          const uint64_t j = j0 + k * 64 + lane();
+          if (j < jh) x[k] = ring_ld(st.h_idx + (j & a.look_mask));
+        }
+#pragma unroll
+        for (uint32_t k = 0; k < 8; ++k) {
+          const uint64_t j = j0 + k * 64 + lane();
+          if (j < jh) st.d_idx[j & a.look_mask] = x[k];
+        }
+      }
+      const uint64_t rl = uni64(ring_ld(st.h_req + (last & a.bag_mask)));
+      const uint64_t rh = uni64(ring_ld(st.h_req + ((v - 1) & a.bag_mask)));
+      for (uint64_t r = rl + lane(); r <= rh; r += 64) st.d_rnb[r & a.req_mask] = ring_ld(st.h_rnb + (r & a.req_mask));
       last = v;
-      if (lane() == 0) __hip_atomic_store(pub_dev, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      fence_rel();  // the copies before the count that publishes them
+      if (lane() == 0) __hip_atomic_store(st.pub_dev, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     if (aborted(c) || host_abort_poll(c)) break;
     if (uni64(__hip_atomic_load(a.pub_host + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM))) {
-      if (lane() == 0) st_rlx(pub_dev + 1, 1ull);
+      if (lane() == 0) st_rlx(st.pub_dev + 1, 1ull);
       break;
     }
     __builtin_amdgcn_s_sleep(16);
@@ -866,10 +907,10 @@ __device__ __forceinline__ void mirror_published(const dev_ctx& c, const embbag_
 }
 
 template <int VPL>
-__global__ __launch_bounds__(WG) void k_serve(dev_ctx c, launch_t li, embbag_args a, uint64_t* pub_dev) {
+__global__ __launch_bounds__(WG) void k_serve(dev_ctx c, launch_t li, embbag_args a, serve_stage st) {
   if (blockIdx.x < li.service_blocks) {
     if (service_role(li) == li.n_ctrl + li.n_cq) {
-      mirror_published(c, a, pub_dev);
+      stage_published(c, a, st);
       return;
     }
     run_service(c, li);
@@ -1813,7 +1854,7 @@ struct agile_session_s {
   uint64_t bag_cap = 0, look_cap = 0, req_cap = 0;  // ring sizes (powers of two)
   uint64_t cap_look = 0, cap_lines = 0, cap_req = 0;  // admission budgets
   void* host = nullptr;  // pinned, mapped, coherent: control words and rings
-  void* dev = nullptr;   // per-request-slot bag counters, device mirror of the control words
+  void* dev = nullptr;   // HBM: per-request-slot bag counters, staged count, ring copies
   hipStream_t hs = nullptr;
   uint64_t* ctl = nullptr;  // [0] bags published, [1] stop
   uint64_t *bag_j0 = nullptr, *bag_j1 = nullptr, *bag_req = nullptr;
@@ -2984,7 +3025,12 @@ agile_status agile_session_open(agile_ctx ctx, agile_store store, const agile_ta
   void* dhb = nullptr;
   if (hipHostGetDevicePointer(&dhb, se->host, 0) != hipSuccess) return cleanup(AGILE_EHIP, "session: mapping");
   uint8_t* dh = (uint8_t*)dhb;
-  const size_t dbytes = al(4 * se->req_cap) + 256;
+  // HBM: per-request-slot bag counters, the staged count and stop flag, and the HBM
+  // copies of the rings that the waves read
+  const size_t q_cnt = 0, q_pub = q_cnt + al(4 * se->req_cap), q_j0 = q_pub + 256,
+               q_j1 = q_j0 + al(8 * se->bag_cap), q_req = q_j1 + al(8 * se->bag_cap),
+               q_tab = q_req + al(8 * se->bag_cap), q_rnb = q_tab + al(4 * se->bag_cap),
+               q_idx = q_rnb + al(4 * se->req_cap), dbytes = q_idx + al(8 * se->look_cap);
   if (hipMalloc(&se->dev, dbytes) != hipSuccess) {
     (void)hipGetLastError();
     se->dev = nullptr;
@@ -2995,8 +3041,23 @@ agile_status agile_session_open(agile_ctx ctx, agile_store store, const agile_ta
     se->hs = nullptr;
     return cleanup(AGILE_EHIP, "session: stream");
   }
+  uint8_t* db = (uint8_t*)se->dev;
+  serve_stage sg{};
+  sg.h_j0 = (const uint64_t*)(dh + o_j0);
+  sg.h_j1 = (const uint64_t*)(dh + o_j1);
+  sg.h_req = (const uint64_t*)(dh + o_breq);
+  sg.h_tab = (const uint32_t*)(dh + o_btab);
+  sg.h_rnb = (const uint32_t*)(dh + o_rnb);
+  sg.h_idx = (const int64_t*)(dh + o_idx);
+  sg.d_j0 = (uint64_t*)(db + q_j0);
+  sg.d_j1 = (uint64_t*)(db + q_j1);
+  sg.d_req = (uint64_t*)(db + q_req);
+  sg.d_tab = (uint32_t*)(db + q_tab);
+  sg.d_rnb = (uint32_t*)(db + q_rnb);
+  sg.d_idx = (int64_t*)(db + q_idx);
+  sg.pub_dev = (uint64_t*)(db + q_pub);
   embbag_args a{};
-  a.idx = (const int64_t*)(dh + o_idx);
+  a.idx = sg.d_idx;
   a.out = (float*)(dh + o_out);
   a.nbags = (uint64_t)INT64_MAX;  // an unbounded stream: the session ends on the stop flag
   a.rows = tb->rows;
@@ -3008,15 +3069,14 @@ agile_status agile_session_open(agile_ctx ctx, agile_store store, const agile_ta
   a.K = K;
   a.mode = mode;
   a.serve = 1;
-  a.bag_j0 = (const uint64_t*)(dh + o_j0);
-  a.bag_j1 = (const uint64_t*)(dh + o_j1);
-  a.bag_req = (const uint64_t*)(dh + o_breq);
-  a.bag_tab = (const uint32_t*)(dh + o_btab);
-  a.req_nbags = (const uint32_t*)(dh + o_rnb);
+  a.bag_j0 = sg.d_j0;
+  a.bag_j1 = sg.d_j1;
+  a.bag_req = sg.d_req;
+  a.bag_tab = sg.d_tab;
+  a.req_nbags = sg.d_rnb;
   a.done = (uint32_t*)(dh + o_done);
-  a.req_cnt = (uint32_t*)se->dev;
-  uint64_t* pub_dev = (uint64_t*)((uint8_t*)se->dev + al(4 * se->req_cap));
-  a.pub_dev = pub_dev;
+  a.req_cnt = (uint32_t*)(db + q_cnt);
+  a.pub_dev = sg.pub_dev;
   a.pub_host = (const uint64_t*)(dh + o_ctl);
   a.bag_mask = se->bag_cap - 1;
   a.look_mask = se->look_cap - 1;
@@ -3036,11 +3096,11 @@ agile_status agile_session_open(agile_ctx ctx, agile_store store, const agile_ta
   li.service_blocks = svc_blocks;
   const dim3 grid(li.service_blocks + uw / WPB);
   if (kind == KIND_SERVE1)
-    hipLaunchKernelGGL(k_serve<1>, grid, dim3(WG), lds_of(ctx, (const void*)k_serve<1>), se->hs, ctx->d, li, a, pub_dev);
+    hipLaunchKernelGGL(k_serve<1>, grid, dim3(WG), lds_of(ctx, (const void*)k_serve<1>), se->hs, ctx->d, li, a, sg);
   else if (kind == KIND_SERVE2)
-    hipLaunchKernelGGL(k_serve<2>, grid, dim3(WG), lds_of(ctx, (const void*)k_serve<2>), se->hs, ctx->d, li, a, pub_dev);
+    hipLaunchKernelGGL(k_serve<2>, grid, dim3(WG), lds_of(ctx, (const void*)k_serve<2>), se->hs, ctx->d, li, a, sg);
   else
-    hipLaunchKernelGGL(k_serve<4>, grid, dim3(WG), lds_of(ctx, (const void*)k_serve<4>), se->hs, ctx->d, li, a, pub_dev);
+    hipLaunchKernelGGL(k_serve<4>, grid, dim3(WG), lds_of(ctx, (const void*)k_serve<4>), se->hs, ctx->d, li, a, sg);
   if (hipGetLastError() != hipSuccess) return cleanup(AGILE_EHIP, "session: launch failed");
   ctx->session = se;
   *out = se;
