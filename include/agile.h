@@ -61,6 +61,14 @@ typedef uint64_t agile_ticket;
 #define AGILE_F_SERIALIZED 0x1u /* workloads run one request at a time on one lane */
 #define AGILE_F_NO_PRIO 0x2u    /* do not raise the service wavefronts' issue priority */
 #define AGILE_F_PROFILE 0x4u    /* accumulate per-stage timers (see agile_debug_counters) */
+#define AGILE_F_LOCKCHAIN 0x8u  /* lock-chain debugging (Sec. 3.5's lock-chain debugger for
+                                   this library's waits): every spinning wavefront records
+                                   what it waits for and set locks record their holder; the
+                                   first wait to time out follows the chain (a set lock to
+                                   its holder, to what that holder waits for, ...) and the
+                                   error text of the next blocking call lists it, ending at
+                                   a wait on no wave (a fill, a write-back, an SQ slot, a free
+                                   way), a running wave, or a cycle */
 
 typedef struct agile_config {
   uint32_t struct_size;  /* sizeof(agile_config) */
@@ -177,6 +185,50 @@ agile_status agile_flush(agile_ctx ctx, agile_store store, void* stream);
  * lines.  Blocks until done; returns the sticky error, if any. */
 agile_status agile_write(agile_ctx ctx, agile_store store, const uint64_t* d_lines, uint32_t n,
                          const void* d_src, void* stream);
+
+/* Reads into user buffers with the Share Table (Sec. 3.4.1; Listing 1's asyncRead into an
+ * AgileBuf).  Request i delivers store block d_blocks[i] (device uint64, < the store's
+ * blocks) into the caller's buffer d_bufs[i] (device memory, 4096 bytes, 16-byte
+ * aligned).  A block resident in the cache is copied at once; a block whose line is being
+ * filled puts the buffer on the line's pending list and the completion service copies
+ * the block into it before the line turns READY, so the requesting wavefront goes on to
+ * its next requests instead of waiting (the buffer, not a cache line, holds the data
+ * afterwards: no pin is kept).  With AGILE_ISSUE_SHARE the Share Table is consulted
+ * first: the first live holder of a block owns it (status AGILE_BUF_OWNER, its buffer
+ * receives the block) and later requests for the same block share the owner's buffer
+ * (AGILE_BUF_SHARED: d_ptrs[i] points at it, no copy is made) until every holder has
+ * released it (agile_buffers_release); a block that finds no free table slot along its
+ * probe is copied privately (AGILE_BUF_PRIVATE, as without the flag).  d_ptrs[i]
+ * (device) receives the address that holds block i, d_status[i] (device) its status.
+ * Blocks until every copy has landed; a set with no evictable way is retried, not
+ * reported.  The sticky error is returned. */
+#define AGILE_ISSUE_SHARE 0x1u
+#define AGILE_BUF_OWNER 1u   /* copied into this request's buffer, registered as the owner */
+#define AGILE_BUF_PRIVATE 2u /* copied into this request's buffer, not in the Share Table */
+#define AGILE_BUF_SHARED 3u  /* d_ptrs[i] is a live holder's buffer; nothing was copied */
+agile_status agile_async_issue(agile_ctx ctx, agile_store store, const uint64_t* d_blocks, uint32_t n,
+                               void* const* d_bufs, void** d_ptrs, uint32_t* d_status,
+                               uint32_t flags, void* stream);
+
+/* Drops the Share Table holds that agile_async_issue returned: request i's hold of block
+ * d_blocks[i] when d_status[i] is AGILE_BUF_OWNER or AGILE_BUF_SHARED (others are
+ * skipped).  A block with no holder left is free for a new owner.  Releasing more often
+ * than held raises the sticky error (AGILE_ESTATE).  Blocks. */
+agile_status agile_buffers_release(agile_ctx ctx, const uint64_t* d_blocks, const uint32_t* d_status,
+                                   uint32_t n, void* stream);
+
+/* The owner propagates its buffer's changes to the cache (Sec. 3.4.1): block d_blocks[i]
+ * takes the 4096 bytes at d_srcs[i] (device, 16-byte aligned) inside its cache line
+ * (the line is read first on a miss; a line being written back is modified once that
+ * write has landed), and the line becomes MODIFIED, to be written back on eviction or
+ * at agile_flush.  Requests for the same line are applied in turn, lowest index first
+ * within a wavefront.  Blocks; returns the sticky error. */
+agile_status agile_buffers_writeback(agile_ctx ctx, agile_store store, const uint64_t* d_blocks,
+                                     const void* const* d_srcs, uint32_t n, void* stream);
+
+/* Empties the Share Table (every holder forgotten).  For use between phases with no
+ * buffer shared.  Blocks. */
+agile_status agile_share_reset(agile_ctx ctx);
 
 /* Drops every clean, unpinned line (cold cache).  Dirty lines make it fail with
  * AGILE_ESTATE (flush first).  Blocks until done. */
@@ -301,6 +353,20 @@ agile_status agile_debug_exclusive_scan_u64(const uint64_t* d_in, uint64_t* d_ou
  * order of keys whose bits agree.  Allocates its work area; blocks. */
 agile_status agile_debug_radix_sort_u64(uint64_t* d_keys, uint64_t n, uint32_t lo, uint32_t hi,
                                         void* stream);
+
+/* The lock-chain walker of AGILE_F_LOCKCHAIN run on a given wait state (diagnostics):
+ * waits[w] (host, n_waits entries) is what wave w waits for, encoded as the walker
+ * records it (kind << 56 | object: kind 0x0A = the set lock of store line `object`,
+ * 0x0D = the fill of cache line `object`, 0x0B its write-back, 0x01 an SQ slot
+ * (q << 32 | ticket), 0x0F a free way; 0 = not waiting); set lock_sets[i] (host) is given
+ * the word lock_words[i] (holder wave + 2, or 1 for an unnamed holder).  The walk starts
+ * at wave start_wave waiting for start_what; the chain's text goes to msg (host,
+ * msg_len bytes, NUL-terminated).  The state is cleared afterwards (waits, the given set
+ * locks, the chain).  No other call may run on the context meanwhile.  Blocks. */
+agile_status agile_debug_lockchain(agile_ctx ctx, const uint64_t* waits, uint32_t n_waits,
+                                   const uint32_t* lock_sets, const uint32_t* lock_words,
+                                   uint32_t n_locks, uint32_t start_wave, uint64_t start_what,
+                                   char* msg, uint32_t msg_len);
 
 /* Raw device counters in their internal order (for diagnostics): out[i] for i < n. */
 agile_status agile_debug_counters(agile_ctx ctx, uint64_t* out, uint32_t n);

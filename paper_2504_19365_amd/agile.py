@@ -15,7 +15,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libagile.so")
 
 OK, EINVAL, ENOMEM, EHIP, ETIMEDOUT, EAGAIN, EIO, EPROTO, ESTATE = 0, -1, -2, -3, -4, -5, -6, -7, -8
-F_SERIALIZED, F_NO_PRIO, F_PROFILE = 0x1, 0x2, 0x4
+F_SERIALIZED, F_NO_PRIO, F_PROFILE, F_LOCKCHAIN = 0x1, 0x2, 0x4, 0x8
 MODE_SYNC, MODE_ASYNC = 0, 1
 
 
@@ -145,6 +145,11 @@ def lib():
             "agile_write": (st, [vp, vp, vp, u32, vp, vp]),
             "agile_embbag_forward_resident": (st, [vp, vp, u64, C.POINTER(Tables), vp, vp, u64, u32,
                                                    vp, vp]),
+            "agile_debug_lockchain": (st, [vp, vp, u32, vp, vp, u32, u32, u64, C.c_char_p, u32]),
+            "agile_async_issue": (st, [vp, vp, vp, u32, vp, vp, vp, u32, vp]),
+            "agile_buffers_release": (st, [vp, vp, vp, u32, vp]),
+            "agile_buffers_writeback": (st, [vp, vp, vp, vp, u32, vp]),
+            "agile_share_reset": (st, [vp]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -370,6 +375,32 @@ class Context:
         self._check(lib().agile_release(self.h, _ptr(tickets), tickets.numel(), _stream(stream)),
                     "agile_release")
 
+    ISSUE_SHARE = 0x1
+    BUF_OWNER, BUF_PRIVATE, BUF_SHARED = 1, 2, 3
+
+    def async_issue(self, blocks, bufs, ptrs, status, share: bool = False, stream=None,
+                    store=None):
+        """Reads into user buffers (agile_async_issue): bufs/ptrs are device int64 arrays
+        of addresses, status a device int32 array."""
+        store = store or self.store
+        self._check(lib().agile_async_issue(self.h, store.handle, _ptr(blocks), blocks.numel(),
+                                            _ptr(bufs), _ptr(ptrs), _ptr(status),
+                                            self.ISSUE_SHARE if share else 0, _stream(stream)),
+                    "agile_async_issue")
+
+    def buffers_release(self, blocks, status, stream=None):
+        self._check(lib().agile_buffers_release(self.h, _ptr(blocks), _ptr(status), blocks.numel(),
+                                                _stream(stream)), "agile_buffers_release")
+
+    def buffers_writeback(self, blocks, srcs, stream=None, store=None):
+        store = store or self.store
+        self._check(lib().agile_buffers_writeback(self.h, store.handle, _ptr(blocks), _ptr(srcs),
+                                                  blocks.numel(), _stream(stream)),
+                    "agile_buffers_writeback")
+
+    def share_reset(self):
+        self._check(lib().agile_share_reset(self.h), "agile_share_reset")
+
     def flush(self, stream=None, store=None):
         store = store or self.store
         self._check(lib().agile_flush(self.h, store.handle, _stream(stream)), "agile_flush")
@@ -492,6 +523,25 @@ class Context:
         return Session(self, h.value, tb.dim)
 
     # ---- diagnostics
+    W_SQ_SLOT, W_SETLOCK, W_WB, W_FILL, W_TICKET, W_WAY, W_CLAIM = 0x01, 0x0A, 0x0B, 0x0D, 0x0E, 0x0F, 0x10
+
+    def debug_lockchain(self, waits: dict, locks: dict, start_wave: int, start_what: int) -> str:
+        """Runs the lock-chain walker on a given wait state (agile_debug_lockchain):
+        waits = {wave: (kind << 56) | object}, locks = {set: lock word}."""
+        n = max(waits) + 1 if waits else 0
+        w = np.zeros(n, dtype=np.uint64)
+        for k, v in waits.items():
+            w[k] = v
+        sets = np.array(list(locks.keys()), dtype=np.uint32)
+        words = np.array(list(locks.values()), dtype=np.uint32)
+        buf = C.create_string_buffer(2048)
+        self._check(lib().agile_debug_lockchain(self.h, _ptr(w) if n else 0, n,
+                                                _ptr(sets) if sets.size else 0,
+                                                _ptr(words) if words.size else 0, sets.size,
+                                                start_wave, start_what, buf, 2048),
+                    "agile_debug_lockchain")
+        return buf.value.decode()
+
     def debug_trace(self, lines, writes, hit, way, stream=None, store=None):
         store = store or self.store
         self._check(lib().agile_debug_trace(self.h, store.handle, _ptr(lines), _ptr(writes),
@@ -506,7 +556,7 @@ class Context:
                      "t_u_issue", "t_u_submit", "t_u_wait", "t_u_consume", "tok_lead",
                      "tok_n", "t_u_desc", "t_u_life", "svc_exit", "img_epoch", "work_p1",
                      "work_p2", "work_p3", "work_p4", "work_p5", "work_p6", "work_p7", "defer",
-                     "hit_total", "deflen")
+                     "pend", "hit_total", "deflen")
 
     def debug_counters(self) -> dict:
         n = len(self.COUNTER_NAMES)

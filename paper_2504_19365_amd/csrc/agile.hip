@@ -459,7 +459,7 @@ __device__ __forceinline__ bool finish_chunk(const dev_ctx& c, const embbag_args
         make_chunk(c, a, one, cc);
         if (!chunk_issue(c, cc, q, true, PIN_LINE)) return false;
         if (rdlane(cc.st, 0) != A_EAGAIN) break;
-        if (!sp.step(c, 0xF0000000ull | (uint32_t)dc.g)) return false;
+        if (!sp.step(c, wi(W_WAY, (uint64_t)dc.g))) return false;
       }
       if (!chunk_wait(c, cc, false)) return false;
       consume<VPL>(c, a, one, cc, acc, false);
@@ -598,7 +598,7 @@ __device__ __forceinline__ void embbag_serial(const dev_ctx& c, const launch_t& 
           if (lane() == 0) wcount(WS_AUX1, 1);
           break;
         }
-        if (!sp.step(c, 0xF1000000ull)) return;
+        if (!sp.step(c, wi(W_WAY, 0))) return;
       }
     }
     if (!a.gather) write_bag<VPL>(c, a, (int64_t)g, acc);
@@ -987,7 +987,7 @@ __global__ __launch_bounds__(WG) void k_wait(dev_ctx c, launch_t li, const agile
         if (m_gen(m) != gen || m_rc(m) == 0) raise_error(c, E_STATE, ((uint64_t)idx << 8) | gen);
       }
     }
-    if (ballot(waiting) && !sp.step(c, 0xE0000000ull | idx)) {
+    if (ballot(waiting) && !sp.step(c, wi(W_TICKET, rdlane(idx, ffs64(ballot(waiting)))))) {
       okay = false;
       break;
     }
@@ -1134,10 +1134,255 @@ __global__ __launch_bounds__(WG) void k_write_lines(dev_ctx c, launch_t li, cons
           // the WRITE is queued: the pin can go (a WRITEBACK line is never evicted)
           if (got) add_rel(c.meta + ch.idx, (uint64_t)0 - RC_ONE);
         }
-        if (ballot(claiming) && !sc.step(c, 0xF0000000ull | ch.idx)) goto out;
+        if (ballot(claiming) && !sc.step(c, wi(W_CLAIM, rdlane(ch.idx, ffs64(ballot(claiming)))))) goto out;
       }
       if (ch.act && ch.st != A_EAGAIN) todo = false;
-      if (ballot(todo) && !sp.step(c, 0xF1000000ull | lid)) goto out;
+      if (ballot(todo) && !sp.step(c, wi(W_WAY, rdlane(lid, ffs64(ballot(todo)))))) goto out;
+    }
+  }
+out:
+  user_wave_done(c, li);
+}
+
+// ---- reads into user buffers and the Share Table (Sec. 3.4.1, Listing 1's asyncRead)
+// Share Table slot of block `blk` for a request whose buffer is `mine`: the first live
+// holder of a block owns the slot and its buffer is the block's; later requests share
+// that buffer (a holder count).  Returns 1 = owner, 2 = no slot along the probe (not
+// registered), 3 = shared (`ptr` = the owner's buffer).  One lane.
+__device__ __forceinline__ uint32_t share_acquire(const dev_ctx& c, uint64_t blk, uint64_t mine, uint64_t& ptr) {
+  const uint64_t key = blk + 1;
+  uint32_t h = (uint32_t)((blk * 0x9E3779B97F4A7C15ull) >> 40) & (SHARE_CAP - 1);
+  for (uint32_t p = 0; p < SHARE_PROBES; ++p, h = (h + 1) & (SHARE_CAP - 1)) {
+    uint64_t k = ld_rlx(c.share_key + h);
+    if (k == 0) {
+      uint64_t z = 0;
+      k = cas(c.share_key + h, z, key) ? key : z;  // z holds the key that won the slot
+    }
+    if (k != key) continue;
+    for (uint32_t spins = 0;; ++spins) {
+      uint32_t r = __hip_atomic_load(c.share_refs + h, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+      if (r == SHARE_BUSY) {  // an owner is installing its buffer: a few stores away
+        __builtin_amdgcn_s_sleep(1);
+        if (spins > (1u << 20)) {
+          raise_error(c, E_TIMEDOUT, wi(W_CLAIM, h));
+          ptr = mine;
+          return 2;
+        }
+        continue;
+      }
+      if (r == 0) {  // no live holder: become the owner
+        if (cas(c.share_refs + h, r, SHARE_BUSY)) {
+          st_rlx(c.share_buf + h, mine);
+          __hip_atomic_store(c.share_refs + h, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+          ptr = mine;
+          return 1;
+        }
+        continue;
+      }
+      if (cas(c.share_refs + h, r, r + 1)) {
+        fence_acq();
+        ptr = ld_rlx(c.share_buf + h);
+        return 3;
+      }
+    }
+  }
+  ptr = mine;
+  return 2;
+}
+
+// Copies 4 KiB from src to dst with the whole wave (64 lanes x 4 x 16 bytes).
+__device__ __forceinline__ void copy_block_wave(const uint8_t* src, uint8_t* dst) {
+  const uint4* s4 = reinterpret_cast<const uint4*>(src);
+  uint4* d4 = reinterpret_cast<uint4*>(dst);
+  uint4 v[4];
+#pragma unroll
+  for (uint32_t i = 0; i < 4; ++i) v[i] = s4[i * 64 + lane()];
+#pragma unroll
+  for (uint32_t i = 0; i < 4; ++i) d4[i * 64 + lane()] = v[i];
+}
+
+// Request i delivers block blocks[i] into buffer bufs[i] (device, 16-byte aligned), or,
+// with sharing, points at the buffer of a live holder of the same block.  A resident
+// block is copied at once; a block whose line is being filled puts its buffer on the
+// line's pending list (the completion service copies it before the line turns READY), so
+// the wave goes on to its next requests instead of waiting; a list found closed (the
+// fill has landed) makes the wave copy the block itself once the line is READY.  Pins are
+// held only while a wave copies or appends.  A set with no evictable way is retried with
+// nothing held.
+__global__ __launch_bounds__(WG) void k_async_issue(dev_ctx c, launch_t li, const uint64_t* blocks, uint32_t n,
+                                                    void* const* bufs, void** ptrs, uint32_t* status, uint32_t share) {
+  if (blockIdx.x < li.service_blocks) {
+    run_service(c, li);
+    return;
+  }
+  user_wave_begin();
+  const uint32_t uw = (blockIdx.x - li.service_blocks) * WPB + threadIdx.x / 64;
+  const uint32_t q = uw % c.num_qp;
+  for (uint64_t base = (uint64_t)uw * 64; base < n; base += (uint64_t)li.user_waves * 64) {
+    const uint64_t i = base + lane();
+    bool todo = i < n;
+    uint64_t blk = 0, dst = 0, ptr = 0;
+    uint32_t st = AGILE_BUF_PRIVATE;
+    if (todo) {
+      blk = blocks[i];
+      dst = (uint64_t)(uintptr_t)bufs[i];
+      if (blk >= c.store_blocks || (dst & 15) || !dst) {
+        raise_error(c, E_STATE, blk);
+        todo = false;
+      } else if (share) {
+        st = share_acquire(c, blk, dst, ptr);
+        if (st == AGILE_BUF_SHARED) todo = false;  // another holder's buffer has (or will have) it
+      }
+      if (st != AGILE_BUF_SHARED) ptr = dst;
+    }
+    const uint32_t boff = (uint32_t)((blk % c.blocks_per_line) << 12);
+    spin_t sp;
+    while (ballot(todo)) {
+      chunk_t ch;
+      ch.act = todo;
+      ch.line_id = (uint32_t)(blk / c.blocks_per_line);
+      ch.off = boff;
+      if (!chunk_issue(c, ch, q, true, PIN_LINE)) goto out;
+      const bool got = ch.act && st_ok(ch.st);
+      // lines being filled: append to the pending list while still pinned (the pin keeps
+      // the line from a new tenant, so the list appended to is this fill's)
+      bool self = got && ch.st == A_HIT;
+      if (got && ch.st != A_HIT) {
+        const uint64_t e = add_rlx(counter(c, C_PEND), 1ull);
+        if (e >= PEND_CAP) {
+          self = true;  // no entry left: copy it ourselves
+        } else {
+          st_rlx(c.pend + 2 * e, dst);
+          fence_rel();
+          uint32_t h = ld_rlx(c.pend_head + ch.idx);
+          for (;;) {
+            if (h == PEND_CLOSED) {
+              self = true;  // the fill has landed (or is being delivered): copy it ourselves
+              break;
+            }
+            st_rlx(c.pend + 2 * e + 1, ((uint64_t)boff << 32) | h);
+            fence_rel();
+            if (cas(c.pend_head + ch.idx, h, (uint32_t)e)) break;
+          }
+        }
+      }
+      // copies by the wave itself: wait (per lane: the pin keeps the tenant) until the
+      // line holds its data, then copy
+      {
+        bool waiting = self;
+        spin_t sw;
+        while (ballot(waiting)) {
+          if (waiting) {
+            const uint64_t m = ld_rlx(c.meta + ch.idx);
+            if (m_state(m) != ST_FETCHING || m_tag(m) != ch.line_id || m_gen(m) != ch.gen) waiting = false;
+          }
+          if (ballot(waiting) && !sw.step(c, wi(W_FILL, rdlane(ch.idx, ffs64(ballot(waiting)))))) goto out;
+        }
+        fence_acq();
+      }
+      for (uint64_t t = ballot(self); t; t &= t - 1) {
+        const uint32_t l = ffs64(t);
+        copy_block_wave(line_ptr(c, rdlane(ch.idx, l)) + rdlane(ch.off, l),
+                        reinterpret_cast<uint8_t*>((uintptr_t)rdlane64(dst, l)));
+      }
+      chunk_release(c, ch, false);
+      if (got) todo = false;
+      if (ballot(todo) && !sp.step(c, wi(W_WAY, rdlane(ch.line_id, ffs64(ballot(todo)))))) goto out;
+    }
+    if (i < n) {
+      ptrs[i] = (void*)(uintptr_t)ptr;
+      status[i] = st;
+    }
+  }
+out:
+  user_wave_done(c, li);
+}
+
+// Drops Share Table holds: request i's hold of block blocks[i] if status[i] says it
+// has one (owner or sharer).  Not a service kernel.
+__global__ void k_share_release(dev_ctx c, const uint64_t* blocks, const uint32_t* status, uint32_t n) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const uint32_t st = status[i];
+  if (st != AGILE_BUF_OWNER && st != AGILE_BUF_SHARED) return;
+  const uint64_t blk = blocks[i], key = blk + 1;
+  uint32_t h = (uint32_t)((blk * 0x9E3779B97F4A7C15ull) >> 40) & (SHARE_CAP - 1);
+  for (uint32_t p = 0; p < SHARE_PROBES; ++p, h = (h + 1) & (SHARE_CAP - 1)) {
+    if (ld_rlx(c.share_key + h) != key) continue;
+    uint32_t r = ld_rlx(c.share_refs + h);
+    for (;;) {
+      if (r == 0 || r == SHARE_BUSY) {
+        raise_error(c, E_STATE, blk);  // released more often than held
+        return;
+      }
+      if (cas(c.share_refs + h, r, r - 1)) return;
+    }
+  }
+  raise_error(c, E_STATE, blk);
+}
+
+// The owner propagates its buffer's changes (Sec. 3.4.1): block blocks[i] takes the
+// 4 KiB at srcs[i] inside its cache line (read first on a miss), which becomes MODIFIED
+// and is written back on eviction or at agile_flush.
+__global__ __launch_bounds__(WG) void k_buf_writeback(dev_ctx c, launch_t li, const uint64_t* blocks, uint32_t n,
+                                                      const void* const* srcs) {
+  if (blockIdx.x < li.service_blocks) {
+    run_service(c, li);
+    return;
+  }
+  user_wave_begin();
+  const uint32_t uw = (blockIdx.x - li.service_blocks) * WPB + threadIdx.x / 64;
+  const uint32_t q = uw % c.num_qp;
+  for (uint64_t base = (uint64_t)uw * 64; base < n; base += (uint64_t)li.user_waves * 64) {
+    const uint64_t i = base + lane();
+    bool todo = i < n;
+    uint64_t blk = 0, src = 0;
+    if (todo) {
+      blk = blocks[i];
+      src = (uint64_t)(uintptr_t)srcs[i];
+      if (blk >= c.store_blocks || (src & 15) || !src) {
+        raise_error(c, E_STATE, blk);
+        todo = false;
+      }
+    }
+    // lanes naming the same line take turns: one lane per distinct line per round
+    spin_t sp;
+    while (ballot(todo)) {
+      chunk_t ch;
+      ch.act = todo;
+      ch.line_id = (uint32_t)(blk / c.blocks_per_line);
+      ch.off = (uint32_t)((blk % c.blocks_per_line) << 12);
+      dedup(ch, todo);
+      const bool first = todo && ch.leader == lane();
+      ch.act = first;
+      if (!chunk_issue(c, ch, q, true, PIN_LINE)) goto out;
+      if (!chunk_wait(c, ch)) goto out;
+      const bool got = first && st_ok(ch.st);
+      {
+        // a line being written back (an eviction that chose it before our pin) is
+        // modified only once that write has landed
+        bool wbw = got;
+        spin_t sw;
+        while (ballot(wbw)) {
+          if (wbw && m_state(ld_rlx(c.meta + ch.idx)) != ST_WRITEBACK) wbw = false;
+          if (ballot(wbw) && !sw.step(c, wi(W_WB, rdlane(ch.idx, ffs64(ballot(wbw)))))) goto out;
+        }
+        fence_acq();
+      }
+      for (uint64_t t = ballot(got); t; t &= t - 1) {
+        const uint32_t l = ffs64(t);
+        copy_block_wave(reinterpret_cast<const uint8_t*>((uintptr_t)rdlane64(src, l)),
+                        line_ptr(c, rdlane(ch.idx, l)) + rdlane(ch.off, l));
+      }
+      if (got) {
+        uint64_t mv = ld_rlx(c.meta + ch.idx);
+        while (m_state(mv) == ST_READY) {
+          if (cas(c.meta + ch.idx, mv, mv + 1ull)) break;  // READY -> MODIFIED
+        }
+      }
+      chunk_release(c, ch, true);
+      if (got) todo = false;
+      if (ballot(todo) && !ballot(got) && !sp.step(c, wi(W_WAY, rdlane(ch.line_id, ffs64(ballot(todo)))))) goto out;
     }
   }
 out:
@@ -1185,7 +1430,7 @@ __global__ __launch_bounds__(WG) void k_trace(dev_ctx c, launch_t li, const uint
         if (!chunk_issue(c, ch, 0, true, PIN_LINE)) goto out;
         if (!chunk_wait(c, ch)) goto out;
         if (rdlane(ch.st, 0) != A_EAGAIN) break;
-        if (!sp.step(c, 0xF2000000ull)) goto out;
+        if (!sp.step(c, wi(W_WAY, 0))) goto out;
       }
       if (lane() == 0) {
         hit[i] = (ch.st == A_MISS) ? 0 : 1;
@@ -1280,7 +1525,7 @@ __device__ __forceinline__ void bwd_wave(const dev_ctx& c, const bwd_args& a, ui
       bool wbw = ch.act && st_ok(ch.st) && ch.leader == lane();
       while (ballot(wbw)) {
         if (wbw && m_state(ld_rlx(c.meta + ch.idx)) != ST_WRITEBACK) wbw = false;
-        if (ballot(wbw) && !sp.step(c, 0xB1000000ull | ch.idx)) return;
+        if (ballot(wbw) && !sp.step(c, wi(W_WB, rdlane(ch.idx, ffs64(ballot(wbw)))))) return;
       }
       const uint64_t okm = ballot(ch.act && st_ok(ch.st));
       for (uint64_t m = okm; m; m &= m - 1) {
@@ -1330,7 +1575,7 @@ __device__ __forceinline__ void bwd_wave(const dev_ctx& c, const bwd_args& a, ui
       chunk_release(c, ch, true);
       if (okm && ((okm >> lane()) & 1ull)) todo = false;
       if (ballot(todo) && !okm) {
-        if (!sp.step(c, 0xF3000000ull | gidx)) return;
+        if (!sp.step(c, wi(W_WAY, gidx))) return;
       }
     }
   }
@@ -1384,7 +1629,7 @@ __device__ __forceinline__ bool cached_read(const dev_ctx& c, uint32_t q, bool a
     if (ok) todo = false;
     if (ballot(todo) && !ballot(ok)) {
       drop();
-      if (!sp.step(c, 0xF4000000ull)) return false;
+      if (!sp.step(c, wi(W_WAY, 0))) return false;
     }
   }
   return true;
@@ -1599,7 +1844,7 @@ __device__ __forceinline__ bool spmv_pin(const dev_ctx& c, uint32_t q, const spm
     if (ballot(ch.act && ch.st == A_EAGAIN)) {
       chunk_release(c, ch, false);
       spmv_drop(c, pf);
-      if (!sp.step(c, 0xF5000000ull)) return false;
+      if (!sp.step(c, wi(W_WAY, 0))) return false;
       continue;
     }
     // no acquire (an agent-scope acquire drops the whole L2 of the XCD): the window's
@@ -1894,7 +2139,8 @@ namespace {
 
 constexpr int KIND_EMBBAG1 = 0, KIND_EMBBAG2 = 1, KIND_EMBBAG4 = 2, KIND_READ = 3, KIND_FLUSH = 4,
               KIND_TRACE = 5, KIND_BWD1 = 6, KIND_BWD2 = 7, KIND_BWD4 = 8, KIND_SERVE1 = 9,
-              KIND_SERVE2 = 10, KIND_SERVE4 = 11, KIND_WRITE = 12, KIND_N = 13;
+              KIND_SERVE2 = 10, KIND_SERVE4 = 11, KIND_WRITE = 12, KIND_ISSUE = 13, KIND_WBACK = 14,
+              KIND_N = 15;
 
 agile_status fail(agile_ctx ctx, agile_status s, const std::string& msg) {
   if (ctx) ctx->last_error = msg;
@@ -1948,6 +2194,8 @@ int occupancy(agile_ctx ctx, int kind) {
     case KIND_READ: f = (const void*)k_async_read; break;
     case KIND_FLUSH: f = (const void*)k_flush; break;
     case KIND_WRITE: f = (const void*)k_write_lines; break;
+    case KIND_ISSUE: f = (const void*)k_async_issue; break;
+    case KIND_WBACK: f = (const void*)k_buf_writeback; break;
     case KIND_BWD1: f = (const void*)k_bwd_sgd<1>; break;
     case KIND_BWD2: f = (const void*)k_bwd_sgd<2>; break;
     case KIND_BWD4: f = (const void*)k_bwd_sgd<4>; break;
@@ -2011,6 +2259,49 @@ agile_status bind_store(agile_ctx ctx) {
   return AGILE_OK;
 }
 
+// Text of a recorded lock chain (see lc_walk); empty when none was recorded.
+static std::string wait_text(uint64_t what, uint64_t word) {
+  const uint32_t kind = (uint32_t)(what >> 56);
+  const unsigned long long id = what & ((1ull << 56) - 1);
+  char b[200];
+  switch (kind) {
+    case W_SQ_SLOT:
+      snprintf(b, sizeof b, "a free slot of SQ %llu for ticket %llu (slot word 0x%llx)", id >> 32, id & 0xFFFFFFFFull,
+               (unsigned long long)word);
+      break;
+    case W_SETLOCK:
+      if (word >= 2)
+        snprintf(b, sizeof b, "the set lock of store line %llu, held by wave %llu", id, (unsigned long long)word - 2);
+      else
+        snprintf(b, sizeof b, "the set lock of store line %llu (%s)", id, word ? "held" : "free now");
+      break;
+    case W_WB:
+    case W_FILL:
+    case W_TICKET:
+    case W_CLAIM:
+      snprintf(b, sizeof b, "%s of cache line %llu (state %llu, pins %llu, tag %llu)",
+               kind == W_WB ? "its write-back" : (kind == W_FILL ? "the fill" : (kind == W_TICKET ? "the ticket's line" : "a write claim")),
+               id, (unsigned long long)(word & 7), (unsigned long long)((word >> 4) & 0xFFFFF), (unsigned long long)(word >> 32));
+      break;
+    case W_WAY: snprintf(b, sizeof b, "an evictable way (after EAGAIN, object %llu)", id); break;
+    case 0: snprintf(b, sizeof b, "nothing (running)"); break;
+    default: snprintf(b, sizeof b, "0x%llx", (unsigned long long)what); break;
+  }
+  return b;
+}
+static std::string format_chain(const uint64_t* ch) {
+  if (!(ch[0] >> 63)) return "";
+  const uint32_t n = (uint32_t)((ch[0] >> 1) & 0xFFFF);
+  const bool cycle = ch[0] & 1;
+  std::string t = "; lock chain:";
+  for (uint32_t i = 0; i < n && i < LC_MAX; ++i) {
+    t += (i ? "; " : " ") + std::string("wave ") + std::to_string(ch[1 + 3 * i]) + " waits for " +
+         wait_text(ch[2 + 3 * i], ch[3 + 3 * i]);
+  }
+  if (cycle) t += "; a cycle back to wave " + std::to_string(ch[1 + 3 * n]);
+  return t;
+}
+
 agile_status map_device_error(agile_ctx ctx) {
   uint32_t err = 0;
   uint64_t info = 0;
@@ -2020,8 +2311,14 @@ agile_status map_device_error(agile_ctx ctx) {
   ctx->poisoned = true;
   char buf[160];
   snprintf(buf, sizeof buf, "device error %u (info 0x%llx)", err, (unsigned long long)info);
+  std::string chain;
+  if (ctx->cfg.flags & AGILE_F_LOCKCHAIN) {
+    std::vector<uint64_t> ch(1 + 3 * LC_MAX + 1, 0);
+    if (hipMemcpy(ch.data(), ctx->d.chain, ch.size() * 8, hipMemcpyDeviceToHost) == hipSuccess)
+      chain = format_chain(ch.data());
+  }
   switch (err) {
-    case E_TIMEDOUT: return fail(ctx, AGILE_ETIMEDOUT, std::string(buf) + ": watchdog timeout");
+    case E_TIMEDOUT: return fail(ctx, AGILE_ETIMEDOUT, std::string(buf) + ": watchdog timeout" + chain);
     case E_IO: return fail(ctx, AGILE_EIO, std::string(buf) + ": command error status");
     case E_PROTO: return fail(ctx, AGILE_EPROTO, std::string(buf) + ": queue protocol violation");
     case E_STATE: return fail(ctx, AGILE_ESTATE, std::string(buf) + ": invalid state or argument");
@@ -2161,7 +2458,7 @@ agile_status agile_init(const agile_config* cfg_in, agile_ctx* out) {
                          (const void*)k_bfs_edges, (const void*)k_spmv, (const void*)k_bwd_sgd<1>,
                          (const void*)k_bwd_sgd<2>, (const void*)k_bwd_sgd<4>, (const void*)k_serve<1>,
                          (const void*)k_serve<2>, (const void*)k_serve<4>, (const void*)k_trace,
-                         (const void*)k_write_lines};
+                         (const void*)k_write_lines, (const void*)k_async_issue, (const void*)k_buf_writeback};
     for (const void* f : fns) {
       hipFuncAttributes fa;
       memset(&fa, 0, sizeof(fa));
@@ -2220,6 +2517,13 @@ agile_status agile_init(const agile_config* cfg_in, agile_ctx* out) {
   ctx->defer_cap = 1ull << 20;  // bags per launch the resident-hit pass can take (4 MiB list)
   if ((s = dalloc(ctx, &ctx->defer_list, ctx->defer_cap * 4)) != AGILE_OK) return bail(s);
   if ((s = dalloc(ctx, &d.err, 128)) != AGILE_OK) return bail(s);
+  if ((s = dalloc(ctx, &d.waits, 16ull * WAIT_SLOTS)) != AGILE_OK) return bail(s);
+  if ((s = dalloc(ctx, &d.chain, 8ull * (1 + 3 * LC_MAX) + 8)) != AGILE_OK) return bail(s);
+  if ((s = dalloc(ctx, &d.pend_head, 4ull * lines)) != AGILE_OK) return bail(s);
+  if ((s = dalloc(ctx, &d.pend, 16ull * PEND_CAP)) != AGILE_OK) return bail(s);
+  if ((s = dalloc(ctx, &d.share_key, 8ull * SHARE_CAP)) != AGILE_OK) return bail(s);
+  if ((s = dalloc(ctx, &d.share_buf, 8ull * SHARE_CAP)) != AGILE_OK) return bail(s);
+  if ((s = dalloc(ctx, &d.share_refs, 4ull * SHARE_CAP)) != AGILE_OK) return bail(s);
   if ((s = dalloc(ctx, &d.err_info, 128)) != AGILE_OK) return bail(s);
   if ((s = dalloc(ctx, &d.abort_dev, 128)) != AGILE_OK) return bail(s);
   void* ab = nullptr;
@@ -2239,7 +2543,12 @@ agile_status agile_init(const agile_config* cfg_in, agile_ctx* out) {
       hipMemset(d.sq, 0, nq * sizeof(sqe_t)) != hipSuccess || hipMemset(d.cq, 0, nq * sizeof(cqe_t)) != hipSuccess ||
       hipMemset(d.qp, 0, (uint64_t)cfg.num_qp * sizeof(qp_t)) != hipSuccess || hipMemset(d.next_tok, 0, 128 * AGILE_MAX_DEVICES) != hipSuccess ||
       hipMemset(d.cnt, 0, (uint64_t)C_COUNT * CSTRIDE * 8) != hipSuccess || hipMemset(d.err, 0, 128) != hipSuccess ||
-      hipMemset(d.err_info, 0, 128) != hipSuccess || hipMemset(d.abort_dev, 0, 128) != hipSuccess)
+      hipMemset(d.err_info, 0, 128) != hipSuccess || hipMemset(d.abort_dev, 0, 128) != hipSuccess ||
+      hipMemset(d.waits, 0, 16ull * WAIT_SLOTS) != hipSuccess ||
+      hipMemset(d.chain, 0, 8ull * (1 + 3 * LC_MAX) + 8) != hipSuccess ||
+      hipMemset(d.pend_head, 0xFF, 4ull * lines) != hipSuccess ||  // PEND_EMPTY
+      hipMemset(d.share_key, 0, 8ull * SHARE_CAP) != hipSuccess ||
+      hipMemset(d.share_refs, 0, 4ull * SHARE_CAP) != hipSuccess)
     return bail(AGILE_EHIP);
   std::vector<uint32_t> slots(nq);
   for (uint64_t i = 0; i < nq; ++i) slots[i] = (uint32_t)((i % cfg.qp_depth) << 2) | SLOT_EMPTY;
@@ -2653,6 +2962,68 @@ agile_status agile_embbag_forward_resident(agile_ctx ctx, const void* d_image, u
   return AGILE_OK;
 }
 
+agile_status agile_async_issue(agile_ctx ctx, agile_store store, const uint64_t* d_blocks, uint32_t n,
+                               void* const* d_bufs, void** d_ptrs, uint32_t* d_status, uint32_t flags,
+                               void* stream) {
+  agile_status s = check_usable(ctx);
+  if (s) return s;
+  if (store != ctx->store) return fail(ctx, AGILE_EINVAL, "async_issue: store is not open on this context");
+  if (n == 0) return AGILE_OK;
+  if (!d_blocks || !d_bufs || !d_ptrs || !d_status) return fail(ctx, AGILE_EINVAL, "async_issue: null pointer");
+  if (flags & ~AGILE_ISSUE_SHARE) return fail(ctx, AGILE_EINVAL, "async_issue: unknown flag");
+  hipStream_t hs = (hipStream_t)stream;
+  // a wave pins at most one chunk (64 lines) at a time
+  const uint64_t by_cache = std::max<uint64_t>(1, ctx->d.num_lines / 64);
+  uint32_t uw = (uint32_t)std::min<uint64_t>({(n + 63) / 64, (uint64_t)user_wave_cap(ctx, KIND_ISSUE), by_cache});
+  uw = (uw + WPB - 1) / WPB * WPB;
+  launch_t li = make_launch(ctx, uw, true);
+  hipLaunchKernelGGL(k_async_issue, dim3(li.service_blocks + uw / WPB), dim3(WG),
+                     lds_of(ctx, (const void*)k_async_issue), hs, ctx->d, li, d_blocks, n, d_bufs, d_ptrs, d_status,
+                     (uint32_t)(flags & AGILE_ISSUE_SHARE));
+  HIPCHK(ctx, hipGetLastError());
+  return sync_stream(ctx, hs);
+}
+
+agile_status agile_buffers_release(agile_ctx ctx, const uint64_t* d_blocks, const uint32_t* d_status, uint32_t n,
+                                   void* stream) {
+  agile_status s = check_usable(ctx);
+  if (s) return s;
+  if (n == 0) return AGILE_OK;
+  if (!d_blocks || !d_status) return fail(ctx, AGILE_EINVAL, "buffers_release: null pointer");
+  hipStream_t hs = (hipStream_t)stream;
+  hipLaunchKernelGGL(k_share_release, dim3((n + 255) / 256), dim3(256), 0, hs, ctx->d, d_blocks, d_status, n);
+  HIPCHK(ctx, hipGetLastError());
+  return sync_stream(ctx, hs);
+}
+
+agile_status agile_buffers_writeback(agile_ctx ctx, agile_store store, const uint64_t* d_blocks,
+                                     const void* const* d_srcs, uint32_t n, void* stream) {
+  agile_status s = check_usable(ctx);
+  if (s) return s;
+  if (store != ctx->store) return fail(ctx, AGILE_EINVAL, "buffers_writeback: store is not open on this context");
+  if (n == 0) return AGILE_OK;
+  if (!d_blocks || !d_srcs) return fail(ctx, AGILE_EINVAL, "buffers_writeback: null pointer");
+  hipStream_t hs = (hipStream_t)stream;
+  const uint64_t by_cache = std::max<uint64_t>(1, ctx->d.num_lines / 64);
+  uint32_t uw = (uint32_t)std::min<uint64_t>({(n + 63) / 64, (uint64_t)user_wave_cap(ctx, KIND_WBACK), by_cache});
+  uw = (uw + WPB - 1) / WPB * WPB;
+  launch_t li = make_launch(ctx, uw, true);
+  hipLaunchKernelGGL(k_buf_writeback, dim3(li.service_blocks + uw / WPB), dim3(WG),
+                     lds_of(ctx, (const void*)k_buf_writeback), hs, ctx->d, li, d_blocks, n, d_srcs);
+  HIPCHK(ctx, hipGetLastError());
+  return sync_stream(ctx, hs);
+}
+
+agile_status agile_share_reset(agile_ctx ctx) {
+  agile_status s = check_usable(ctx);
+  if (s) return s;
+  HIPCHK(ctx, hipDeviceSynchronize());
+  HIPCHK(ctx, hipMemset(ctx->d.share_key, 0, 8ull * SHARE_CAP));
+  HIPCHK(ctx, hipMemset(ctx->d.share_refs, 0, 4ull * SHARE_CAP));
+  HIPCHK(ctx, hipDeviceSynchronize());
+  return AGILE_OK;
+}
+
 static agile_status ensure_scratch(agile_ctx ctx, size_t need, hipStream_t hs) {
   if (need <= ctx->scratch_bytes) return AGILE_OK;
   HIPCHK(ctx, hipStreamSynchronize(hs));
@@ -2958,6 +3329,51 @@ agile_status agile_probe_copy(const void* src, const uint64_t* d_list, uint64_t 
   hipLaunchKernelGGL(k_probe_copy, dim3(blocks), dim3(WG), 0, (hipStream_t)stream, s, d_list, n, (uint8_t*)d_dst,
                      dst_blocks, per_wave);
   return hipGetLastError() == hipSuccess ? AGILE_OK : AGILE_EHIP;
+}
+
+// ---- lock-chain walker on a given wait state (diagnostics)
+__global__ void k_lc_walk(dev_ctx c, uint32_t n_waits, uint32_t w0, uint64_t what) {
+  // the given waits are current: stamp them now
+  for (uint32_t w = threadIdx.x; w < n_waits; w += 64)
+    if (ld_rlx(c.waits + 2 * w)) st_rlx(c.waits + 2 * w + 1, now());
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+  if (threadIdx.x == 0) lc_walk(c, w0, what);
+}
+
+agile_status agile_debug_lockchain(agile_ctx ctx, const uint64_t* waits, uint32_t n_waits, const uint32_t* lock_sets,
+                                   const uint32_t* lock_words, uint32_t n_locks, uint32_t start_wave,
+                                   uint64_t start_what, char* msg, uint32_t msg_len) {
+  agile_status s = check_usable(ctx);
+  if (s) return s;
+  if ((n_waits && !waits) || (n_locks && (!lock_sets || !lock_words)) || !msg || !msg_len)
+    return fail(ctx, AGILE_EINVAL, "lockchain: null pointer");
+  if (n_waits > WAIT_SLOTS || start_wave >= WAIT_SLOTS) return fail(ctx, AGILE_EINVAL, "lockchain: wave out of range");
+  for (uint32_t i = 0; i < n_locks; ++i)
+    if (lock_sets[i] >= ctx->d.num_sets) return fail(ctx, AGILE_EINVAL, "lockchain: set out of range");
+  HIPCHK(ctx, hipDeviceSynchronize());
+  if (n_waits) {
+    std::vector<uint64_t> w2(2ull * n_waits, 0);
+    for (uint32_t i = 0; i < n_waits; ++i) w2[2 * i] = waits[i];
+    HIPCHK(ctx, hipMemcpy(ctx->d.waits, w2.data(), 16ull * n_waits, hipMemcpyHostToDevice));
+  }
+  for (uint32_t i = 0; i < n_locks; ++i)
+    HIPCHK(ctx, hipMemcpy(ctx->d.set_lock + lock_sets[i], lock_words + i, 4, hipMemcpyHostToDevice));
+  HIPCHK(ctx, hipMemset(ctx->d.chain, 0, 8ull * (1 + 3 * LC_MAX) + 8));
+  hipLaunchKernelGGL(k_lc_walk, dim3(1), dim3(64), 0, nullptr, ctx->d, n_waits, start_wave, start_what);
+  HIPCHK(ctx, hipGetLastError());
+  HIPCHK(ctx, hipDeviceSynchronize());
+  std::vector<uint64_t> ch(1 + 3 * LC_MAX + 1, 0);
+  HIPCHK(ctx, hipMemcpy(ch.data(), ctx->d.chain, ch.size() * 8, hipMemcpyDeviceToHost));
+  // put the state back: no wait recorded, the given set locks free, no chain
+  if (n_waits) HIPCHK(ctx, hipMemset(ctx->d.waits, 0, 16ull * n_waits));
+  for (uint32_t i = 0; i < n_locks; ++i) HIPCHK(ctx, hipMemset(ctx->d.set_lock + lock_sets[i], 0, 4));
+  HIPCHK(ctx, hipMemset(ctx->d.chain, 0, 8ull * (1 + 3 * LC_MAX) + 8));
+  HIPCHK(ctx, hipDeviceSynchronize());
+  const std::string t = format_chain(ch.data());
+  snprintf(msg, msg_len, "%s", t.size() > 2 ? t.c_str() + 2 : "");
+  return AGILE_OK;
 }
 
 // ---- serving sessions: one persistent kernel fed through rings in pinned host memory

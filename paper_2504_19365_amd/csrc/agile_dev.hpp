@@ -158,6 +158,8 @@ enum : uint32_t {
   C_WORK_P1, C_WORK_P2, C_WORK_P3, C_WORK_P4, C_WORK_P5, C_WORK_P6, C_WORK_P7,
   // resident-hit pass: bags it deferred to the I/O pass
   C_DEFER,
+  // entries of the pending lists taken by the launch
+  C_PEND,
   // lookups of a launch whose bags went through the resident-hit pass, and of the bags
   // it deferred: the pass's own requests and hits are their difference (it counts
   // nothing itself; agile_get_stats adds the difference)
@@ -205,7 +207,21 @@ struct dev_ctx {
   uint64_t timeout_ticks;
   uint32_t flags;
   uint32_t _c0;
+  // lock-chain debugging (flag FLAG_LOCKCHAIN): what each spinning wave waits for, and
+  // the chain the first timed-out wave recorded
+  uint64_t* waits;  // [2 * WAIT_SLOTS]: per wave number, what it waits for and when it last looked
+  uint64_t* chain;  // [1 + 3 * LC_MAX]
+  // reads into user buffers (Sec. 3.4.1): each cache line's list of buffers waiting for
+  // its fill, the list entries of a launch, and the Share Table (block -> buffer)
+  uint32_t* pend_head;   // [num_lines]: first entry, PEND_EMPTY, or PEND_CLOSED once drained
+  uint64_t* pend;        // [2 * PEND_CAP]: destination address; next entry | block offset << 32
+  uint64_t* share_key;   // [SHARE_CAP]: block + 1, 0 = free
+  uint64_t* share_buf;   // [SHARE_CAP]: the owner's buffer
+  uint32_t* share_refs;  // [SHARE_CAP]: holders (owner + sharers); SHARE_BUSY while installing
 };
+constexpr uint32_t PEND_EMPTY = 0xFFFFFFFFu, PEND_CLOSED = 0xFFFFFFFEu;
+constexpr uint32_t PEND_CAP = 1u << 20;
+constexpr uint32_t SHARE_CAP = 1u << 18, SHARE_PROBES = 64, SHARE_BUSY = 0xFFFFFFFFu;
 
 struct launch_t {
   uint32_t service_blocks;  // leading workgroups that run service wavefronts
@@ -221,6 +237,23 @@ struct launch_t {
 // memory pipeline with the emulated controller or the completion service.
 constexpr uint32_t WG = 1024;
 constexpr uint32_t FLAG_PROFILE = 0x4;
+constexpr uint32_t FLAG_LOCKCHAIN = 0x8;
+constexpr uint32_t WAIT_SLOTS = 1u << 16;
+constexpr uint32_t LC_MAX = 16;
+// What a spinning wave waits for (error reports and lock-chain debugging): the kind in
+// the top byte, the object below it.
+enum : uint32_t {
+  W_SQ_SLOT = 0x01,  // a free slot of SQ q for ticket t: (q << 32) | t
+  W_SETLOCK = 0x0A,  // the lock of the set of store line id
+  W_WB = 0x0B,       // its own write-back of cache line index
+  W_FILL = 0x0D,     // the fill of cache line index
+  W_TICKET = 0x0E,   // a ticket's line (cache line index)
+  W_WAY = 0x0F,      // an evictable way (after EAGAIN)
+  W_CLAIM = 0x10     // a write claim of cache line index
+};
+__host__ __device__ constexpr uint64_t wi(uint32_t kind, uint64_t id) {
+  return ((uint64_t)kind << 56) | (id & ((1ull << 56) - 1));
+}
 // Token times of the IOPS cap are kept in 44.20 fixed point of the wall clock, modulo
 // 2^64: the integer part wraps after about two days of 100 MHz ticks, so a stored token
 // time is only used through its difference to now, and only while that lead is positive
@@ -255,6 +288,9 @@ __device__ __forceinline__ void count(const dev_ctx& c, uint32_t i, uint64_t v) 
   if (v) add_rlx(counter(c, i), v);
 }
 __device__ __forceinline__ bool profiling(const dev_ctx& c) { return (c.flags & FLAG_PROFILE) != 0; }
+__device__ __forceinline__ bool lockchain(const dev_ctx& c) { return (c.flags & FLAG_LOCKCHAIN) != 0; }
+// The wave's number in its launch.
+__device__ __forceinline__ uint32_t wave_gid() { return (blockIdx.x * blockDim.x + threadIdx.x) >> 6; }
 // Adds now() - t to timer i (lane 0 only, profile flag only); returns now().
 __device__ __forceinline__ uint64_t ptick(const dev_ctx& c, uint32_t i, uint64_t t) {
   if (!profiling(c)) return 0;
@@ -293,12 +329,25 @@ __device__ __forceinline__ void raise_error(const dev_ctx& c, uint32_t code, uin
 // woken more than ~12% late and thousands of waves that wait for queued I/O (milliseconds
 // when the device is saturated) do not flood the memory system that the controller's
 // copies share.
+__device__ void lc_walk(const dev_ctx& c, uint32_t w0, uint64_t what);
+// Lock-chain mode: a spinning wave notes what it waits for when it starts and the time
+// at every step, so a record whose time is older than LC_FRESH ticks (far more than the
+// longest back-off between steps) belongs to a wave that has stopped waiting.
+constexpr uint64_t LC_FRESH = 20000;  // 200 us
+__device__ __forceinline__ void lc_note(const dev_ctx& c, uint64_t info, bool first) {
+  const uint32_t w = wave_gid();
+  if (w < WAIT_SLOTS && lane() == ffs64(ballot(true))) {
+    if (first) st_rlx(c.waits + 2 * w, info);
+    st_rlx(c.waits + 2 * w + 1, now());
+  }
+}
 struct spin_t {
   uint64_t t0;
   uint32_t n;
   __device__ spin_t() : t0(now()), n(0) {}
   __device__ __forceinline__ bool step(const dev_ctx& c, uint64_t info) {
     ++n;
+    if (lockchain(c)) lc_note(c, info, n == 1);
     if (n < 7) {
       const uint32_t reps = 1u << (n - 1);
       for (uint32_t r = 0; r < reps; ++r) __builtin_amdgcn_s_sleep(4);
@@ -312,7 +361,10 @@ struct spin_t {
       if (aborted(c)) return false;
       if ((n & 63) == 0 && host_abort_poll(c)) return false;  // every few ms
       if (now() - t0 > c.timeout_ticks) {
-        if (lane() == ffs64(ballot(true))) raise_error(c, E_TIMEDOUT, info);
+        if (lane() == ffs64(ballot(true))) {
+          if (lockchain(c)) lc_walk(c, wave_gid(), info);
+          raise_error(c, E_TIMEDOUT, info);
+        }
         return false;
       }
     }
@@ -406,7 +458,7 @@ __device__ __forceinline__ bool submit(const dev_ctx& c, uint32_t q, bool want, 
     }
     if (!progress) {
       ++spins;
-      if (!sp.step(c, ((uint64_t)q << 32) | T)) return false;
+      if (!sp.step(c, wi(W_SQ_SLOT, ((uint64_t)q << 32) | T))) return false;
     }
   }
   if (spins && lane() == 0) count(c, C_SQ_SPINS, spins);
@@ -755,7 +807,8 @@ __device__ __forceinline__ void controller(const dev_ctx& c, const launch_t& li,
       while (now() < stop) __builtin_amdgcn_s_sleep(2);
     }
     if (aborted(c)) break;
-    if (now() - idle_since > c.timeout_ticks) {
+    // (a held command may legitimately wait out the emulated latency first)
+    if (now() - idle_since > c.timeout_ticks + c.lat_ticks) {
       if (ballot(pend)) raise_error(c, E_TIMEDOUT, 0xC1000000ull | cw);
       // idle for a whole timeout while users still run: keep waiting for them unless
       // the context was aborted (their own waits carry deadlines).
@@ -812,6 +865,34 @@ __device__ __forceinline__ void completion(const dev_ctx& c, const launch_t& li,
       if (nb) {
         fence_acq();
         fence_rel();
+      }
+      // user buffers waiting for lines this window fills: each fresh READ closes its
+      // line's pending list, and the whole wave copies the line's block into every buffer
+      // on it before the line turns READY (Sec. 3.4.1)
+      uint32_t plist = PEND_EMPTY, pline = 0;
+      if (fresh) {
+        const cqe_t* e = c.cq + (size_t)q * c.depth + (pos & dmask);
+        const uint32_t line = e->dw0;
+        if (e->dw1 == OPC_READ && line < c.num_lines) {
+          plist = __hip_atomic_exchange(c.pend_head + line, PEND_CLOSED, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+          pline = line;
+        }
+      }
+      if (ballot(plist < PEND_CLOSED)) {
+        for (uint64_t todo = ballot(plist < PEND_CLOSED); todo; todo &= todo - 1) {
+          const uint32_t l = ffs64(todo);
+          const uint8_t* src = line_ptr(c, rdlane(pline, l));
+          for (uint32_t en = rdlane(plist, l); en < PEND_CAP;) {
+            const uint64_t dst = uni64(ld_rlx(c.pend + 2 * en));
+            const uint64_t nx = uni64(ld_rlx(c.pend + 2 * en + 1));
+            const uint4* s4 = reinterpret_cast<const uint4*>(src + (nx >> 32));
+            uint4* d4 = reinterpret_cast<uint4*>((uintptr_t)dst);
+#pragma unroll
+            for (uint32_t i = 0; i < 4; ++i) d4[i * 64 + lane()] = s4[i * 64 + lane()];
+            en = (uint32_t)nx;
+          }
+        }
+        fence_rel();  // the copies before the lines turn READY
       }
       if (fresh) {
         {
@@ -909,6 +990,7 @@ __device__ __forceinline__ void run_service(const dev_ctx& c, const launch_t& li
       for (uint32_t p = 0; p < WORK_PARTS; ++p) st_rlx(counter(c, work_counter(p)), 0ull);
       // and the deferred count of the resident-hit pass that ran before this launch
       st_rlx(counter(c, C_DEFER), 0ull);
+      st_rlx(counter(c, C_PEND), 0ull);
       st_rel(counter(c, C_SVC_EXIT), 0ull);
     }
   }
@@ -990,9 +1072,10 @@ struct acq_t {
   uint32_t gen;
 };
 
-__device__ __forceinline__ bool try_lock(uint32_t* l) {
+// A set lock holds 1, or in lock-chain mode the holder's wave number + 2.
+__device__ __forceinline__ bool try_lock(const dev_ctx& c, uint32_t* l) {
   uint32_t z = 0;
-  return cas(l, z, 1u);
+  return cas(l, z, lockchain(c) ? wave_gid() + 2u : 1u);
 }
 __device__ __forceinline__ void unlock(uint32_t* l) { st_rel(l, 0u); }
 
@@ -1153,7 +1236,7 @@ __device__ __forceinline__ acq_t acquire_try(const dev_ctx& c, uint32_t line_id,
       }
     }
   }
-  if (!try_lock(c.set_lock + set)) return r;  // A_NONE: retry later
+  if (!try_lock(c, c.set_lock + set)) return r;  // A_NONE: retry later
   // re-probe under the lock: tags only change while the lock is held
   for (uint32_t w = 0; w < c.assoc; ++w) {
     const uint64_t m = ld_rlx(c.meta + base + w);
@@ -1183,6 +1266,7 @@ __device__ __forceinline__ acq_t acquire_try(const dev_ctx& c, uint32_t line_id,
                           ((uint64_t)((m_gen(m) + 1) & 0xFF) << GEN_SHIFT) | (RC_ONE * cnt) |
                           M_REF | ST_FETCHING;
       if (cas(c.meta + retake, m, nw)) {
+        st_rlx(c.pend_head + retake, PEND_EMPTY);
         r.res = A_MISS;
         r.idx = retake;
         r.gen = (m_gen(m) + 1) & 0xFF;
@@ -1220,6 +1304,7 @@ __device__ __forceinline__ acq_t acquire_try(const dev_ctx& c, uint32_t line_id,
              (RC_ONE * cnt) | M_REF | ST_FETCHING;
       }
       if (cas(c.meta + idx, m, nw)) {
+        if (!dirty) st_rlx(c.pend_head + idx, PEND_EMPTY);  // a new tenant: no waiting buffers yet
         st_rlx(c.hand + set, (h + 1) % c.assoc);
         r.res = dirty ? A_NEED_WB : A_MISS;
         r.idx = idx;
@@ -1349,12 +1434,12 @@ __device__ __forceinline__ bool chunk_issue(const dev_ctx& c, chunk_t& ch, uint3
       bool waiting = wb;
       while (ballot(waiting)) {
         if (waiting && m_state(ld_rlx(c.meta + idx)) != ST_WRITEBACK) waiting = false;
-        if (ballot(waiting) && !sw.step(c, 0xB0000000ull | idx)) return false;
+        if (ballot(waiting) && !sw.step(c, wi(W_WB, idx))) return false;
       }
       fence_acq();
     }
     if (ballot(pending && st == A_NONE)) {
-      if (!sp.step(c, 0xA0000000ull | ch.line_id)) return false;
+      if (!sp.step(c, wi(W_SETLOCK, rdlane(ch.line_id, ffs64(ballot(pending && st == A_NONE)))))) return false;
     }
   }
   const bool pin = lead && (npin ? st_ok(st) : st == A_MISS);
@@ -1402,7 +1487,7 @@ __device__ __forceinline__ bool chunk_wait(const dev_ctx& c, const chunk_t& ch, 
       if (m_state(m) != ST_FETCHING || m_tag(m) != ch.line_id || m_gen(m) != ch.gen) waiting = false;
     }
     if (!ballot(waiting)) break;
-    if (!sp.step(c, 0xD0000000ull | ch.idx)) return false;
+    if (!sp.step(c, wi(W_FILL, rdlane(ch.idx, ffs64(ballot(waiting)))))) return false;
   }
   if (acquire) fence_acq();
   wtick(c, WS_T_WAIT, t_wait);
@@ -1418,6 +1503,59 @@ __device__ __forceinline__ bool line_still_valid(const dev_ctx& c, uint32_t idx,
   const uint32_t st = m_state(m);
   return m_tag(m) == tag && m_gen(m) == gen &&
          (st == ST_READY || st == ST_DIRTY || st == ST_WRITEBACK);
+}
+
+// Lock-chain report (flag FLAG_LOCKCHAIN; the lock-chain debugger of Sec. 3.5, for this
+// library's waits): starting at wave w0 waiting for `what`, follows a set lock to the
+// wave that holds it and on to what that wave waits for, until a wait on something no
+// wave holds (a fill, a write-back, an SQ slot, a free way), a wave that is not waiting,
+// or a wave already in the chain (a cycle).  Each hop records (wave, what, the object's
+// word: the lock word, the line's metadata or the slot word) in c.chain; the first
+// report of a launch wins.  One lane calls it.
+__device__ void lc_walk(const dev_ctx& c, uint32_t w0, uint64_t what) {
+  uint64_t z = 0;
+  if (!cas(c.chain, z, 1ull)) return;
+  uint32_t w = w0, n = 0;
+  uint64_t seen[LC_MAX];
+  bool cycle = false;
+  while (n < LC_MAX) {
+    const uint32_t kind = (uint32_t)(what >> 56);
+    const uint64_t id = what & ((1ull << 56) - 1);
+    uint64_t word = 0;
+    uint32_t next = ~0u;
+    if (kind == W_SETLOCK) {
+      word = ld_rlx(c.set_lock + set_of(c, (uint32_t)id));
+      if (word >= 2) next = (uint32_t)word - 2;
+    } else if ((kind == W_WB || kind == W_FILL || kind == W_TICKET || kind == W_CLAIM) && id < c.num_lines) {
+      word = ld_rlx(c.meta + id);
+    } else if (kind == W_SQ_SLOT && (id >> 32) < c.num_qp) {
+      word = ld_rlx(c.slot + (size_t)(id >> 32) * c.depth + ((uint32_t)id & (c.depth - 1)));
+    }
+    st_rlx(c.chain + 1 + 3 * n, (uint64_t)w);
+    st_rlx(c.chain + 2 + 3 * n, what);
+    st_rlx(c.chain + 3 + 3 * n, word);
+    seen[n] = w;
+    ++n;
+    if (next == ~0u || next >= WAIT_SLOTS) break;
+    for (uint32_t k = 0; k < n; ++k)
+      if (seen[k] == next) cycle = true;
+    if (cycle) {
+      st_rlx(c.chain + 1 + 3 * n, (uint64_t)next);  // the wave the cycle returns to
+      break;
+    }
+    w = next;
+    what = ld_rlx(c.waits + 2 * w);
+    if (what && now() - ld_rlx(c.waits + 2 * w + 1) > LC_FRESH) what = 0;
+    if (!what) {  // the holder is not waiting: record it and stop
+      st_rlx(c.chain + 1 + 3 * n, (uint64_t)w);
+      st_rlx(c.chain + 2 + 3 * n, 0ull);
+      st_rlx(c.chain + 3 + 3 * n, 0ull);
+      ++n;
+      break;
+    }
+  }
+  fence_rel();
+  st_rlx(c.chain, (1ull << 63) | ((uint64_t)n << 1) | (cycle ? 1ull : 0ull));
 }
 
 // Drops the pins the chunk holds (leaders only).
