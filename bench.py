@@ -24,6 +24,7 @@ import time
 import numpy as np
 
 HBM_PEAK_GBS = 8000.0
+PREFETCH = "prefetch"  # run() mode: asynchronous with next-batch prefetch
 
 
 def log(*a):
@@ -31,7 +32,7 @@ def log(*a):
 
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
-TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_embbag_dlrm_16GiB_traffic.md")
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_embbag_pf_dlrm_16GiB_traffic.md")
 HIT_TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_embbag_dlrm_hit_replay_traffic.md")
 KERNEL_SOURCES = ("paper_2504_19365_amd/csrc/agile.hip", "paper_2504_19365_amd/csrc/agile_dev.hpp",
                   "include/agile.h")
@@ -78,8 +79,10 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--profile-only", nargs="?", const="step", default=None,
-                    choices=("step", "hit", "bwd", "randread", "devices", "graph"),
-                    help="for profilers: 'step' runs the warm-up and timed steps only, 'hit' "
+                    choices=("step", "step_async", "hit", "bwd", "randread", "devices", "graph"),
+                    help="for profilers: 'step' runs the warm-up and timed steps only "
+                         "('step_async': the same in the asynchronous mode without the "
+                         "next-batch prefetch), 'hit' "
                          "the hit-path replay only, 'bwd' / 'randread' / 'devices' / 'graph' that "
                          "measurement only")
     ap.add_argument("--extras", default="serve,randread,devices,bwd,graph",
@@ -585,25 +588,37 @@ def main():
     cum = gen.zipf_cum(rows, 1.05)
     nb = args.warmup + args.steps
     batches = []
-    for n in range(nb):
+    # one batch more than the steps: the one the last timed step of the prefetch mode
+    # prefetches (so that every prefetch-mode step reads one batch, as every other does)
+    for n in range(nb + 1):
         off, idx = gen.embbag_batch(cum, B, T, 1, 80, seed=1000 + n)
         batches.append((torch.from_numpy(off).cuda(), torch.from_numpy(idx).cuda(), idx.size))
-    outs = [torch.empty((B * T, dim), dtype=torch.float32, device="cuda") for _ in range(nb)]
+    outs = [torch.empty((B * T, dim), dtype=torch.float32, device="cuda") for _ in range(nb + 1)]
     stream = torch.cuda.current_stream()
 
-    def run(mode, K, which, time_each=True):
-        """Runs the given batch indices; returns per-launch ms (HIP events on the launch
-        stream) and the wall time of the whole sequence."""
+    def run(mode, K, which, time_each=True, nxt=None):
+        """Runs the given batch indices; returns per-call ms (HIP events on the launch
+        stream) and the wall time of the whole sequence.  mode PREFETCH: each call also
+        prefetches the batch after it in `which` (after the last one, batch `nxt`, if
+        any)."""
         evs = []
         torch.cuda.synchronize()
         w0 = time.perf_counter()
-        for i in which:
+        for k, i in enumerate(which):
             off, idx, n = batches[i]
             if time_each:
                 e0 = torch.cuda.Event(enable_timing=True)
                 e1 = torch.cuda.Event(enable_timing=True)
                 e0.record(stream)
-            ctx.embbag_forward(tb, idx, off, B, K, outs[i], mode=mode)
+            if mode == PREFETCH:
+                j = which[k + 1] if k + 1 < len(which) else nxt
+                if j is None:
+                    ctx.embbag_forward_prefetch(tb, idx, off, B, K, outs[i], None, None, 0)
+                else:
+                    ctx.embbag_forward_prefetch(tb, idx, off, B, K, outs[i], batches[j][1],
+                                                batches[j][0], B)
+            else:
+                ctx.embbag_forward(tb, idx, off, B, K, outs[i], mode=mode)
             if time_each:
                 e1.record(stream)
                 evs.append((e0, e1))
@@ -691,29 +706,53 @@ def main():
         hctx.shutdown()
         return
 
-    # ---- timed step: asynchronous mode
-    cold()
-    run(agile.MODE_ASYNC, args.K, warm_ids)
-    s0 = ctx.stats()
-    ms_async, wall_async = run(agile.MODE_ASYNC, args.K, timed_ids)
-    s1 = ctx.stats()
-    out_async = [outs[i].clone() for i in timed_ids[-2:]]
-    reads = s1["read_cmds"] - s0["read_cmds"]
-    hits = s1["hits"] - s0["hits"]
-    misses = s1["misses"] - s0["misses"]
-    log(f"async: {np.mean(ms_async):.2f} ms/step, reads {reads}, hits {hits}, misses {misses}")
+    # ---- timed step: the asynchronous mode of Sec. 4.3's DLRM runs, each step computing
+    # its batch while the next batch is prefetched into the cache.  The warm-up ends
+    # with the prefetch of the first timed batch and the last timed step prefetches the
+    # batch after the timed ones, so every timed step reads one batch through the store,
+    # as a step of the other modes does.
+    def aligned(mode, warm, ids):
+        """(warm-up, timed) batch lists of a mode, aligned so that every mode's timed
+        calls read the same batches through the store after the same history: the
+        prefetch mode computes `ids` and reads the batch after each; the other modes
+        compute, and read, the batches one later."""
+        if mode == PREFETCH:
+            return warm, ids
+        return warm + ids[:1], ids[1:] + [ids[-1] + 1]
+
+    def timed(mode):
+        w, ids = aligned(mode, warm_ids, timed_ids)
+        cold()
+        run(mode, args.K, w, nxt=ids[0])
+        a0 = ctx.stats()
+        ms, _ = run(mode, args.K, ids, nxt=ids[-1] + 1)
+        a1 = ctx.stats()
+        st = {k: a1[k] - a0[k] for k in ("read_cmds", "hits", "misses")}
+        st["lookups"] = sum(batches[i][2] for i in ids)
+        return ms, st
+
+    step_mode = PREFETCH if args.profile_only != "step_async" else agile.MODE_ASYNC
+    ms_step_l, st_step = timed(step_mode)
+    out_step = [outs[i].clone() for i in timed_ids[-2:]]
+    reads, hits, misses = st_step["read_cmds"], st_step["hits"], st_step["misses"]
+    log(f"async + next-batch prefetch: {np.mean(ms_step_l):.2f} ms/step, reads {reads}, "
+        f"hits {hits}, demand misses {misses}")
     if args.profile_only:
-        print(json.dumps({"profile_only": True, "ms_per_step": float(np.mean(ms_async))}))
+        print(json.dumps({"profile_only": args.profile_only,
+                          "ms_per_step": float(np.mean(ms_step_l))}))
         return
 
-    # ---- synchronous mode on identical inputs, same cold start and warmup
-    cold()
-    run(agile.MODE_SYNC, args.K, warm_ids)
-    s2 = ctx.stats()
-    ms_sync, wall_sync = run(agile.MODE_SYNC, args.K, timed_ids)
-    s3 = ctx.stats()
-    same = all(torch.equal(a, outs[i]) for a, i in zip(out_async, timed_ids[-2:]))
-    log(f"sync: {np.mean(ms_sync):.2f} ms/step; outputs identical: {same}")
+    # ---- the same inputs and cold start, the timed calls reading the same batches after
+    # the same history (see aligned): asynchronous with chunk lookahead only (no
+    # prefetch across batches), and synchronous
+    ms_async, st_async = timed(agile.MODE_ASYNC)
+    same_async = all(torch.equal(a, outs[i]) for a, i in zip(out_step, timed_ids[-2:]))
+    log(f"async, chunk lookahead only: {np.mean(ms_async):.2f} ms/step, reads "
+        f"{st_async['read_cmds']}; outputs identical: {same_async}")
+    ms_sync, st_sync = timed(agile.MODE_SYNC)
+    same = all(torch.equal(a, outs[i]) for a, i in zip(out_step, timed_ids[-2:]))
+    log(f"sync: {np.mean(ms_sync):.2f} ms/step, reads {st_sync['read_cmds']}; "
+        f"outputs identical: {same}")
 
     # ---- parity on sampled bags against the oracle (K of the timed step)
     import oracle
@@ -773,17 +812,23 @@ def main():
         """Compute-inclusive time of a batch (mean over `ids`) with every row a hit."""
         return float(np.mean([hit_run(K, 3, waves, bi) for bi in ids]))
 
-    def pair(K, ids, warm, waves=0):
+    def pair(K, ids, warm, waves=0, prefetch=False):
         res = {}
         ctx.set_max_user_waves(waves)
-        for mode, name in ((agile.MODE_SYNC, "sync"), (agile.MODE_ASYNC, "async")):
+        modes = [(agile.MODE_SYNC, "sync"), (agile.MODE_ASYNC, "async")]
+        if prefetch:
+            modes.append((PREFETCH, "prefetch"))
+        both = ids[1:]  # batches every mode computes in its timed calls
+        for mode, name in modes:
+            w, t = aligned(mode, warm, ids) if prefetch else (warm, ids)
             cold()
-            run(mode, K, warm, time_each=False)
-            ms, _ = run(mode, K, ids)
+            run(mode, K, w, time_each=False, nxt=t[0])
+            ms, _ = run(mode, K, t, nxt=t[-1] + 1)
             res[name] = float(np.mean(ms))
-            res[name + "_out"] = [outs[i].clone() for i in ids]
+            res[name + "_out"] = [outs[i].clone() for i in both]
         ctx.set_max_user_waves(0)
-        res["identical"] = all(torch.equal(a, b) for a, b in zip(res["sync_out"], res["async_out"]))
+        res["identical"] = all(torch.equal(a, b) for _, name in modes[1:]
+                               for a, b in zip(res["sync_out"], res[name + "_out"]))
         return res
 
     sweep = []
@@ -804,7 +849,7 @@ def main():
                 log(f"K_bal = {K} (I/O {t_io:.2f} ms, {per_k * 1e3:.3f} us per unit of K)")
             else:
                 K = int(k)
-            res = pair(K, ids3, warm_ids[:1])
+            res = pair(K, ids3, warm_ids[:1], prefetch=True)
             if K == 0:
                 t_io = res["sync"]
             comp = t_hit(K)
@@ -813,10 +858,14 @@ def main():
             bound = 1 + ctc if ctc <= 1 else 1 + 1 / ctc
             sweep.append({"K": K, "balanced": k == "bal", "sync_ms": round(res["sync"], 3),
                           "async_ms": round(res["async"], 3),
-                          "speedup": round(res["sync"] / res["async"], 3), "ctc": round(ctc, 4),
+                          "speedup": round(res["sync"] / res["async"], 3),
+                          "async_prefetch_ms": round(res["prefetch"], 3),
+                          "speedup_prefetch": round(res["sync"] / res["prefetch"], 3),
+                          "ctc": round(ctc, 4),
                           "eq1_bound": round(bound, 3), "identical": res["identical"]})
             log(f"full GPU K={K}: sync {res['sync']:.2f} async {res['async']:.2f} "
-                f"speedup {res['sync'] / res['async']:.3f} ctc {ctc:.3f} bound {bound:.3f} "
+                f"(x{res['sync'] / res['async']:.3f}) async+prefetch {res['prefetch']:.2f} "
+                f"(x{res['sync'] / res['prefetch']:.3f}) ctc {ctc:.3f} bound {bound:.3f} "
                 f"identical {res['identical']}")
 
     # ---- thread-level overlap (Sec. 4.2): one 1024-thread group (16 wavefronts) for both
@@ -902,19 +951,21 @@ def main():
         if "graph" in wanted:
             extras["graph"] = measure_graph(agile, gen, oracle, args.graph_scale, log)
 
-    ms_step = float(np.mean(ms_async))
+    ms_step = float(np.mean(ms_step_l))
     default_workload = (args.K == 0 and rows == 4194304 and T == 8 and B == 2048
                         and args.cache_gib == 2.0)
     traffic = committed_traffic() if default_workload else None
-    rows_per_s = lookups_timed / (sum(ms_async) * 1e-3)
-    iops = reads / (sum(ms_async) * 1e-3)
+    rows_per_s = lookups_timed / (sum(ms_step_l) * 1e-3)
+    iops = reads / (sum(ms_step_l) * 1e-3)
     cap_iops = 1.5e6
     store_peak_gbs = cap_iops * 4096 / 1e9
     algo_bytes = (lookups_timed * (dim * 4 + 8) + len(timed_ids) * B * T * (dim * 4 + 8))
-    achieved_hbm = algo_bytes / (sum(ms_async) * 1e-3) / 1e9
+    achieved_hbm = algo_bytes / (sum(ms_step_l) * 1e-3) / 1e9
     rec = {
         "metric": "embedding rows/s (DLRM-style embedding-bag forward, async, through the "
                   "emulated NVMe store and HBM software cache)",
+        "mode": "async with next-batch prefetch (each step computes its batch while the next "
+                "one is prefetched)",
         "value": round(rows_per_s, 1),
         "unit": "rows/s",
         "n_gpus": 1,
@@ -929,12 +980,17 @@ def main():
         "config": {"workload": f"embbag fwd {T} tables x {rows} x {dim} fp32 (16 GiB pinned "
                                f"store, 80us/cmd, 1.5M IOPS cap), {args.cache_gib} GiB 16-way "
                                f"cache, 16 QPs x 1024, batch {B}x{T} bags len U[1,80] "
-                               f"Zipf(1.05), K={args.K}, async",
+                               f"Zipf(1.05), K={args.K}, async (next-batch prefetch)",
                    "global_batch": B, "tables": T, "rows": rows, "dim": dim, "K": args.K},
         "sync": {"ms_per_step": round(float(np.mean(ms_sync)), 3),
-                 "rows_per_s": round(lookups_timed / (sum(ms_sync) * 1e-3), 1),
+                 "rows_per_s": round(st_sync["lookups"] / (sum(ms_sync) * 1e-3), 1),
                  "async_over_sync": round(float(np.mean(ms_sync)) / ms_step, 3),
-                 "outputs_identical": same},
+                 "read_cmds": st_sync["read_cmds"], "outputs_identical": same},
+        "async_chunk_lookahead_only": {
+            "ms_per_step": round(float(np.mean(ms_async)), 3),
+            "rows_per_s": round(st_async["lookups"] / (sum(ms_async) * 1e-3), 1),
+            "over_sync": round(float(np.mean(ms_sync)) / float(np.mean(ms_async)), 3),
+            "read_cmds": st_async["read_cmds"], "outputs_identical": same_async},
         "oracle_parity_sampled": parity,
         "store_roofline": {"miss_iops": round(iops, 1), "cap_iops": cap_iops,
                            "frac": round(iops / cap_iops, 4),
@@ -961,7 +1017,7 @@ def main():
                      "traffic_unit": "HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, scaled)",
                      "algorithmic_bytes_per_launch": int(algo_bytes / len(timed_ids)),
                      "hbm_gbs_of_algorithmic_bytes": round(achieved_hbm, 3),
-                     "kernel": "k_embbag<2>",
+                     "kernel": "k_embbag_pf<2>",
                      "note": "achieved = 4 KiB READs per second of the timed launches; the "
                              "peak is the emulated store's 1.5M IOPS x 4 KiB; the same "
                              "kernel's HBM-bound regime is roofline_hit"},

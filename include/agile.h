@@ -322,6 +322,29 @@ agile_status agile_embbag_forward(agile_ctx ctx, agile_store store, const agile_
                                   const int64_t* d_idx, const int64_t* d_off, uint64_t B,
                                   uint32_t K, uint32_t mode, float* d_out, void* stream);
 
+/* The asynchronous mode of Sec. 4.3's DLRM runs: this batch is computed while the next
+ * batch's data is prefetched into the cache (Listing 1's prefetch(), Sec. 3.5), so the
+ * store works on batch n+1 while the GPU computes batch n.  Computes exactly what
+ * agile_embbag_forward computes for (d_idx, d_off, B, K) into d_out (bit-identical, any
+ * mode), and requests every line of the next batch (d_next_idx, d_next_off, B_next: the
+ * same layout and tables) that is neither resident nor in flight, without pinning it: a
+ * set with no evictable way drops the request, a row outside the store is skipped, and a
+ * prefetched line may be evicted again before it is used (the next call then reads it on
+ * demand; results never depend on the prefetch).  When the call's work on the stream has
+ * completed, so have all its prefetch reads.  B_next == 0 prefetches nothing (the call is
+ * then agile_embbag_forward in AGILE_MODE_ASYNC); B == 0 only prefetches (d_idx, d_off and
+ * d_out may then be NULL).  d_next_idx may be NULL when every next bag is empty.
+ * Stream-ordered, one launch: the service wavefronts, up to 64 prefetch wavefronts that
+ * submit the next batch's reads and then compute, and every other wavefront computing
+ * this batch's bags, each served from resident lines where it can be and through the
+ * cache and queues from where it cannot (the same wave count as the I/O launch of
+ * agile_embbag_forward).  No host synchronisation, allocation or memset.  With
+ * AGILE_F_SERIALIZED nothing is prefetched.  Errors as for agile_embbag_forward. */
+agile_status agile_embbag_forward_prefetch(agile_ctx ctx, agile_store store, const agile_tables* tb,
+                                           const int64_t* d_idx, const int64_t* d_off, uint64_t B,
+                                           uint32_t K, float* d_out, const int64_t* d_next_idx,
+                                           const int64_t* d_next_off, uint64_t B_next, void* stream);
+
 /* ---------------------------------------------------------------- diagnostics ------
  * For tests and tools; not part of the I/O path. */
 

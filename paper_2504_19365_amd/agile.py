@@ -118,6 +118,8 @@ def lib():
             "agile_gather": (st, [vp, vp, C.POINTER(Tables), vp, u64, u32, vp, vp]),
             "agile_embbag_forward": (st, [vp, vp, C.POINTER(Tables), vp, vp, u64, u32, u32, vp,
                                           vp]),
+            "agile_embbag_forward_prefetch": (st, [vp, vp, C.POINTER(Tables), vp, vp, u64, u32,
+                                                   vp, vp, vp, u64, vp]),
             "agile_debug_trace": (st, [vp, vp, vp, vp, u64, vp, vp, vp]),
             "agile_embbag_backward_sgd": (st, [vp, vp, C.POINTER(Tables), vp, vp, u64, u64, vp,
                                                C.c_float, vp]),
@@ -443,6 +445,16 @@ class Context:
         self._check(lib().agile_embbag_forward(self.h, store.handle, C.byref(tb), _ptr(idx),
                                                _ptr(off), B, K, mode, _ptr(out), _stream(stream)),
                     "agile_embbag_forward")
+
+    def embbag_forward_prefetch(self, tb: Tables, idx, off, B: int, K: int, out, next_idx,
+                                next_off, B_next: int, stream=None, store=None):
+        """Computes this batch (as embbag_forward) while the lines of the next batch
+        (next_idx, next_off, B_next samples) are prefetched into the cache, unpinned."""
+        store = store or self.store
+        self._check(lib().agile_embbag_forward_prefetch(
+            self.h, store.handle, C.byref(tb), _ptr(idx), _ptr(off), B, K, _ptr(out),
+            _ptr(next_idx), _ptr(next_off), B_next, _stream(stream)),
+            "agile_embbag_forward_prefetch")
 
     def embbag_backward_sgd(self, tb: Tables, idx, off, B: int, grad, lr: float, stream=None,
                             store=None):

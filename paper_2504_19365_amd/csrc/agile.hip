@@ -677,24 +677,27 @@ constexpr uint32_t HIT_WAVES = 1;
 struct alignas(16) hit_lds_t {
   uint8_t b[HIT_WAVES][PROBE_LDS];
 };
+// From this K on, each round of rows is checked right after it has loaded and before it
+// is computed, so that a line evicted during a long computation costs nothing (the rows
+// already read stay valid); below it one check per chunk, after every row has been used,
+// keeps the loads of consecutive rounds in flight together.
+constexpr uint32_t EARLY_CHECK_K = 256;
+
+// Serves lookups [j0, j1) of bag g from resident lines into acc, chunk by chunk, and
+// writes the bag's output when it gets to the end.  Returns the first lookup it did not
+// consume: a chunk with a line that is absent or still being fetched stops it at the
+// chunk's start, a row whose line changed tenant while it was read at that row's round
+// (K >= EARLY_CHECK_K) or at the chunk's start (smaller K); acc then holds exactly the
+// lookups before that position.
 template <int VPL>
-__device__ __forceinline__ bool hit_bag(const dev_ctx& c, const embbag_args& a, uint64_t g, uint8_t* lds) {
+__device__ __forceinline__ int64_t hit_bag_part(const dev_ctx& c, const embbag_args& a, uint64_t g, uint8_t* lds,
+                                                float (&acc)[VPL], int64_t j0, int64_t j1) {
   const uint32_t d0 = lane() * VPL;
   const bool mine = d0 < a.dim;
   constexpr uint32_t R = rows_per_round<VPL>();
   const uint64_t lmask = (1ull << c.line_shift) - 1;
-  int64_t j0, j1;
-  if (a.gather) {
-    j0 = (int64_t)g * 64;
-    j1 = ((int64_t)a.n < j0 + 64) ? (int64_t)a.n : j0 + 64;
-  } else {
-    j0 = a.off[g];
-    j1 = a.off[g + 1];
-  }
   const uint32_t t = a.gather ? 0u : (uint32_t)(g % a.T);
-  float acc[VPL];
-#pragma unroll
-  for (int v = 0; v < VPL; ++v) acc[v] = 0.0f;
+  const bool early = a.K >= EARLY_CHECK_K;
   for (int64_t j = j0; j < j1; j += 64) {
     const uint32_t n = (uint32_t)((j1 - j) < 64 ? (j1 - j) : 64);
     chunk_t ch;
@@ -716,14 +719,31 @@ __device__ __forceinline__ bool hit_bag(const dev_ctx& c, const embbag_args& a, 
     else if (ch.act)
       w = probe_set(c, base, ch.line_id, m);
     const bool hit = ch.act && w >= 0 && m_valid_data(m_state(m));
-    if (ballot(ch.act && !hit)) return false;
+    if (ballot(ch.act && !hit)) return j;
     ch.idx = base + (uint32_t)(w < 0 ? 0 : w);
     ch.gen = m_gen(m);
     if (ch.act && !(m & M_REF)) or_rlx(c.meta + ch.idx, M_REF);
     // each lane's row address, so a row costs two lane reads and one load
     const uint64_t raddr = (uint64_t)(uintptr_t)line_ptr(c, ch.idx) + ch.off;
-    // the rows in rounds of R, two rounds in flight, added as they arrive
     float va[R][VPL], vb[R][VPL];
+    if (early) {
+      for (uint32_t r = 0; r < n; r += R) {
+        const uint32_t gr = (n - r) < R ? (n - r) : R;
+        hit_load<VPL>(raddr, r, gr, d0, mine, va);
+        // the round's loads have completed before its lines are looked at again
+        __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
+        asm volatile("" ::: "memory");
+        const uint32_t src = (r + lane()) & 63;
+        const uint32_t vidx = shfl32(ch.idx, src), vtag = shfl32(ch.line_id, src), vgen = shfl32(ch.gen, src);
+        if (ballot(lane() < gr && !line_still_valid(c, vidx, vtag, vgen))) return j + r;
+        hit_use<VPL>(a, j + r, gr, d0, mine, va, acc);
+      }
+      continue;
+    }
+    float acc0[VPL];
+#pragma unroll
+    for (int v = 0; v < VPL; ++v) acc0[v] = acc[v];
+    // the rows in rounds of R, two rounds in flight, added as they arrive
     hit_load<VPL>(raddr, 0, n < R ? n : R, d0, mine, va);
     for (uint32_t r = 0; r < n;) {
       uint32_t gcur = (n - r) < R ? (n - r) : R;
@@ -744,10 +764,31 @@ __device__ __forceinline__ bool hit_bag(const dev_ctx& c, const embbag_args& a, 
     __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
     asm volatile("" ::: "memory");
     const bool bad = ch.act && !line_still_valid(c, ch.idx, ch.line_id, ch.gen);
-    if (ballot(bad)) return false;
+    if (ballot(bad)) {
+#pragma unroll
+      for (int v = 0; v < VPL; ++v) acc[v] = acc0[v];
+      return j;
+    }
   }
   if (!a.gather) write_bag<VPL>(c, a, (int64_t)g, acc);
-  return true;
+  return j1;
+}
+
+// The whole bag g from resident lines, or false (nothing written).
+template <int VPL>
+__device__ __forceinline__ bool hit_bag(const dev_ctx& c, const embbag_args& a, uint64_t g, uint8_t* lds) {
+  int64_t j0, j1;
+  if (a.gather) {
+    j0 = (int64_t)g * 64;
+    j1 = ((int64_t)a.n < j0 + 64) ? (int64_t)a.n : j0 + 64;
+  } else {
+    j0 = a.off[g];
+    j1 = a.off[g + 1];
+  }
+  float acc[VPL];
+#pragma unroll
+  for (int v = 0; v < VPL; ++v) acc[v] = 0.0f;
+  return hit_bag_part<VPL>(c, a, g, lds, acc, j0, j1) == j1;
 }
 
 // The resident-hit pass: bag g = workgroup * HIT_WAVES + wave.  It carries no service
@@ -760,6 +801,142 @@ __global__ __launch_bounds__(64 * HIT_WAVES, 4) void k_embbag_hit(dev_ctx c, emb
   if (g >= a.nbags) return;
   if (!hit_bag<VPL>(c, a, g, lds.b[threadIdx.x / 64]) && lane() == 0)
     list[add_rlx(counter(c, C_DEFER), 1ull)] = (uint32_t)g;
+}
+
+// ---- next-batch prefetch (Sec. 4.3's asynchronous DLRM mode: the data of the next epoch
+// is requested while the current one computes)
+// One launch carries the service wavefronts, a few prefetch wavefronts and the compute
+// loop over the current batch.  The prefetch wavefronts walk the next batch's lookups 64
+// at a time and claim the lines that are neither resident nor in flight without pinning
+// them (a full set drops the request): they never wait for data, only for queue slots,
+// so the store is kept busy by them while every other wavefront computes.  Once their
+// share is submitted they join the compute loop.  The compute loop takes whole bags
+// from work counters and serves each from resident lines as the resident-hit pass does
+// (optimistic reads, checked after loading); where that stops (a line absent or in
+// flight, or a line that changed tenant), the same wavefront goes on with the rest of
+// the bag through the cache and the queues (issue, wait, consume, as the I/O launch
+// does), so no bag waits for a second launch.
+struct pf_args {
+  const int64_t* idx;  // the next batch's lookups
+  const int64_t* off;  // its bag offsets [nbags + 1]
+  uint64_t nbags;      // its bags; 0: nothing to prefetch
+  uint64_t store_bytes;
+  uint64_t backlog;    // commands in flight (all queues) above which prefetching pauses
+  uint32_t waves;      // user wavefronts that prefetch before they compute
+  uint32_t _p0;
+};
+
+// The bag holding lookup j: the g with off[g] <= j < off[g + 1] (off[0] <= j < off[nb]).
+__device__ __forceinline__ uint64_t bag_of(const int64_t* off, uint64_t nb, int64_t j) {
+  uint64_t lo = 0, hi = nb;
+  while (hi - lo > 1) {
+    const uint64_t mid = (lo + hi) >> 1;
+    if (off[mid] <= j)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+__device__ __forceinline__ bool prefetch_wave(const dev_ctx& c, const embbag_args& a, const pf_args& p,
+                                              uint32_t w) {
+  const int64_t j_lo = p.off[0], j_hi = p.off[p.nbags];
+  const uint32_t q = w % c.num_qp;
+  const uint64_t lmask = (1ull << c.line_shift) - 1;
+  for (int64_t j0 = j_lo + (int64_t)w * 64; j0 < j_hi; j0 += (int64_t)p.waves * 64) {
+    chunk_t ch;
+    const int64_t j = j0 + lane();
+    ch.act = j < j_hi;
+    ch.pinned = false;
+    ch.line_id = 0;
+    ch.off = 0;
+    if (ch.act) {
+      const uint64_t g = bag_of(p.off, p.nbags, j);
+      const uint64_t byte = a.base_off + (g % a.T) * a.table_bytes + (uint64_t)p.idx[j] * a.row_bytes;
+      ch.act = byte < p.store_bytes;  // a hint: a row outside the store is not fetched
+      ch.line_id = (uint32_t)(byte >> c.line_shift);
+      ch.off = (uint32_t)(byte & lmask);
+    }
+    // the store serves its queues first come, first served: a bounded backlog keeps it
+    // busy while the reads that computing waves need now wait behind little of it
+    spin_t sp;
+    while (uni64(ld_rlx(counter(c, C_SUBMITTED))) - uni64(ld_rlx(counter(c, C_COMPLETED))) >= p.backlog)
+      if (!sp.step(c, wi(W_BACKLOG, p.backlog))) return false;
+    if (!chunk_issue(c, ch, q, false, PIN_PREFETCH)) return false;
+  }
+  return true;
+}
+
+// Lookups [j, j1) of bag g through the cache and the queues, one chunk at a time, added
+// to acc; writes the bag's output.  False on abort or time-out.
+template <int VPL>
+__device__ __forceinline__ bool io_rest(const dev_ctx& c, const embbag_args& a, uint32_t q, int64_t g, int64_t j,
+                                        int64_t j1, float (&acc)[VPL]) {
+  chunk_t cc, cn;
+  while (j < j1) {
+    desc_t d;
+    d.g = g;
+    d.j = j;
+    d.end = j1;
+    d.n = (uint32_t)((j1 - j) < 64 ? (j1 - j) : 64);
+    d.last = j + d.n == j1;
+    d.valid = true;
+    make_chunk(c, a, d, cc);
+    if (!chunk_issue(c, cc, q, true, PIN_NONE)) return false;
+    bool none_held = false;
+    if (!finish_chunk<VPL>(c, a, q, d, cc, acc, cn, none_held)) return false;
+    j += d.n;
+  }
+  return true;
+}
+
+// The compute loop over work counters: wave uw of nw starts in partition uw mod P
+// (P = min(WORK_PARTS, nw); bag g belongs to partition g mod P) and moves on when it is
+// used up.  The lookups that go through the queues are counted as such (and taken out
+// of the resident-hit total the launch adds).
+template <int VPL>
+__device__ __forceinline__ void pf_compute(const dev_ctx& c, const embbag_args& a, uint32_t uw, uint32_t nw) {
+  const uint32_t parts = nw < WORK_PARTS ? nw : WORK_PARTS;
+  const uint32_t q = uw % c.num_qp;
+  uint8_t* lds = probe_area();
+  for (uint32_t t = 0; t < parts;) {
+    const uint32_t pp = (uw + t) % parts;
+    uint64_t v = 0;
+    if (lane() == 0) v = add_rlx(counter(c, work_counter(pp)), 1ull);
+    const uint64_t g = rdlane64(v, 0) * parts + pp;
+    if (g >= a.nbags) {
+      ++t;
+      continue;
+    }
+    const int64_t j0 = a.off[g], j1 = a.off[g + 1];
+    float acc[VPL];
+#pragma unroll
+    for (int e = 0; e < VPL; ++e) acc[e] = 0.0f;
+    const int64_t j = hit_bag_part<VPL>(c, a, g, lds, acc, j0, j1);
+    if (j < j1) {
+      if (lane() == 0) wcount(WS_DEFLEN, (uint64_t)(j1 - j));
+      if (!io_rest<VPL>(c, a, q, (int64_t)g, j, j1, acc)) return;
+    }
+  }
+}
+
+template <int VPL>
+__global__ __launch_bounds__(WG) void k_embbag_pf(dev_ctx c, launch_t li, embbag_args a, pf_args p) {
+  if (blockIdx.x < li.service_blocks) {
+    run_service(c, li);
+    return;
+  }
+  user_wave_begin();
+  const uint32_t uw = (blockIdx.x - li.service_blocks) * WPB + threadIdx.x / 64;
+  if (uw == 0 && lane() == 0 && a.nbags)
+    add_rlx(counter(c, C_HIT_TOTAL), (uint64_t)(a.off[a.nbags] - a.off[0]));
+  if (uw < a.active_waves) {
+    bool ok = true;
+    if (uw < p.waves && p.nbags) ok = prefetch_wave(c, a, p, uw);
+    if (ok && a.nbags) pf_compute<VPL>(c, a, uw, a.active_waves);
+  }
+  user_wave_done(c, li);
 }
 
 // Embedding-bag forward over a copy of the tables resident in device memory: no cache,
@@ -2140,7 +2317,7 @@ namespace {
 constexpr int KIND_EMBBAG1 = 0, KIND_EMBBAG2 = 1, KIND_EMBBAG4 = 2, KIND_READ = 3, KIND_FLUSH = 4,
               KIND_TRACE = 5, KIND_BWD1 = 6, KIND_BWD2 = 7, KIND_BWD4 = 8, KIND_SERVE1 = 9,
               KIND_SERVE2 = 10, KIND_SERVE4 = 11, KIND_WRITE = 12, KIND_ISSUE = 13, KIND_WBACK = 14,
-              KIND_N = 15;
+              KIND_PF1 = 15, KIND_PF2 = 16, KIND_PF4 = 17, KIND_N = 18;
 
 agile_status fail(agile_ctx ctx, agile_status s, const std::string& msg) {
   if (ctx) ctx->last_error = msg;
@@ -2202,6 +2379,9 @@ int occupancy(agile_ctx ctx, int kind) {
     case KIND_SERVE1: f = (const void*)k_serve<1>; break;
     case KIND_SERVE2: f = (const void*)k_serve<2>; break;
     case KIND_SERVE4: f = (const void*)k_serve<4>; break;
+    case KIND_PF1: f = (const void*)k_embbag_pf<1>; break;
+    case KIND_PF2: f = (const void*)k_embbag_pf<2>; break;
+    case KIND_PF4: f = (const void*)k_embbag_pf<4>; break;
     default: f = (const void*)k_trace; break;
   }
   e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, f, WG, lds_of(ctx, f));
@@ -2284,6 +2464,7 @@ static std::string wait_text(uint64_t what, uint64_t word) {
                id, (unsigned long long)(word & 7), (unsigned long long)((word >> 4) & 0xFFFFF), (unsigned long long)(word >> 32));
       break;
     case W_WAY: snprintf(b, sizeof b, "an evictable way (after EAGAIN, object %llu)", id); break;
+    case W_BACKLOG: snprintf(b, sizeof b, "fewer than %llu commands in flight (prefetch)", id); break;
     case 0: snprintf(b, sizeof b, "nothing (running)"); break;
     default: snprintf(b, sizeof b, "0x%llx", (unsigned long long)what); break;
   }
@@ -2458,7 +2639,8 @@ agile_status agile_init(const agile_config* cfg_in, agile_ctx* out) {
                          (const void*)k_bfs_edges, (const void*)k_spmv, (const void*)k_bwd_sgd<1>,
                          (const void*)k_bwd_sgd<2>, (const void*)k_bwd_sgd<4>, (const void*)k_serve<1>,
                          (const void*)k_serve<2>, (const void*)k_serve<4>, (const void*)k_trace,
-                         (const void*)k_write_lines, (const void*)k_async_issue, (const void*)k_buf_writeback};
+                         (const void*)k_write_lines, (const void*)k_async_issue, (const void*)k_buf_writeback,
+                         (const void*)k_embbag_pf<1>, (const void*)k_embbag_pf<2>, (const void*)k_embbag_pf<4>};
     for (const void* f : fns) {
       hipFuncAttributes fa;
       memset(&fa, 0, sizeof(fa));
@@ -2831,14 +3013,20 @@ agile_status agile_get_info(agile_ctx ctx, agile_info* out) {
   return AGILE_OK;
 }
 
+// Wavefronts of a fused prefetch launch that prefetch before they compute: enough to keep
+// every queue pair's submissions going, few enough that almost every wavefront computes.
+constexpr uint32_t PF_WAVES = 64;
+
 static agile_status embbag_launch(agile_ctx ctx, agile_store store, const agile_tables* tb, const int64_t* d_idx,
                                   const int64_t* d_off, uint64_t B, uint64_t n, uint32_t K, uint32_t mode,
-                                  float* d_out, void* stream, bool gather) {
+                                  float* d_out, void* stream, bool gather, const int64_t* d_next_idx = nullptr,
+                                  const int64_t* d_next_off = nullptr, uint64_t B_next = 0) {
   agile_status s = check_usable(ctx);
   if (s) return s;
   if (store != ctx->store) return fail(ctx, AGILE_EINVAL, "workload: store is not open on this context");
   // d_idx may be NULL when every bag is empty (it is only read for existing lookups)
-  if (!tb || !d_out || (!gather && !d_off)) return fail(ctx, AGILE_EINVAL, "workload: null pointer");
+  // (a call that only prefetches, B == 0, needs no output or offsets)
+  if (!tb || ((gather || B) && (!d_out || (!gather && !d_off)))) return fail(ctx, AGILE_EINVAL, "workload: null pointer");
   if (tb->dim == 0 || tb->dim > 256 || tb->num_tables == 0 || tb->rows == 0)
     return fail(ctx, AGILE_EINVAL, "workload: dim must be 1..256, tables and rows non-zero");
   const uint64_t row_bytes = (uint64_t)tb->dim * 4;
@@ -2848,6 +3036,7 @@ static agile_status embbag_launch(agile_ctx ctx, agile_store store, const agile_
   if (tb->base_offset + table_bytes * tb->num_tables > store->bytes)
     return fail(ctx, AGILE_EINVAL, "workload: tables exceed the store");
   if (mode > AGILE_MODE_ASYNC) return fail(ctx, AGILE_EINVAL, "workload: bad mode");
+  if (B_next && !d_next_off) return fail(ctx, AGILE_EINVAL, "workload: null next-batch offsets");
   embbag_args a{};
   a.idx = d_idx;
   a.off = d_off;
@@ -2863,7 +3052,7 @@ static agile_status embbag_launch(agile_ctx ctx, agile_store store, const agile_
   a.K = K;
   a.mode = mode;
   a.gather = gather ? 1u : 0u;
-  if (a.nbags == 0) return AGILE_OK;
+  if (a.nbags == 0 && B_next == 0) return AGILE_OK;
   const int kind = tb->dim <= 64 ? KIND_EMBBAG1 : (tb->dim <= 128 ? KIND_EMBBAG2 : KIND_EMBBAG4);
   uint32_t uw, active;
   if (ctx->cfg.flags & AGILE_F_SERIALIZED) {
@@ -2880,12 +3069,47 @@ static agile_status embbag_launch(agile_ctx ctx, agile_store store, const agile_
   a.active_waves = active;
   const bool serial = (ctx->cfg.flags & AGILE_F_SERIALIZED) != 0;
   hipStream_t hs = (hipStream_t)stream;
+  if (B_next && !serial) {
+    // one fused launch: service, the next batch's prefetch and this batch's compute
+    // (with its misses served in the same launch); the same admission as the I/O
+    // launch, since a computing wave pins at most one chunk of its own misses
+    const int pkind = kind - KIND_EMBBAG1 + KIND_PF1;
+    const uint64_t by_cache = std::max<uint64_t>(1, ctx->d.num_lines / 128);
+    const uint32_t cap = (uint32_t)std::min<uint64_t>(user_wave_cap(ctx, pkind), by_cache);
+    pf_args p{};
+    p.idx = d_next_idx;
+    p.off = d_next_off;
+    p.nbags = B_next * tb->num_tables;
+    p.store_bytes = store->bytes;
+    p.waves = std::min<uint32_t>(PF_WAVES, cap);
+    {
+      // eight times the commands the store needs in flight to run at its cap (Little's
+      // law: IOPS x latency, per device), at least 2048, at most half of all queue slots
+      const double little = (double)ctx->cfg.iops_cap * (double)ctx->cfg.latency_ns * 1e-9;
+      const uint64_t slots = (uint64_t)ctx->cfg.num_qp * ctx->cfg.qp_depth;
+      p.backlog = std::max<uint64_t>(1, std::min<uint64_t>(slots / 2, std::max<uint64_t>(2048, (uint64_t)(8.0 * little * ctx->d.n_dev))));
+    }
+    embbag_args ap = a;
+    ap.mode = AGILE_MODE_ASYNC;
+    ap.active_waves = a.nbags ? cap : p.waves;
+    const uint32_t puw = (ap.active_waves + WPB - 1) / WPB * WPB;
+    const launch_t lp = make_launch(ctx, puw, true);
+    const dim3 pg(lp.service_blocks + puw / WPB);
+    if (kind == KIND_EMBBAG1)
+      hipLaunchKernelGGL(k_embbag_pf<1>, pg, dim3(WG), lds_of(ctx, (const void*)k_embbag_pf<1>), hs, ctx->d, lp, ap, p);
+    else if (kind == KIND_EMBBAG2)
+      hipLaunchKernelGGL(k_embbag_pf<2>, pg, dim3(WG), lds_of(ctx, (const void*)k_embbag_pf<2>), hs, ctx->d, lp, ap, p);
+    else
+      hipLaunchKernelGGL(k_embbag_pf<4>, pg, dim3(WG), lds_of(ctx, (const void*)k_embbag_pf<4>), hs, ctx->d, lp, ap, p);
+    HIPCHK(ctx, hipGetLastError());
+    return AGILE_OK;
+  }
   // the resident-hit pass first (see hit_bag), when the deferred list can hold every
   // bag and the wave count is not capped (a cap applies to the I/O launch, which then
   // runs every bag); the I/O launch then runs only the bags the pass deferred.  Both
   // launches are stream ordered; the I/O launch's last service wavefront clears the
   // deferred count, so the pair can be captured in a graph and replayed.
-  if (!serial && !ctx->cfg.max_user_waves && a.nbags <= ctx->defer_cap) {
+  if (!serial && !ctx->cfg.max_user_waves && a.nbags <= ctx->defer_cap && a.nbags) {
     const dim3 hg((uint32_t)((a.nbags + HIT_WAVES - 1) / HIT_WAVES)), hb(64 * HIT_WAVES);
     if (kind == KIND_EMBBAG1)
       hipLaunchKernelGGL(k_embbag_hit<1>, hg, hb, 0, hs, ctx->d, a, ctx->defer_list);
@@ -2896,6 +3120,7 @@ static agile_status embbag_launch(agile_ctx ctx, agile_store store, const agile_
     HIPCHK(ctx, hipGetLastError());
     a.list = ctx->defer_list;
   }
+  if (a.nbags == 0) return AGILE_OK;
   launch_t li = make_launch(ctx, uw, true);
   const dim3 grid(li.service_blocks + uw / WPB);
   if (kind == KIND_EMBBAG1)
@@ -2919,6 +3144,15 @@ agile_status agile_embbag_forward(agile_ctx ctx, agile_store store, const agile_
                                   void* stream) {
   if (B == 0) return check_usable(ctx);
   return embbag_launch(ctx, store, tb, d_idx, d_off, B, 0, K, mode, d_out, stream, false);
+}
+
+agile_status agile_embbag_forward_prefetch(agile_ctx ctx, agile_store store, const agile_tables* tb,
+                                           const int64_t* d_idx, const int64_t* d_off, uint64_t B, uint32_t K,
+                                           float* d_out, const int64_t* d_next_idx, const int64_t* d_next_off,
+                                           uint64_t B_next, void* stream) {
+  if (B == 0 && B_next == 0) return check_usable(ctx);
+  return embbag_launch(ctx, store, tb, d_idx, d_off, B, 0, K, AGILE_MODE_ASYNC, d_out, stream, false,
+                       d_next_idx, d_next_off, B_next);
 }
 
 agile_status agile_embbag_forward_resident(agile_ctx ctx, const void* d_image, uint64_t image_bytes,

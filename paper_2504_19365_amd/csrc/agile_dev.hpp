@@ -249,7 +249,8 @@ enum : uint32_t {
   W_FILL = 0x0D,     // the fill of cache line index
   W_TICKET = 0x0E,   // a ticket's line (cache line index)
   W_WAY = 0x0F,      // an evictable way (after EAGAIN)
-  W_CLAIM = 0x10     // a write claim of cache line index
+  W_CLAIM = 0x10,    // a write claim of cache line index
+  W_BACKLOG = 0x11   // the store's backlog to shrink below `id` commands (prefetch)
 };
 __host__ __device__ constexpr uint64_t wi(uint32_t kind, uint64_t id) {
   return ((uint64_t)kind << 56) | (id & ((1ull << 56) - 1));
@@ -1211,13 +1212,15 @@ __device__ __forceinline__ int probe_staged(const dev_ctx& c, bool want, uint32_
 
 // `cnt` == 0 asks for an unpinned hit: a resident or in-flight line is reported with its
 // generation and not pinned (the caller validates after reading); a miss still pins its
-// claim with one reference.
-__device__ __forceinline__ acq_t acquire_try(const dev_ctx& c, uint32_t line_id, uint32_t cnt, int retake) {
+// claim with one reference, unless !pin_miss (a prefetch: the claim is FETCHING with no
+// reference, which no eviction takes, and once filled it is an ordinary unpinned line).
+__device__ __forceinline__ acq_t acquire_try(const dev_ctx& c, uint32_t line_id, uint32_t cnt, int retake,
+                                             bool pin_miss = true) {
   acq_t r{A_NONE, 0, 0};
   const uint32_t set = set_of(c, line_id);
   const uint32_t base = set * c.assoc;
   const bool pin_hits = cnt != 0;
-  if (cnt == 0) cnt = 1;
+  if (cnt == 0 && pin_miss) cnt = 1;
   if (retake < 0) {
     // lock-free probe
     uint64_t m = 0;
@@ -1333,7 +1336,9 @@ __device__ __forceinline__ acq_t acquire_try(const dev_ctx& c, uint32_t line_id,
 enum : uint32_t {
   PIN_LINE = 0,  // one pin per distinct line (writers, serialized traces)
   PIN_EACH = 1,  // one pin per lane (host tickets)
-  PIN_NONE = 2   // optimistic readers: hits are not pinned, a wave's own misses are
+  PIN_NONE = 2,  // optimistic readers: hits are not pinned, a wave's own misses are
+  PIN_PREFETCH = 3  // prefetch (Listing 1's prefetch()): nothing is pinned, a full set
+                    // drops the lane's request, and the caller neither waits nor releases
 };
 
 struct chunk_t {
@@ -1377,7 +1382,8 @@ __device__ __forceinline__ bool chunk_issue(const dev_ctx& c, chunk_t& ch, uint3
   const uint64_t t_issue = now();
   uint32_t st = A_NONE, idx = 0, gen = 0;
   bool part = ch.act;  // lanes that go through dedup and the acquire loop
-  if (pin_mode == PIN_NONE && probe_first) {
+  const bool pf = pin_mode == PIN_PREFETCH;
+  if ((pin_mode == PIN_NONE || pf) && probe_first) {
     // optimistic readers: every lane first probes its own set; a resident or in-flight
     // line is taken unpinned on the spot, and only the lanes left over elect leaders
     const uint32_t base = ch.act ? set_of(c, ch.line_id) * c.assoc : 0u;
@@ -1404,7 +1410,7 @@ __device__ __forceinline__ bool chunk_issue(const dev_ctx& c, chunk_t& ch, uint3
   while (ballot(pending)) {
     bool wb = false, rd = false;
     if (pending) {
-      const acq_t a = acquire_try(c, ch.line_id, npin, retake);
+      const acq_t a = acquire_try(c, ch.line_id, npin, retake, !pf);
       if (a.res != A_NONE) {
         st = a.res;
         idx = a.idx;
@@ -1442,7 +1448,7 @@ __device__ __forceinline__ bool chunk_issue(const dev_ctx& c, chunk_t& ch, uint3
       if (!sp.step(c, wi(W_SETLOCK, rdlane(ch.line_id, ffs64(ballot(pending && st == A_NONE)))))) return false;
     }
   }
-  const bool pin = lead && (npin ? st_ok(st) : st == A_MISS);
+  const bool pin = lead && !pf && (npin ? st_ok(st) : st == A_MISS);
   // broadcast to followers
   const uint32_t lst = shfl32(st, ch.leader);
   const uint32_t lidx = shfl32(idx, ch.leader);

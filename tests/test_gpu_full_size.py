@@ -173,3 +173,46 @@ def test_backward_sgd_full_size_whole_store():
         ctx.close_store()
         ctx.shutdown()
         buf.free()
+
+
+@pytest.mark.timeout(300)
+@pytest.mark.parametrize("K", [0, 8002])
+def test_dlrm_full_size_prefetch_sequence_sampled_bags(dlrm_image, K):
+    """The benchmark's timed step (asynchronous, each batch computed while the next one is
+    prefetched) on three consecutive batches from a cold cache, at K = 0 and at the
+    balanced K: 256 sampled bags of every batch equal the oracle bit for bit, the last
+    batch equals the synchronous forward of the same batch, and the cache is quiescent
+    afterwards."""
+    import torch
+    rows, dim, T, B = 4194304, 128, 8, 2048
+    buf = dlrm_image
+    ctx = agile.Context(cache_bytes=2 << 30, line_bytes=4096, assoc=16, num_qp=16, qp_depth=1024,
+                        latency_ns=80_000, iops_cap=1_500_000, timeout_ns=int(30e9))
+    try:
+        ctx.open_store(buf)
+        tb = ctx.tables(rows, dim, T)
+        cum = gen.zipf_cum(rows, 1.05)
+        host = [gen.embbag_batch(cum, B, T, 1, 80, seed=1002 + n) for n in range(4)]
+        dev = [(cuda(o), cuda(i)) for o, i in host]
+        ctx.invalidate()
+        outs = []
+        for n in range(3):
+            o = torch.empty((B * T, dim), dtype=torch.float32, device="cuda")
+            ctx.embbag_forward_prefetch(tb, dev[n][1], dev[n][0], B, K, o, dev[n + 1][1],
+                                        dev[n + 1][0], B)
+            outs.append(o)
+        ctx.sync()
+        for n in range(3):
+            off, idx = host[n]
+            sample = np.sort(np.random.default_rng(60 + n + K).choice(B * T, 256, replace=False))
+            ref = oracle.embbag_forward(buf.array, rows, dim, T, idx, off, B, K, bags=sample)
+            got = outs[n].cpu().numpy()[sample]
+            assert np.array_equal(got.view(np.uint32), ref.view(np.uint32)), f"batch {n}"
+        check_quiescent_invariants(ctx, 16)
+        o_s = torch.empty_like(outs[2])
+        ctx.embbag_forward(tb, dev[2][1], dev[2][0], B, K, o_s, mode=agile.MODE_SYNC)
+        ctx.sync()
+        assert torch.equal(o_s, outs[2])
+    finally:
+        ctx.close_store()
+        ctx.shutdown()
