@@ -140,7 +140,8 @@ agile_status agile_close_store(agile_ctx ctx, agile_store store);
  * uint64), coalesces duplicates within a wavefront, looks up the cache and, on a miss,
  * claims a line and submits a READ.  Writes one ticket per block to d_tickets (device).
  * Each successful ticket pins its line until agile_release; a ticket whose set has no
- * evictable way carries status EAGAIN and pins nothing.  Stream-ordered and returns at
+ * evictable way, or whose line already holds 262,144 pins, carries status EAGAIN and pins
+ * nothing.  Stream-ordered and returns at
  * once to the host.  Unlike the paper's prefetch(), whose reads proceed beside the
  * calling kernel, the reads of this call complete within its own kernel launch (the
  * launch carries the service wavefronts that drain every command, see the note at the

@@ -100,6 +100,12 @@ __device__ __forceinline__ uint32_t shfl32(uint32_t v, uint32_t src) {
 enum : uint32_t { ST_INVALID = 0, ST_FETCHING = 1, ST_READY = 2, ST_DIRTY = 3, ST_WRITEBACK = 4 };
 constexpr uint64_t M_STATE = 7ull, M_REF = 8ull, RC_ONE = 1ull << 4, RC_MASK = 0xFFFFFull << 4;
 constexpr uint32_t GEN_SHIFT = 24, TAG_SHIFT = 32;
+// Pins a line may hold.  Pins are taken with one atomic add and given back when the
+// line turns out not to be the one wanted or to be at the limit, so the 20-bit count
+// must also hold every addition in flight above the limit: at most 64 per wavefront
+// (8,192 wavefronts on 256 CUs), 2^19 in all, and 2^18 + 2^19 < 2^20.
+constexpr uint32_t RC_LIMIT = 1u << 18;
+static_assert(RC_LIMIT + 64u * 8192u < (1u << 20), "the pin count could carry into the generation");
 __device__ __forceinline__ uint32_t m_state(uint64_t m) { return (uint32_t)(m & M_STATE); }
 __device__ __forceinline__ uint32_t m_rc(uint64_t m) { return (uint32_t)((m & RC_MASK) >> 4); }
 __device__ __forceinline__ uint32_t m_gen(uint64_t m) { return (uint32_t)(m >> GEN_SHIFT) & 0xFF; }
@@ -1082,11 +1088,17 @@ __device__ __forceinline__ void unlock(uint32_t* l) { st_rel(l, 0u); }
 
 // Pins a way whose probe showed `tag` valid.  The pin is an atomic add of the pin
 // count; if the word it returns no longer carries `tag` in a non-INVALID state the add is
-// undone.  Returns the old word (0 state INVALID on failure).
+// undone and the result is false.  Otherwise true, with res = HIT or JOIN (pinned), or
+// res = EAGAIN when the line already holds RC_LIMIT pins (the add is undone).
 __device__ __forceinline__ bool pin_way(const dev_ctx& c, uint32_t idx, uint32_t tag, uint32_t cnt,
                                         uint32_t& res, uint32_t& gen) {
   const uint64_t old = add_rlx(c.meta + idx, RC_ONE * cnt);
   if (m_tag(old) == tag && m_state(old) != ST_INVALID) {
+    if (m_rc(old) + cnt > RC_LIMIT) {  // the line holds as many pins as it may: EAGAIN
+      add_rlx(c.meta + idx, (uint64_t)0 - RC_ONE * cnt);
+      res = A_EAGAIN;
+      return true;
+    }
     res = (m_state(old) == ST_FETCHING) ? A_JOIN : A_HIT;
     gen = m_gen(old);
     if (!(old & M_REF)) or_rlx(c.meta + idx, M_REF);

@@ -174,6 +174,45 @@ def test_ticket_api_read_wait_release(image):
         ctx.shutdown()
 
 
+def test_ticket_pin_limit_per_line(image):
+    """300,000 tickets for one block: a line holds at most 262,144 pins, so at most that
+    many tickets succeed and the others carry EAGAIN with nothing pinned (the pin count
+    never reaches the generation bits); every successful ticket names the same line with
+    the block's bytes, and after the release nothing is pinned."""
+    import torch
+    ctx = make_ctx(image)
+    try:
+        n = 300_000
+        blocks = np.full(n, 5, dtype=np.uint64)
+        tk = torch.empty(n, dtype=torch.int64, device="cuda")
+        ctx.async_read(cuda(blocks), tk)
+        ctx.sync()
+        t = tk.cpu().numpy().view(np.uint64)
+        status = (t >> np.uint64(40)) & np.uint64(0xFF)
+        ok = status == 0
+        assert np.all((status == 0) | (status == 1))
+        assert 200_000 <= ok.sum() <= 262_144
+        lines = np.unique(t[ok] & np.uint64(0xFFFFFFFF))
+        gens = np.unique((t[ok] >> np.uint64(32)) & np.uint64(0xFF))
+        assert lines.size == 1 and gens.size == 1
+        tags, st, rc = dump_meta(ctx)
+        assert rc[int(lines[0])] == ok.sum() and rc.sum() == ok.sum()
+        assert tags[int(lines[0])] == 5 and st[int(lines[0])] == 2
+        ptr = torch.empty(64, dtype=torch.int64, device="cuda")
+        first = torch.from_numpy(t[ok][:64].view(np.int64)).cuda()
+        assert ctx.wait(first, ptr) == agile.OK
+        info = ctx.info()
+        off = int(ptr[0].item()) - info["cache_base"]
+        cache = device_bytes(info["cache_base"], info["num_lines"] * 4096).cpu().numpy()
+        assert np.array_equal(cache[off:off + 4096], image.array[5 * 4096:6 * 4096])
+        ctx.release(tk)
+        ctx.sync()
+        check_quiescent_invariants(ctx, 8)
+    finally:
+        ctx.close_store()
+        ctx.shutdown()
+
+
 @pytest.mark.parametrize("mode", [agile.MODE_SYNC, agile.MODE_ASYNC])
 def test_cache_deadlock_case_one_set_four_ways(image, lookups, mode):
     """Sec. 2.3.2: waves that pin lines while asking for more must not deadlock; with one
