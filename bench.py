@@ -61,8 +61,8 @@ def committed_traffic(path=TRAFFIC_PROFILE):
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=12)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=16)
+    ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--K", type=int, default=0, help="fmaf chain per element in the timed step")
     ap.add_argument("--rows", type=int, default=4194304)
     ap.add_argument("--tables", type=int, default=8)
