@@ -80,6 +80,7 @@ struct src_state {
   uint32_t dealt;  // static bags looked at so far (0..STATIC_ROUNDS)
   uint32_t tried;  // partitions found used up so far
   int64_t nb;      // bags of the launch: a.nbags, or the deferred count for a list
+  int64_t A;       // waves taking part: a.active_waves, or fewer for a short list
 };
 constexpr uint32_t STATIC_ROUNDS = 2;
 
@@ -153,7 +154,7 @@ __device__ __forceinline__ bool wait_published(const dev_ctx& c, const embbag_ar
 // Takes the next bag into the held slot (or marks the source exhausted).
 __device__ __forceinline__ void hold_next(const dev_ctx& c, const launch_t& li, const embbag_args& a,
                                           src_state& ss) {
-  const int64_t A = (int64_t)a.active_waves, nb = ss.nb;
+  const int64_t A = ss.A, nb = ss.nb;
   const int64_t dealt = (int64_t)STATIC_ROUNDS * A < nb ? (int64_t)STATIC_ROUNDS * A : nb;
   int64_t g = -1;
   while (ss.dealt < STATIC_ROUNDS) {
@@ -167,7 +168,7 @@ __device__ __forceinline__ void hold_next(const dev_ctx& c, const launch_t& li, 
   // never more partitions than waves: every partition then has a wave that starts in it
   // and stays until it is used up, so a bag is never left where no wave looks (a serving
   // wave that waits on an unpublished bag of its partition blocks only that partition)
-  const uint32_t parts = a.active_waves < WORK_PARTS ? a.active_waves : WORK_PARTS;
+  const uint32_t parts = (uint32_t)(A < (int64_t)WORK_PARTS ? A : (int64_t)WORK_PARTS);
   if (nb <= dealt) ss.tried = parts;  // every bag was dealt: no counter to visit
   while (g < 0 && ss.tried < parts) {
     const uint32_t p = (ss.uw + ss.tried) % parts;
@@ -241,7 +242,7 @@ __device__ __forceinline__ desc_t next_desc(const dev_ctx& c, const launch_t& li
       // hold the next bag now, except near the end of the work: a held bag cannot go to
       // a wave that runs out, so the last bags are taken only when needed
       ss.g = -1;
-      if (g + 2 * (int64_t)a.active_waves < ss.nb) hold_next(c, li, a, ss);
+      if (g + 2 * ss.A < ss.nb) hold_next(c, li, a, ss);
       if (j1 > j0) {
         r.g = bag;
         r.j = j0;
@@ -489,7 +490,8 @@ __device__ __forceinline__ bool finish_chunk(const dev_ctx& c, const embbag_args
 //    are issued, both are waited for, then both are computed; the wave's compute never
 //    overlaps its own I/O.
 template <int VPL>
-__device__ __forceinline__ void embbag_wave(const dev_ctx& c, const launch_t& li, const embbag_args& a, uint32_t uw) {
+__device__ __forceinline__ void embbag_wave(const dev_ctx& c, const launch_t& li, const embbag_args& a, uint32_t uw,
+                                            uint32_t active) {
   const uint32_t q = uw % c.num_qp;
   const bool async = a.mode == AGILE_MODE_ASYNC;
   float acc[VPL];
@@ -499,7 +501,7 @@ __device__ __forceinline__ void embbag_wave(const dev_ctx& c, const launch_t& li
   none.valid = false;
   // a list launch runs the bags the resident-hit pass before it deferred
   const int64_t nb = a.list ? (int64_t)uni64(ld_rlx(counter(c, C_DEFER))) : (int64_t)a.nbags;
-  src_state ss{-1, -1, 0, 0, false, uw, 0, 0, nb};
+  src_state ss{-1, -1, 0, 0, false, uw, 0, 0, nb, (int64_t)active};
   chunk_t cc, cn;
   if (!async) {
     desc_t dc = next_desc<VPL>(c, li, a, none, ss, true);
@@ -1005,20 +1007,33 @@ __global__ __launch_bounds__(64 * RES_WAVES) void k_embbag_resident(dev_ctx c, c
     if (d0 + e < a.dim) o[e] = acc[e];
 }
 
+// A launch that runs the deferred list of the resident-hit pass before it sizes itself by
+// the list (its count is final when the launch starts): only the leading user
+// workgroups that give one wave per deferred bag take part (at least one workgroup), the
+// others leave at once, and the service waits for the ones taking part.  A replay whose
+// bags were all served costs one workgroup and the service instead of the whole grid.
 template <int VPL>
 __global__ __launch_bounds__(WG) void k_embbag(dev_ctx c, launch_t li, embbag_args a) {
+  uint32_t active = a.active_waves;
+  if (a.list) {
+    const uint64_t nd = uni64(ld_rlx(counter(c, C_DEFER)));
+    const uint64_t need = ((nd > WPB ? nd : WPB) + WPB - 1) / WPB * WPB;
+    if (need < li.user_waves) li.user_waves = (uint32_t)need;
+    if (li.user_waves < active) active = li.user_waves;
+  }
   if (blockIdx.x < li.service_blocks) {
     run_service(c, li);
     return;
   }
+  if ((blockIdx.x - li.service_blocks) * WPB >= li.user_waves) return;  // the whole workgroup
   user_wave_begin();
   const uint32_t uw = (blockIdx.x - li.service_blocks) * WPB + threadIdx.x / 64;
   if (a.list && uw == 0 && lane() == 0)
     add_rlx(counter(c, C_HIT_TOTAL), a.gather ? a.n : (uint64_t)(a.off[a.nbags] - a.off[0]));
   if (c.flags & AGILE_F_SERIALIZED) {
     if (uw == 0) embbag_serial<VPL>(c, li, a);
-  } else if (uw < a.active_waves) {
-    embbag_wave<VPL>(c, li, a, uw);
+  } else if (uw < active) {
+    embbag_wave<VPL>(c, li, a, uw, active);
   }
   user_wave_done(c, li);
 }
@@ -1095,7 +1110,7 @@ __global__ __launch_bounds__(WG) void k_serve(dev_ctx c, launch_t li, embbag_arg
   }
   user_wave_begin();
   const uint32_t uw = (blockIdx.x - li.service_blocks) * WPB + threadIdx.x / 64;
-  if (uw < a.active_waves) embbag_wave<VPL>(c, li, a, uw);
+  if (uw < a.active_waves) embbag_wave<VPL>(c, li, a, uw, a.active_waves);
   user_wave_done(c, li);
 }
 
