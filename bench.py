@@ -85,9 +85,10 @@ def parse():
                          "next-batch prefetch), 'hit' "
                          "the hit-path replay only, 'bwd' / 'randread' / 'devices' / 'graph' that "
                          "measurement only")
-    ap.add_argument("--extras", default="serve,randread,devices,bwd,graph",
-                    help="comma list of extra measurements: serve, bwd, graph, randread, devices "
-                         "('' = none)")
+    ap.add_argument("--extras", default="sens,serve,randread,devices,bwd,graph",
+                    help="comma list of extra measurements: sens (queue and cache "
+                         "sensitivity of the asynchronous mode at K_bal), serve, bwd, graph, "
+                         "randread, devices ('' = none)")
     ap.add_argument("--cpu-child", default="", choices=("", "single", "par"),
                     help=argparse.SUPPRESS)
     ap.add_argument("--serve-seconds", type=float, default=0.5)
@@ -596,11 +597,12 @@ def main():
     outs = [torch.empty((B * T, dim), dtype=torch.float32, device="cuda") for _ in range(nb + 1)]
     stream = torch.cuda.current_stream()
 
-    def run(mode, K, which, time_each=True, nxt=None):
-        """Runs the given batch indices; returns per-call ms (HIP events on the launch
-        stream) and the wall time of the whole sequence.  mode PREFETCH: each call also
-        prefetches the batch after it in `which` (after the last one, batch `nxt`, if
-        any)."""
+    def run(mode, K, which, time_each=True, nxt=None, c=None):
+        """Runs the given batch indices (on context c, default the step's); returns
+        per-call ms (HIP events on the launch stream) and the wall time of the whole
+        sequence.  mode PREFETCH: each call also prefetches the batch after it in
+        `which` (after the last one, batch `nxt`, if any)."""
+        cx = c or ctx
         evs = []
         torch.cuda.synchronize()
         w0 = time.perf_counter()
@@ -613,16 +615,16 @@ def main():
             if mode == PREFETCH:
                 j = which[k + 1] if k + 1 < len(which) else nxt
                 if j is None:
-                    ctx.embbag_forward_prefetch(tb, idx, off, B, K, outs[i], None, None, 0)
+                    cx.embbag_forward_prefetch(tb, idx, off, B, K, outs[i], None, None, 0)
                 else:
-                    ctx.embbag_forward_prefetch(tb, idx, off, B, K, outs[i], batches[j][1],
-                                                batches[j][0], B)
+                    cx.embbag_forward_prefetch(tb, idx, off, B, K, outs[i], batches[j][1],
+                                               batches[j][0], B)
             else:
-                ctx.embbag_forward(tb, idx, off, B, K, outs[i], mode=mode)
+                cx.embbag_forward(tb, idx, off, B, K, outs[i], mode=mode)
             if time_each:
                 e1.record(stream)
                 evs.append((e0, e1))
-        ctx.sync()
+        cx.sync()
         wall = time.perf_counter() - w0
         return [a.elapsed_time(b) for a, b in evs], wall
 
@@ -868,6 +870,45 @@ def main():
                 f"(x{res['sync'] / res['prefetch']:.3f}) ctc {ctc:.3f} bound {bound:.3f} "
                 f"identical {res['identical']}")
 
+    # ---- sensitivity of the asynchronous DLRM mode to the queues and the cache (Sec. 4.3):
+    # at K_bal, sync against async with next-batch prefetch, with 1, 4 and 16 queue pairs
+    # of depth 64, and with caches of 0.5, 1 and 4 GiB (the step's own point, 16 x 1024
+    # queue slots and 2 GiB, is the sweep's K_bal row)
+    sensitivity = None
+    if k_bal and "sens" in [e for e in args.extras.split(",") if e]:
+        sensitivity = {"K": k_bal, "points": []}
+        ids3 = timed_ids[:3]
+        points = ([{"num_qp": n, "qp_depth": 64} for n in (1, 4, 16)]
+                  + [{"cache_bytes": int(g * 2**30)} for g in (0.5, 1.0, 4.0)])
+        for over in points:
+            c2 = agile.Context(**{**cfg, **over})
+            c2.open_store(buf)
+            res = {}
+            for mode, name in ((agile.MODE_SYNC, "sync"), (PREFETCH, "prefetch")):
+                w, t = aligned(mode, warm_ids[:1], ids3)
+                c2.invalidate()
+                run(mode, k_bal, w, time_each=False, nxt=t[0], c=c2)
+                s0 = c2.stats()
+                ms, _ = run(mode, k_bal, t, nxt=t[-1] + 1, c=c2)
+                s1 = c2.stats()
+                res[name] = float(np.mean(ms))
+                res[name + "_reads"] = s1["read_cmds"] - s0["read_cmds"]
+                res[name + "_out"] = [outs[i].clone() for i in ids3[1:]]
+            c2.close_store()
+            c2.shutdown()
+            same_s = all(torch.equal(a, b) for a, b in zip(res["sync_out"], res["prefetch_out"]))
+            pt = {**{k: (round(v / 2**30, 2) if k == "cache_bytes" else v) for k, v in over.items()},
+                  "sync_ms": round(res["sync"], 3), "prefetch_ms": round(res["prefetch"], 3),
+                  "speedup": round(res["sync"] / res["prefetch"], 3),
+                  "sync_reads": res["sync_reads"], "prefetch_reads": res["prefetch_reads"],
+                  "identical": same_s}
+            if "cache_bytes" in pt:
+                pt["cache_gib"] = pt.pop("cache_bytes")
+            sensitivity["points"].append(pt)
+            log(f"sensitivity {over}: sync {res['sync']:.2f} async+prefetch {res['prefetch']:.2f} "
+                f"(x{res['sync'] / res['prefetch']:.3f}) reads {res['sync_reads']} / "
+                f"{res['prefetch_reads']} identical {same_s}")
+
     # ---- thread-level overlap (Sec. 4.2): one 1024-thread group (16 wavefronts) for both
     # modes, K set so that the computation-to-communication ratio spans 0..2
     overlap = []
@@ -1008,6 +1049,7 @@ def main():
         "k_bal": k_bal,
         "compute_sweep_full_gpu": sweep,
         "overlap_1024_threads": overlap,
+        "dlrm_sensitivity_sec_4_3": sensitivity,
         # the timed step's own bound: its misses go through the emulated store, whose
         # roofline is the IOPS cap x 4 KiB (the 80 us latency is hidden by the queues)
         "roofline": {"bound": "store", "achieved": round(iops * 4096 / 1e9, 4),

@@ -3099,10 +3099,11 @@ static agile_status embbag_launch(agile_ctx ctx, agile_store store, const agile_
     p.waves = std::min<uint32_t>(PF_WAVES, cap);
     {
       // eight times the commands the store needs in flight to run at its cap (Little's
-      // law: IOPS x latency, per device), at least 2048, at most half of all queue slots
+      // law: IOPS x latency, per device), at least 2048, at most every queue slot (with
+      // few slots a read the computing waves need waits at most one queue's worth)
       const double little = (double)ctx->cfg.iops_cap * (double)ctx->cfg.latency_ns * 1e-9;
       const uint64_t slots = (uint64_t)ctx->cfg.num_qp * ctx->cfg.qp_depth;
-      p.backlog = std::max<uint64_t>(1, std::min<uint64_t>(slots / 2, std::max<uint64_t>(2048, (uint64_t)(8.0 * little * ctx->d.n_dev))));
+      p.backlog = std::min<uint64_t>(slots, std::max<uint64_t>(2048, (uint64_t)(8.0 * little * ctx->d.n_dev)));
     }
     embbag_args ap = a;
     ap.mode = AGILE_MODE_ASYNC;
