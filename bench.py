@@ -965,6 +965,83 @@ def main():
         pctx.close_store()
         pctx.shutdown()
 
+    # ---- the same 1024-thread group, overlap at the batch (Sec. 4.2: in the synchronous
+    # mode computation starts once all of its data is in): sync fetches a batch (a call
+    # that only prefetches it) and then computes it (a call whose next batch is empty);
+    # async computes a batch while the next one is fetched.  The same kernel, prefetch
+    # path, backlog and 16 wavefronts in both; K = 0, then K set for CTC 0.7..2.  The cache
+    # is the hit replay's (no set overflows with two batches in it): the curve measures
+    # overlap, not cache pressure (with the step's 2 GiB cache the next batch's prefetch
+    # evicts lines of the current one before 16 slow wavefronts use them, and each such
+    # line is a demand read that 16 wavefronts cannot hide; the full-GPU sensitivity rows
+    # show the cache's effect).
+    overlap_b = []
+    if args.sweep:
+        W = 16
+        empty_off = torch.zeros(B * T + 1, dtype=torch.int64, device="cuda")
+        bctx = agile.Context(**{**cfg, "cache_bytes": int(args.hit_cache_gib * 2**30)})
+        bctx.open_store(buf)
+        bctx.set_max_user_waves(W)
+
+        def fetch(i):
+            bctx.embbag_forward_prefetch(tb, None, None, 0, 0, None, batches[i][1], batches[i][0], B)
+
+        def compute(i, K):
+            bctx.embbag_forward_prefetch(tb, batches[i][1], batches[i][0], B, K, outs[i], None,
+                                         empty_off, B)
+
+        def b_sync(K, ids):
+            """Per batch of `ids`: (fetch ms, compute ms); the warm-up fetches and computes
+            the batches before ids[0] that the async run's warm-up computes or prefetches."""
+            bctx.invalidate()
+            for i in warm_ids[:1] + ids[:1]:
+                fetch(i)
+                compute(i, K)
+            io, cp = [], []
+            for i in ids[1:] + [ids[-1] + 1]:
+                e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+                e0.record(stream)
+                fetch(i)
+                e1.record(stream)
+                compute(i, K)
+                e2.record(stream)
+                bctx.sync()
+                io.append(e0.elapsed_time(e1))
+                cp.append(e1.elapsed_time(e2))
+            return float(np.mean(io)), float(np.mean(cp))
+
+        def b_async(K, ids):
+            bctx.invalidate()
+            run(PREFETCH, K, warm_ids[:1], time_each=False, nxt=ids[0], c=bctx)
+            ms, _ = run(PREFETCH, K, ids, nxt=ids[-1] + 1, c=bctx)
+            return float(np.mean(ms))
+
+        idsb = timed_ids[:2]
+        io0, c0 = b_sync(0, idsb)
+        _, c1 = b_sync(256, idsb)
+        slope = max((c1 - c0) / 256.0, 1e-9)
+        ks = [0]
+        for target in (0.7, 1.0, 1.5, 2.0):
+            K = max(0, int(round((target * io0 - c0) / slope)))
+            if K not in ks:
+                ks.append(K)
+        for K in ks:
+            io, cp = b_sync(K, idsb)
+            sync_out = [outs[i].clone() for i in idsb[1:]]
+            t_a = b_async(K, idsb)
+            same_b = all(torch.equal(a, outs[i]) for a, i in zip(sync_out, idsb[1:]))
+            ctc = cp / io
+            bound = 1 + ctc if ctc <= 1 else 1 + 1 / ctc
+            overlap_b.append({"K": K, "ctc": round(ctc, 4), "fetch_ms": round(io, 3),
+                              "compute_ms": round(cp, 3), "sync_ms": round(io + cp, 3),
+                              "async_ms": round(t_a, 3), "speedup": round((io + cp) / t_a, 3),
+                              "eq1_bound": round(bound, 3), "identical": same_b})
+            log(f"16 waves, batch overlap K={K}: ctc {ctc:.3f} sync {io + cp:.2f} (fetch {io:.2f} + "
+                f"compute {cp:.2f}) async {t_a:.2f} speedup {(io + cp) / t_a:.3f} bound {bound:.3f} "
+                f"identical {same_b}")
+        bctx.close_store()
+        bctx.shutdown()
+
     # ---- CPU baseline: the oracle on a bounded sample of the same workload, in child
     # processes that never touch the GPU: (i) the single-threaded oracle pinned to one
     # core, (ii) the same loop with its bags spread over every core (OpenMP)
@@ -1049,6 +1126,7 @@ def main():
         "k_bal": k_bal,
         "compute_sweep_full_gpu": sweep,
         "overlap_1024_threads": overlap,
+        "overlap_1024_threads_batch": overlap_b,
         "dlrm_sensitivity_sec_4_3": sensitivity,
         # the timed step's own bound: its misses go through the emulated store, whose
         # roofline is the IOPS cap x 4 KiB (the 80 us latency is hidden by the queues)

@@ -335,11 +335,12 @@ agile_status agile_embbag_forward(agile_ctx ctx, agile_store store, const agile_
  * completed, so have all its prefetch reads.  B_next == 0 prefetches nothing (the call is
  * then agile_embbag_forward in AGILE_MODE_ASYNC); B == 0 only prefetches (d_idx, d_off and
  * d_out may then be NULL).  d_next_idx may be NULL when every next bag is empty.
- * Stream-ordered, one launch: the service wavefronts, up to 64 prefetch wavefronts that
- * submit the next batch's reads and then compute, and every other wavefront computing
- * this batch's bags, each served from resident lines where it can be and through the
- * cache and queues from where it cannot (the same wave count as the I/O launch of
- * agile_embbag_forward).  No host synchronisation, allocation or memset.  With
+ * Stream-ordered, one launch: the service wavefronts, 64 prefetch wavefronts that submit
+ * the next batch's reads and then compute, and every other wavefront computing this
+ * batch's bags, each served from resident lines where it can be and through the cache
+ * and queues from where it cannot (the same wave count as the I/O launch of
+ * agile_embbag_forward); a launch of at most 256 wavefronts (a small cache, or a cap
+ * from agile_set_max_user_waves) has every wavefront prefetch and compute in turns.  No host synchronisation, allocation or memset.  With
  * AGILE_F_SERIALIZED nothing is prefetched.  Errors as for agile_embbag_forward. */
 agile_status agile_embbag_forward_prefetch(agile_ctx ctx, agile_store store, const agile_tables* tb,
                                            const int64_t* d_idx, const int64_t* d_off, uint64_t B,

@@ -824,8 +824,8 @@ struct pf_args {
   uint64_t nbags;      // its bags; 0: nothing to prefetch
   uint64_t store_bytes;
   uint64_t backlog;    // commands in flight (all queues) above which prefetching pauses
-  uint32_t waves;      // user wavefronts that prefetch before they compute
-  uint32_t _p0;
+  uint32_t waves;      // user wavefronts that prefetch
+  uint32_t interleave; // they prefetch and compute in turns (else prefetch, then compute)
 };
 
 // The bag holding lookup j: the g with off[g] <= j < off[g + 1] (off[0] <= j < off[nb]).
@@ -841,31 +841,46 @@ __device__ __forceinline__ uint64_t bag_of(const int64_t* off, uint64_t nb, int6
   return lo;
 }
 
+// The store's backlog (commands submitted and not yet completed, all queues) is at the
+// prefetch's bound.  The store serves its queues first come, first served: a bounded
+// backlog keeps it busy while the reads that computing waves need now wait behind
+// little of it.
+__device__ __forceinline__ bool backlog_full(const dev_ctx& c, const pf_args& p) {
+  return uni64(ld_rlx(counter(c, C_SUBMITTED))) - uni64(ld_rlx(counter(c, C_COMPLETED))) >= p.backlog;
+}
+
+// Claims (unpinned) the lines of the next batch's lookups [j0, j0 + 64) that are neither
+// resident nor in flight, and submits their READs.  False on abort or time-out.
+__device__ __forceinline__ bool prefetch_chunk(const dev_ctx& c, const embbag_args& a, const pf_args& p,
+                                               uint32_t q, int64_t j0, int64_t j_hi) {
+  const uint64_t lmask = (1ull << c.line_shift) - 1;
+  chunk_t ch;
+  const int64_t j = j0 + lane();
+  ch.act = j < j_hi;
+  ch.pinned = false;
+  ch.line_id = 0;
+  ch.off = 0;
+  if (ch.act) {
+    const uint64_t g = bag_of(p.off, p.nbags, j);
+    const uint64_t byte = a.base_off + (g % a.T) * a.table_bytes + (uint64_t)p.idx[j] * a.row_bytes;
+    ch.act = byte < p.store_bytes;  // a hint: a row outside the store is not fetched
+    ch.line_id = (uint32_t)(byte >> c.line_shift);
+    ch.off = (uint32_t)(byte & lmask);
+  }
+  return chunk_issue(c, ch, q, false, PIN_PREFETCH);
+}
+
+// A dedicated prefetch wave's share: chunks w, w + P, ... of the next batch (P = p.waves),
+// each after the backlog is below its bound.
 __device__ __forceinline__ bool prefetch_wave(const dev_ctx& c, const embbag_args& a, const pf_args& p,
                                               uint32_t w) {
   const int64_t j_lo = p.off[0], j_hi = p.off[p.nbags];
   const uint32_t q = w % c.num_qp;
-  const uint64_t lmask = (1ull << c.line_shift) - 1;
   for (int64_t j0 = j_lo + (int64_t)w * 64; j0 < j_hi; j0 += (int64_t)p.waves * 64) {
-    chunk_t ch;
-    const int64_t j = j0 + lane();
-    ch.act = j < j_hi;
-    ch.pinned = false;
-    ch.line_id = 0;
-    ch.off = 0;
-    if (ch.act) {
-      const uint64_t g = bag_of(p.off, p.nbags, j);
-      const uint64_t byte = a.base_off + (g % a.T) * a.table_bytes + (uint64_t)p.idx[j] * a.row_bytes;
-      ch.act = byte < p.store_bytes;  // a hint: a row outside the store is not fetched
-      ch.line_id = (uint32_t)(byte >> c.line_shift);
-      ch.off = (uint32_t)(byte & lmask);
-    }
-    // the store serves its queues first come, first served: a bounded backlog keeps it
-    // busy while the reads that computing waves need now wait behind little of it
     spin_t sp;
-    while (uni64(ld_rlx(counter(c, C_SUBMITTED))) - uni64(ld_rlx(counter(c, C_COMPLETED))) >= p.backlog)
+    while (backlog_full(c, p))
       if (!sp.step(c, wi(W_BACKLOG, p.backlog))) return false;
-    if (!chunk_issue(c, ch, q, false, PIN_PREFETCH)) return false;
+    if (!prefetch_chunk(c, a, p, q, j0, j_hi)) return false;
   }
   return true;
 }
@@ -896,13 +911,13 @@ __device__ __forceinline__ bool io_rest(const dev_ctx& c, const embbag_args& a, 
 // The compute loop over work counters: wave uw of nw starts in partition uw mod P
 // (P = min(WORK_PARTS, nw); bag g belongs to partition g mod P) and moves on when it is
 // used up.  The lookups that go through the queues are counted as such (and taken out
-// of the resident-hit total the launch adds).
+// of the resident-hit total the launch adds).  compute_bag takes and computes the
+// wave's next bag: 1 done, 0 no bag left, -1 abort or time-out.
 template <int VPL>
-__device__ __forceinline__ void pf_compute(const dev_ctx& c, const embbag_args& a, uint32_t uw, uint32_t nw) {
+__device__ __forceinline__ int compute_bag(const dev_ctx& c, const embbag_args& a, uint32_t uw, uint32_t nw,
+                                           uint32_t& t) {
   const uint32_t parts = nw < WORK_PARTS ? nw : WORK_PARTS;
-  const uint32_t q = uw % c.num_qp;
-  uint8_t* lds = probe_area();
-  for (uint32_t t = 0; t < parts;) {
+  while (t < parts) {
     const uint32_t pp = (uw + t) % parts;
     uint64_t v = 0;
     if (lane() == 0) v = add_rlx(counter(c, work_counter(pp)), 1ull);
@@ -915,11 +930,42 @@ __device__ __forceinline__ void pf_compute(const dev_ctx& c, const embbag_args& 
     float acc[VPL];
 #pragma unroll
     for (int e = 0; e < VPL; ++e) acc[e] = 0.0f;
-    const int64_t j = hit_bag_part<VPL>(c, a, g, lds, acc, j0, j1);
+    const int64_t j = hit_bag_part<VPL>(c, a, g, probe_area(), acc, j0, j1);
     if (j < j1) {
       if (lane() == 0) wcount(WS_DEFLEN, (uint64_t)(j1 - j));
-      if (!io_rest<VPL>(c, a, q, (int64_t)g, j, j1, acc)) return;
+      if (!io_rest<VPL>(c, a, uw % c.num_qp, (int64_t)g, j, j1, acc)) return -1;
     }
+    return 1;
+  }
+  return 0;
+}
+
+// With few wavefronts in the launch every wave prefetches and computes, in turns: it
+// tops the store's backlog up with its next chunks of the next batch, computes one bag,
+// and so on; once its bags are gone it finishes its chunks.  (With many wavefronts a few
+// dedicated prefetch waves keep the store busy and the others never stop computing.)
+template <int VPL>
+__device__ __forceinline__ void pf_interleaved(const dev_ctx& c, const embbag_args& a, const pf_args& p, uint32_t uw,
+                                               uint32_t nw) {
+  const int64_t j_hi = p.off[p.nbags];
+  const uint32_t q = uw % c.num_qp;
+  int64_t pj = p.off[0] + (int64_t)uw * 64;
+  uint32_t t = 0;
+  bool comp = a.nbags > 0;
+  while (pj < j_hi || comp) {
+    while (pj < j_hi && !backlog_full(c, p)) {
+      if (!prefetch_chunk(c, a, p, q, pj, j_hi)) return;
+      pj += (int64_t)p.waves * 64;
+    }
+    if (comp) {
+      const int r = compute_bag<VPL>(c, a, uw, nw, t);
+      if (r < 0) return;
+      comp = r > 0;
+      continue;
+    }
+    spin_t sp;
+    while (pj < j_hi && backlog_full(c, p))
+      if (!sp.step(c, wi(W_BACKLOG, p.backlog))) return;
   }
 }
 
@@ -934,9 +980,17 @@ __global__ __launch_bounds__(WG) void k_embbag_pf(dev_ctx c, launch_t li, embbag
   if (uw == 0 && lane() == 0 && a.nbags)
     add_rlx(counter(c, C_HIT_TOTAL), (uint64_t)(a.off[a.nbags] - a.off[0]));
   if (uw < a.active_waves) {
-    bool ok = true;
-    if (uw < p.waves && p.nbags) ok = prefetch_wave(c, a, p, uw);
-    if (ok && a.nbags) pf_compute<VPL>(c, a, uw, a.active_waves);
+    const bool pfw = uw < p.waves && p.nbags;
+    if (pfw && p.interleave) {
+      pf_interleaved<VPL>(c, a, p, uw, a.active_waves);
+    } else {
+      bool ok = true;
+      if (pfw) ok = prefetch_wave(c, a, p, uw);
+      uint32_t t = 0;
+      if (ok && a.nbags)
+        while (compute_bag<VPL>(c, a, uw, a.active_waves, t) > 0) {
+        }
+    }
   }
   user_wave_done(c, li);
 }
@@ -3096,14 +3150,22 @@ static agile_status embbag_launch(agile_ctx ctx, agile_store store, const agile_
     p.off = d_next_off;
     p.nbags = B_next * tb->num_tables;
     p.store_bytes = store->bytes;
-    p.waves = std::min<uint32_t>(PF_WAVES, cap);
+    // a few dedicated prefetch waves when the launch has many; every wave, in turns with
+    // its compute, when it has few (a call that only prefetches: up to PF_WAVES waves)
+    const bool few = a.nbags && cap <= 4 * PF_WAVES;
+    p.waves = few ? cap : std::min<uint32_t>(PF_WAVES, cap);
+    p.interleave = few ? 1u : 0u;
     {
-      // eight times the commands the store needs in flight to run at its cap (Little's
-      // law: IOPS x latency, per device), at least 2048, at most every queue slot (with
-      // few slots a read the computing waves need waits at most one queue's worth)
-      const double little = (double)ctx->cfg.iops_cap * (double)ctx->cfg.latency_ns * 1e-9;
+      // The backlog: a multiple of the commands the store needs in flight to run at its
+      // cap (Little's law: IOPS x latency, over the devices), at most every queue slot.
+      // Eight times, at least 2048, with many waves; with few, twice, at least 256: a read
+      // that a computing wave misses waits behind the backlog, and with few waves each
+      // such wait idles a larger share of the launch.
+      const double little = (double)ctx->cfg.iops_cap * (double)ctx->cfg.latency_ns * 1e-9 * ctx->d.n_dev;
       const uint64_t slots = (uint64_t)ctx->cfg.num_qp * ctx->cfg.qp_depth;
-      p.backlog = std::min<uint64_t>(slots, std::max<uint64_t>(2048, (uint64_t)(8.0 * little * ctx->d.n_dev)));
+      const uint64_t want = few ? std::max<uint64_t>(256, (uint64_t)(2.0 * little))
+                                : std::max<uint64_t>(2048, (uint64_t)(8.0 * little));
+      p.backlog = std::min<uint64_t>(slots, want);
     }
     embbag_args ap = a;
     ap.mode = AGILE_MODE_ASYNC;
