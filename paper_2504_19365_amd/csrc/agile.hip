@@ -841,6 +841,31 @@ __device__ __forceinline__ uint64_t bag_of(const int64_t* off, uint64_t nb, int6
   return lo;
 }
 
+// The bag of each lane's lookup j = j0 + lane (all lanes take part; j0 < off[nb]): the
+// bag of j0 by a 64-ary search over the offsets (one wave-wide round per factor of 64),
+// then a lane's own bag from the next 64 offsets, held one per lane, by a 6-step search
+// among them (the number of bag boundaries in (j0, j]).  A lane whose lookup lies past
+// those 64 boundaries (a run of empty bags) searches the offsets alone.
+__device__ __forceinline__ uint64_t chunk_bags(const int64_t* off, uint64_t nb, int64_t j0, int64_t j) {
+  uint64_t lo = 0, hi = nb;  // off[lo] <= j0 < off[hi]
+  while (hi - lo > 1) {
+    const uint64_t step = (hi - lo + 63) / 64;
+    const uint64_t p = lo + (uint64_t)lane() * step;
+    const uint64_t m = ballot(p < hi && off[p] <= j0);
+    const uint64_t nlo = lo + (uint64_t)(63 - __builtin_clzll(m)) * step;
+    hi = (nlo + step < hi) ? nlo + step : hi;
+    lo = nlo;
+  }
+  const uint64_t bi = lo + 1 + lane();
+  const uint64_t bnd = bi <= nb ? (uint64_t)off[bi] : ~0ull;  // offsets are >= 0
+  uint32_t cnt = 0;
+#pragma unroll
+  for (uint32_t st = 32; st; st >>= 1)
+    if (shfl64(bnd, cnt + st - 1) <= (uint64_t)j) cnt += st;
+  if (cnt == 63 && shfl64(bnd, 63) <= (uint64_t)j) return j < off[nb] ? bag_of(off, nb, j) : nb;
+  return lo + cnt;
+}
+
 // The store's backlog (commands submitted and not yet completed, all queues) is at the
 // prefetch's bound.  The store serves its queues first come, first served: a bounded
 // backlog keeps it busy while the reads that computing waves need now wait behind
@@ -860,8 +885,8 @@ __device__ __forceinline__ bool prefetch_chunk(const dev_ctx& c, const embbag_ar
   ch.pinned = false;
   ch.line_id = 0;
   ch.off = 0;
+  const uint64_t g = chunk_bags(p.off, p.nbags, j0, j);
   if (ch.act) {
-    const uint64_t g = bag_of(p.off, p.nbags, j);
     const uint64_t byte = a.base_off + (g % a.T) * a.table_bytes + (uint64_t)p.idx[j] * a.row_bytes;
     ch.act = byte < p.store_bytes;  // a hint: a row outside the store is not fetched
     ch.line_id = (uint32_t)(byte >> c.line_shift);

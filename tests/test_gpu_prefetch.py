@@ -180,3 +180,37 @@ def test_prefetch_next_batch_all_empty_and_rows_outside_store():
         ctx.close_store()
         ctx.shutdown()
         buf.free()
+
+
+def test_prefetch_finds_bags_across_runs_of_empty_bags():
+    """The prefetch finds a lookup's bag (its table) 64 lookups at a time; a run of
+    hundreds of empty bags inside a chunk, and empty bags at both ends, still give every
+    lookup its own table: after a call that only prefetches, every distinct line of the
+    batch is resident, each was read once, and computing the batch misses nothing."""
+    import torch
+    rows, dim, T, B = 65536, 64, 4, 256
+    buf = table_store(rows, dim, [1, 2, 3, 4])
+    ctx = agile.Context(cache_bytes=64 << 20, line_bytes=4096, assoc=8, num_qp=8, qp_depth=256,
+                        timeout_ns=int(10e9))
+    try:
+        ctx.open_store(buf)
+        tb = ctx.tables(rows, dim, T)
+        empty = [0, 1] + list(range(5, 301)) + list(range(600, 700)) + [B * T - 1]
+        off, idx = _batch(rows, T, B, 71, lo=1, hi=6, empty=tuple(empty))
+        di, do = cuda(idx), cuda(off)
+        ctx.embbag_forward_prefetch(tb, None, None, 0, 0, None, di, do, B)
+        ctx.sync()
+        want = _lines(off, idx, T, rows, dim)
+        assert ctx.stats(reset=True)["read_cmds"] == want.size
+        tags = check_quiescent_invariants(ctx, 8)[0]
+        assert np.isin(want, tags).all()
+        out = torch.empty((B * T, dim), device="cuda")
+        ctx.embbag_forward(tb, di, do, B, 0, out, mode=agile.MODE_SYNC)
+        ctx.sync()
+        assert ctx.stats()["misses"] == 0
+        ref = oracle.embbag_forward(buf.array, rows, dim, T, idx, off, B, 0)
+        assert np.array_equal(out.cpu().numpy().view(np.uint32), ref.view(np.uint32))
+    finally:
+        ctx.close_store()
+        ctx.shutdown()
+        buf.free()
