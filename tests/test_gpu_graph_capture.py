@@ -84,3 +84,67 @@ def test_captured_forward_replays_match_oracle(image, mode, geom):
     finally:
         ctx.close_store()
         ctx.shutdown()
+
+
+@pytest.mark.parametrize("geom", [dict(cache_bytes=16 << 20, assoc=16, num_qp=8, qp_depth=256),
+                                  dict(cache_bytes=64 << 20, assoc=16, num_qp=8, qp_depth=256)])
+def test_captured_prefetch_forward_replays_match_oracle(image, geom):
+    """agile_embbag_forward_prefetch (one launch: this batch computed while the next is
+    prefetched) captured once and replayed, with invalidations and eager calls between the
+    replays: every replay equals the oracle, completes every command it submits, and
+    leaves the next batch resident (a forward of it then reads nothing)."""
+    import torch
+    ctx = agile.Context(line_bytes=4096, timeout_ns=int(10e9), **geom)
+    try:
+        ctx.open_store(image)
+        tb = ctx.tables(ROWS, DIM)
+        B, K = 512, 16
+        off, idx = batch(7, B)
+        off2, idx2 = batch(8, B)
+        ref = oracle.embbag_forward(image.array, ROWS, DIM, 1, idx, off, B, K)
+        ref2 = oracle.embbag_forward(image.array, ROWS, DIM, 1, idx2, off2, B, K)
+        d_off, d_idx = cuda(off), cuda(idx)
+        d_off2, d_idx2 = cuda(off2), cuda(idx2)
+        out = torch.zeros((B, DIM), dtype=torch.float32, device="cuda")
+        out2 = torch.empty((B, DIM), dtype=torch.float32, device="cuda")
+
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            ctx.embbag_forward_prefetch(tb, d_idx, d_off, B, K, out, d_idx2, d_off2, B)
+        torch.cuda.current_stream().wait_stream(side)
+        ctx.sync()
+        assert np.array_equal(out.cpu().numpy().view(np.uint32), ref.view(np.uint32))
+
+        g = torch.cuda.CUDAGraph()
+        out.zero_()
+        with torch.cuda.graph(g):
+            ctx.embbag_forward_prefetch(tb, d_idx, d_off, B, K, out, d_idx2, d_off2, B)
+        torch.cuda.synchronize()
+
+        for rep in range(4):
+            if rep % 2:
+                ctx.invalidate()
+            out.zero_()
+            ctx.stats(reset=True)
+            g.replay()
+            torch.cuda.synchronize()
+            st = ctx.stats()
+            assert np.array_equal(out.cpu().numpy().view(np.uint32), ref.view(np.uint32)), rep
+            assert st["submitted"] == st["completed"]
+            if rep % 2:
+                assert st["read_cmds"] > 0, rep  # the invalidated cache was read again
+            if geom["cache_bytes"] >= 64 << 20:
+                # the whole store fits: the prefetched batch is resident after the replay
+                ctx.stats(reset=True)
+                ctx.embbag_forward(tb, d_idx2, d_off2, B, K, out2, mode=agile.MODE_SYNC)
+                ctx.sync()
+                assert ctx.stats()["read_cmds"] == 0, rep
+            else:
+                ctx.embbag_forward(tb, d_idx2, d_off2, B, K, out2, mode=agile.MODE_ASYNC)
+                ctx.sync()
+            assert np.array_equal(out2.cpu().numpy().view(np.uint32), ref2.view(np.uint32)), rep
+        del g
+    finally:
+        ctx.close_store()
+        ctx.shutdown()

@@ -79,6 +79,43 @@ def test_forward_over_devices_equals_oracle(logical, n, mode):
 
 
 @pytest.mark.parametrize("n", [2, 3])
+def test_prefetch_forward_over_devices_equals_oracle(logical, n):
+    """A batch computed while the next is prefetched, over a store striped on n devices
+    (each prefetched line goes to its own device's queue pairs): every batch equals the
+    oracle, and a call that only prefetches a batch leaves all of its lines resident."""
+    import torch
+    ctx = _ctx(cache_bytes=48 << 20)
+    bufs = _open(ctx, logical, n)
+    try:
+        B, K = 384, 8
+        tb = ctx.tables(ROWS, DIM, T)
+        cum = gen.zipf_cum(ROWS, 1.05)
+        host = [gen.embbag_batch(cum, B, T, 1, 40, seed=60 + k) for k in range(3)]
+        dev = [(cuda(o), cuda(i)) for o, i in host]
+        for k in range(2):
+            out = torch.empty((B * T, DIM), dtype=torch.float32, device="cuda")
+            ctx.embbag_forward_prefetch(tb, dev[k][1], dev[k][0], B, K, out, dev[k + 1][1],
+                                        dev[k + 1][0], B)
+            ctx.sync()
+            ref = oracle.embbag_forward(logical, ROWS, DIM, T, host[k][1], host[k][0], B, K)
+            assert np.array_equal(out.cpu().numpy().view(np.uint32), ref.view(np.uint32)), k
+        # batch 2 was prefetched by the last call: computing it reads nothing
+        ctx.stats(reset=True)
+        out = torch.empty((B * T, DIM), dtype=torch.float32, device="cuda")
+        ctx.embbag_forward(tb, dev[2][1], dev[2][0], B, K, out, mode=agile.MODE_SYNC)
+        ctx.sync()
+        assert ctx.stats()["read_cmds"] == 0
+        ref = oracle.embbag_forward(logical, ROWS, DIM, T, host[2][1], host[2][0], B, K)
+        assert np.array_equal(out.cpu().numpy().view(np.uint32), ref.view(np.uint32))
+        assert _devices_equal(bufs, logical, n)
+        check_quiescent_invariants(ctx, 8)
+    finally:
+        ctx.close_store()
+        ctx.shutdown()
+        _free(bufs)
+
+
+@pytest.mark.parametrize("n", [2, 3])
 def test_ticket_reads_over_devices(logical, n):
     import torch
     ctx = _ctx(cache_bytes=16 << 20, num_qp=12, qp_depth=64)
