@@ -324,8 +324,12 @@ def measure_bwd(agile, gen, oracle, log, steps: int = 4):
     image_ok = bool(np.array_equal(buf.array, ref))
     del ref
     looked = sum(int(bs[i][1].numel()) for i in range(1, steps + 1))
+    cmds = st["read_cmds"] + st["write_cmds"]
     res = {"steps": steps, "ms_per_step": round(el / steps * 1e3, 3),
            "lookups_per_s": round(looked / el, 1), "rows_updated": st["rows_updated"],
+           # the store's roofline: its READs and WRITEs per second against the IOPS cap
+           "store_cmds_per_step": int(cmds / steps), "store_iops": round(cmds / el, 1),
+           "store_frac": round(cmds / el / 1.5e6, 4),
            "wb_evict": st["wb_evict"], "flush_lines": st2["wb_flush"], "flush_s": round(fl, 4),
            "flush_gbs": round(st2["wb_flush"] * 4096 / max(fl, 1e-9) / 1e9, 3),
            "flushed_image_equals_oracle": image_ok}
