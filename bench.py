@@ -277,9 +277,11 @@ def measure_devices(agile, gen, buf, nbytes: int, log, reps: int = 3):
 def measure_bwd(agile, gen, oracle, log, steps: int = 4):
     """Write path at the differentiation configuration: 4 tables of 8,388,608 x 64 fp32
     (8 GiB store), 1 GiB 16-way cache; batch 4096 x 4 bags, len U[1,40], Zipf(1.1);
-    forward + backward (fused SGD, lr 0.01) per step, then a flush.  The oracle applies
-    the same updates, batch after batch, to a copy of the initial image; after the flush
-    the whole store image must equal it bit for bit."""
+    forward + backward (fused SGD, lr 0.01) per step, then a flush.  Then the same on the
+    next batches with the backward prefetching the next step's batch (Sec. 4.3's
+    asynchronous mode for a training step).  The oracle applies the same updates, batch
+    after batch, to a copy of the initial image; after each flush the whole store image
+    must equal it bit for bit."""
     import torch
     rows, dim, T, B = 8388608, 64, 4, 4096
     tbytes = rows * dim * 4
@@ -292,7 +294,7 @@ def measure_bwd(agile, gen, oracle, log, steps: int = 4):
     tb = ctx.tables(rows, dim, T)
     cum = gen.zipf_cum(rows, 1.1)
     bs, host = [], []
-    for n in range(steps + 1):
+    for n in range(2 * steps + 3):
         off, idx = gen.embbag_batch(cum, B, T, 1, 40, seed=30 + n)
         g = gen.normal_f32(31 + n, B * T * dim)
         host.append((off, idx, g))
@@ -301,30 +303,37 @@ def measure_bwd(agile, gen, oracle, log, steps: int = 4):
     ref = buf.array.copy()
     out = torch.empty((B * T, dim), device="cuda")
 
-    def step(i):
+    def step(i, prefetch=False):
         off, idx, g = bs[i]
         ctx.embbag_forward(tb, idx, off, B, 0, out)
-        ctx.embbag_backward_sgd(tb, idx, off, B, g, 0.01)
+        if prefetch:
+            ctx.embbag_backward_sgd_prefetch(tb, idx, off, B, g, 0.01, bs[i + 1][1], bs[i + 1][0], B)
+        else:
+            ctx.embbag_backward_sgd(tb, idx, off, B, g, 0.01)
 
-    step(0)
-    ctx.sync()
-    ctx.stats(reset=True)
-    t0 = time.perf_counter()
-    for i in range(1, steps + 1):
-        step(i)
-    ctx.sync()
-    el = time.perf_counter() - t0
-    st = ctx.stats()
-    t1 = time.perf_counter()
-    ctx.flush()
-    fl = time.perf_counter() - t1
-    st2 = ctx.stats()
-    for off, idx, g in host:
-        oracle.embbag_backward_sgd(ref, rows, dim, T, idx, off, B, g.reshape(B * T, dim), 0.01)
-    image_ok = bool(np.array_equal(buf.array, ref))
-    del ref
-    looked = sum(int(bs[i][1].numel()) for i in range(1, steps + 1))
-    cmds = st["read_cmds"] + st["write_cmds"]
+    def run(first, prefetch):
+        """A warm-up step on batch `first`, then `steps` timed steps, then the flush; the
+        oracle replays the same updates.  Returns the figures of the timed steps."""
+        step(first, prefetch)
+        ctx.sync()
+        ctx.stats(reset=True)
+        t0 = time.perf_counter()
+        for i in range(first + 1, first + steps + 1):
+            step(i, prefetch)
+        ctx.sync()
+        el = time.perf_counter() - t0
+        st = ctx.stats()
+        t1 = time.perf_counter()
+        ctx.flush()
+        fl = time.perf_counter() - t1
+        st2 = ctx.stats()
+        for off, idx, g in host[first:first + steps + 1]:
+            oracle.embbag_backward_sgd(ref, rows, dim, T, idx, off, B, g.reshape(B * T, dim), 0.01)
+        looked = sum(int(bs[i][1].numel()) for i in range(first + 1, first + steps + 1))
+        cmds = st["read_cmds"] + st["write_cmds"]
+        return el, st, st2, fl, looked, cmds, bool(np.array_equal(buf.array, ref))
+
+    el, st, st2, fl, looked, cmds, image_ok = run(0, False)
     res = {"steps": steps, "ms_per_step": round(el / steps * 1e3, 3),
            "lookups_per_s": round(looked / el, 1), "rows_updated": st["rows_updated"],
            # the store's roofline: its READs and WRITEs per second against the IOPS cap
@@ -334,6 +343,17 @@ def measure_bwd(agile, gen, oracle, log, steps: int = 4):
            "flush_gbs": round(st2["wb_flush"] * 4096 / max(fl, 1e-9) / 1e9, 3),
            "flushed_image_equals_oracle": image_ok}
     log(f"bwd: {res}")
+    # the next batches, the backward prefetching the next step's batch (each timed step
+    # reads one batch through the store: the warm-up prefetches the first timed one)
+    el, st, st2, fl, looked, cmds, image_ok = run(steps + 1, True)
+    res["next_batch_prefetch"] = {
+        "ms_per_step": round(el / steps * 1e3, 3), "lookups_per_s": round(looked / el, 1),
+        "store_cmds_per_step": int(cmds / steps), "store_iops": round(cmds / el, 1),
+        "store_frac": round(cmds / el / 1.5e6, 4), "wb_evict": st["wb_evict"],
+        "flushed_image_equals_oracle": image_ok,
+        "speedup_over_plain_step": round(res["ms_per_step"] / (el / steps * 1e3), 3)}
+    log(f"bwd with next-batch prefetch: {res['next_batch_prefetch']}")
+    del ref
     ctx.close_store()
     ctx.shutdown()
     buf.free()

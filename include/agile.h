@@ -340,8 +340,10 @@ agile_status agile_embbag_forward(agile_ctx ctx, agile_store store, const agile_
  * batch's bags, each served from resident lines where it can be and through the cache
  * and queues from where it cannot (the same wave count as the I/O launch of
  * agile_embbag_forward); a launch of at most 256 wavefronts (a small cache, or a cap
- * from agile_set_max_user_waves) has every wavefront prefetch and compute in turns.  No host synchronisation, allocation or memset.  With
- * AGILE_F_SERIALIZED nothing is prefetched.  Errors as for agile_embbag_forward. */
+ * from agile_set_max_user_waves) has every wavefront prefetch and compute in turns.
+ * No host synchronisation, allocation or memset: the call may be captured in a HIP graph
+ * and replayed, as agile_embbag_forward.  With AGILE_F_SERIALIZED nothing is prefetched.
+ * Errors as for agile_embbag_forward. */
 agile_status agile_embbag_forward_prefetch(agile_ctx ctx, agile_store store, const agile_tables* tb,
                                            const int64_t* d_idx, const int64_t* d_off, uint64_t B,
                                            uint32_t K, float* d_out, const int64_t* d_next_idx,
@@ -413,6 +415,23 @@ agile_status agile_debug_dump(agile_ctx ctx, int64_t* d_tags, uint8_t* d_states,
 agile_status agile_embbag_backward_sgd(agile_ctx ctx, agile_store store, const agile_tables* tb,
                                        const int64_t* d_idx, const int64_t* d_off, uint64_t B,
                                        uint64_t n, const float* d_grad, float lr, void* stream);
+
+/* agile_embbag_backward_sgd of this batch while the next batch (d_next_idx, d_next_off,
+ * B_next: the layout of agile_embbag_forward, same tables) is prefetched into the cache,
+ * as agile_embbag_forward_prefetch does it (Sec. 4.3's asynchronous mode, here for a
+ * training step: the next step's forward then finds its lines resident; Listing 1's
+ * prefetch()).  The updates are exactly those of agile_embbag_backward_sgd.  The
+ * prefetch is unpinned and best effort: a line whose set has no evictable way is not
+ * fetched, and a prefetched line may be evicted again (a DIRTY victim is written back
+ * first).  Stream-ordered, one launch for the updates (its leading 64 wavefronts first
+ * prefetch, with at most a bounded number of commands in flight, then update rows);
+ * B_next == 0 is agile_embbag_backward_sgd; n == 0 only prefetches.  Uses the work area
+ * of agile_embbag_backward_sgd; errors as for it. */
+agile_status agile_embbag_backward_sgd_prefetch(agile_ctx ctx, agile_store store, const agile_tables* tb,
+                                                const int64_t* d_idx, const int64_t* d_off, uint64_t B,
+                                                uint64_t n, const float* d_grad, float lr,
+                                                const int64_t* d_next_idx, const int64_t* d_next_off,
+                                                uint64_t B_next, void* stream);
 
 /* The same backward pass for callers that cannot allocate device memory (code under HIP
  * graph capture, tight serving loops, harnesses that forbid hipMalloc): identical

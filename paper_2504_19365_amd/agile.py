@@ -123,6 +123,8 @@ def lib():
             "agile_debug_trace": (st, [vp, vp, vp, vp, u64, vp, vp, vp]),
             "agile_embbag_backward_sgd": (st, [vp, vp, C.POINTER(Tables), vp, vp, u64, u64, vp,
                                                C.c_float, vp]),
+            "agile_embbag_backward_sgd_prefetch": (st, [vp, vp, C.POINTER(Tables), vp, vp, u64,
+                                                        u64, vp, C.c_float, vp, vp, u64, vp]),
             "agile_debug_dump": (st, [vp, vp, vp, vp, vp]),
             "agile_debug_counters": (st, [vp, vp, u32]),
             "agile_probe_copy": (st, [vp, vp, u64, vp, u64, u32, u32, vp]),
@@ -463,6 +465,16 @@ class Context:
                                                     _ptr(off), B, idx.numel(), _ptr(grad), lr,
                                                     _stream(stream)),
                     "agile_embbag_backward_sgd")
+
+    def embbag_backward_sgd_prefetch(self, tb: Tables, idx, off, B: int, grad, lr: float, next_idx,
+                                     next_off, B_next: int, stream=None, store=None):
+        """The backward with SGD of this batch while the next batch's lines are prefetched."""
+        store = store or self.store
+        self._check(lib().agile_embbag_backward_sgd_prefetch(
+            self.h, store.handle, C.byref(tb), _ptr(idx), _ptr(off), B,
+            0 if idx is None else idx.numel(), _ptr(grad), lr,
+            _ptr(next_idx), _ptr(next_off), B_next, _stream(stream)),
+            "agile_embbag_backward_sgd_prefetch")
 
     def bfs(self, g: CSR, src: int, level, stream=None, store=None) -> int:
         store = store or self.store

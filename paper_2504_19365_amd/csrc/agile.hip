@@ -823,6 +823,8 @@ struct pf_args {
   const int64_t* off;  // its bag offsets [nbags + 1]
   uint64_t nbags;      // its bags; 0: nothing to prefetch
   uint64_t store_bytes;
+  uint64_t base_off, table_bytes;  // the tables (bag g is of table g mod T)
+  uint32_t row_bytes, T;
   uint64_t backlog;    // commands in flight (all queues) above which prefetching pauses
   uint32_t waves;      // user wavefronts that prefetch
   uint32_t interleave; // they prefetch and compute in turns (else prefetch, then compute)
@@ -876,8 +878,8 @@ __device__ __forceinline__ bool backlog_full(const dev_ctx& c, const pf_args& p)
 
 // Claims (unpinned) the lines of the next batch's lookups [j0, j0 + 64) that are neither
 // resident nor in flight, and submits their READs.  False on abort or time-out.
-__device__ __forceinline__ bool prefetch_chunk(const dev_ctx& c, const embbag_args& a, const pf_args& p,
-                                               uint32_t q, int64_t j0, int64_t j_hi) {
+__device__ __forceinline__ bool prefetch_chunk(const dev_ctx& c, const pf_args& p, uint32_t q, int64_t j0,
+                                               int64_t j_hi) {
   const uint64_t lmask = (1ull << c.line_shift) - 1;
   chunk_t ch;
   const int64_t j = j0 + lane();
@@ -887,7 +889,7 @@ __device__ __forceinline__ bool prefetch_chunk(const dev_ctx& c, const embbag_ar
   ch.off = 0;
   const uint64_t g = chunk_bags(p.off, p.nbags, j0, j);
   if (ch.act) {
-    const uint64_t byte = a.base_off + (g % a.T) * a.table_bytes + (uint64_t)p.idx[j] * a.row_bytes;
+    const uint64_t byte = p.base_off + (g % p.T) * p.table_bytes + (uint64_t)p.idx[j] * p.row_bytes;
     ch.act = byte < p.store_bytes;  // a hint: a row outside the store is not fetched
     ch.line_id = (uint32_t)(byte >> c.line_shift);
     ch.off = (uint32_t)(byte & lmask);
@@ -897,15 +899,14 @@ __device__ __forceinline__ bool prefetch_chunk(const dev_ctx& c, const embbag_ar
 
 // A dedicated prefetch wave's share: chunks w, w + P, ... of the next batch (P = p.waves),
 // each after the backlog is below its bound.
-__device__ __forceinline__ bool prefetch_wave(const dev_ctx& c, const embbag_args& a, const pf_args& p,
-                                              uint32_t w) {
+__device__ __forceinline__ bool prefetch_wave(const dev_ctx& c, const pf_args& p, uint32_t w) {
   const int64_t j_lo = p.off[0], j_hi = p.off[p.nbags];
   const uint32_t q = w % c.num_qp;
   for (int64_t j0 = j_lo + (int64_t)w * 64; j0 < j_hi; j0 += (int64_t)p.waves * 64) {
     spin_t sp;
     while (backlog_full(c, p))
       if (!sp.step(c, wi(W_BACKLOG, p.backlog))) return false;
-    if (!prefetch_chunk(c, a, p, q, j0, j_hi)) return false;
+    if (!prefetch_chunk(c, p, q, j0, j_hi)) return false;
   }
   return true;
 }
@@ -979,7 +980,7 @@ __device__ __forceinline__ void pf_interleaved(const dev_ctx& c, const embbag_ar
   bool comp = a.nbags > 0;
   while (pj < j_hi || comp) {
     while (pj < j_hi && !backlog_full(c, p)) {
-      if (!prefetch_chunk(c, a, p, q, pj, j_hi)) return;
+      if (!prefetch_chunk(c, p, q, pj, j_hi)) return;
       pj += (int64_t)p.waves * 64;
     }
     if (comp) {
@@ -1010,7 +1011,7 @@ __global__ __launch_bounds__(WG) void k_embbag_pf(dev_ctx c, launch_t li, embbag
       pf_interleaved<VPL>(c, a, p, uw, a.active_waves);
     } else {
       bool ok = true;
-      if (pfw) ok = prefetch_wave(c, a, p, uw);
+      if (pfw) ok = prefetch_wave(c, p, uw);
       uint32_t t = 0;
       if (ok && a.nbags)
         while (compute_bag<VPL>(c, a, uw, a.active_waves, t) > 0) {
@@ -1852,15 +1853,18 @@ __device__ __forceinline__ void bwd_wave(const dev_ctx& c, const bwd_args& a, ui
   }
 }
 
+// With a next batch (p.nbags), the first p.waves waves first prefetch its lines (the
+// next step's forward then finds them resident) and then join the others, which take
+// the distinct rows' groups from a counter meanwhile.
 template <int VPL>
-__global__ __launch_bounds__(WG) void k_bwd_sgd(dev_ctx c, launch_t li, bwd_args a) {
+__global__ __launch_bounds__(WG) void k_bwd_sgd(dev_ctx c, launch_t li, bwd_args a, pf_args p) {
   if (blockIdx.x < li.service_blocks) {
     run_service(c, li);
     return;
   }
   user_wave_begin();
   const uint32_t uw = (blockIdx.x - li.service_blocks) * WPB + threadIdx.x / 64;
-  bwd_wave<VPL>(c, a, uw);
+  if (!(uw < p.waves && p.nbags) || prefetch_wave(c, p, uw)) bwd_wave<VPL>(c, a, uw);
   user_wave_done(c, li);
 }
 
@@ -3175,6 +3179,10 @@ static agile_status embbag_launch(agile_ctx ctx, agile_store store, const agile_
     p.off = d_next_off;
     p.nbags = B_next * tb->num_tables;
     p.store_bytes = store->bytes;
+    p.base_off = tb->base_offset;
+    p.table_bytes = table_bytes;
+    p.row_bytes = (uint32_t)row_bytes;
+    p.T = tb->num_tables;
     // a few dedicated prefetch waves when the launch has many; every wave, in turns with
     // its compute, when it has few (a call that only prefetches: up to PF_WAVES waves)
     const bool few = a.nbags && cap <= 4 * PF_WAVES;
@@ -3554,7 +3562,9 @@ static agile_status spmv_run(agile_ctx ctx, const agile_csr* g, const float* d_x
 
 
 static agile_status bwd_launch(agile_ctx ctx, const agile_tables* tb, const int64_t* d_idx, const int64_t* d_off,
-                               uint64_t B, uint64_t n, const float* d_grad, float lr, void* work, hipStream_t hs);
+                               uint64_t B, uint64_t n, const float* d_grad, float lr, void* work, hipStream_t hs,
+                               const int64_t* d_next_idx = nullptr, const int64_t* d_next_off = nullptr,
+                               uint64_t B_next = 0);
 
 // Argument checks shared by both backward entry points (nothing is launched on failure).
 static agile_status bwd_check(agile_ctx ctx, agile_store store, const agile_tables* tb, const int64_t* d_idx,
@@ -3586,6 +3596,27 @@ agile_status agile_embbag_backward_sgd(agile_ctx ctx, agile_store store, const a
   return bwd_launch(ctx, tb, d_idx, d_off, B, n, d_grad, lr, ctx->scratch, hs);
 }
 
+agile_status agile_embbag_backward_sgd_prefetch(agile_ctx ctx, agile_store store, const agile_tables* tb,
+                                                const int64_t* d_idx, const int64_t* d_off, uint64_t B, uint64_t n,
+                                                const float* d_grad, float lr, const int64_t* d_next_idx,
+                                                const int64_t* d_next_off, uint64_t B_next, void* stream) {
+  agile_status s = check_usable(ctx);
+  if (s) return s;
+  if ((s = bwd_check(ctx, store, tb, d_idx, d_off, n, d_grad)) != AGILE_OK) return s;
+  if (B_next && !d_next_off) return fail(ctx, AGILE_EINVAL, "backward: null next-batch offsets");
+  if (ctx->cfg.flags & AGILE_F_SERIALIZED) B_next = 0;
+  hipStream_t hs = (hipStream_t)stream;
+  if (n == 0 || B == 0) {
+    // nothing to update: the prefetch alone, as agile_embbag_forward_prefetch does it
+    if (!B_next) return AGILE_OK;
+    return embbag_launch(ctx, store, tb, nullptr, nullptr, 0, 0, 0, AGILE_MODE_ASYNC, nullptr, stream, false,
+                         d_next_idx, d_next_off, B_next);
+  }
+  const size_t need = bwd_work_bytes(n);
+  if ((s = ensure_scratch(ctx, need, hs)) != AGILE_OK) return s;
+  return bwd_launch(ctx, tb, d_idx, d_off, B, n, d_grad, lr, ctx->scratch, hs, d_next_idx, d_next_off, B_next);
+}
+
 agile_status agile_embbag_backward_sgd_noalloc(agile_ctx ctx, agile_store store, const agile_tables* tb,
                                                const int64_t* d_idx, const int64_t* d_off, uint64_t B,
                                                uint64_t n, const float* d_grad, float lr, void* stream) {
@@ -3602,7 +3633,8 @@ agile_status agile_embbag_backward_sgd_noalloc(agile_ctx ctx, agile_store store,
 }
 
 static agile_status bwd_launch(agile_ctx ctx, const agile_tables* tb, const int64_t* d_idx, const int64_t* d_off,
-                               uint64_t B, uint64_t n, const float* d_grad, float lr, void* work, hipStream_t hs) {
+                               uint64_t B, uint64_t n, const float* d_grad, float lr, void* work, hipStream_t hs,
+                               const int64_t* d_next_idx, const int64_t* d_next_off, uint64_t B_next) {
   const uint64_t nbags = B * tb->num_tables;
   const uint64_t row_bytes = (uint64_t)tb->dim * 4;
   uint8_t* sb = (uint8_t*)work;
@@ -3642,12 +3674,29 @@ static agile_status bwd_launch(agile_ctx ctx, const agile_tables* tb, const int6
   uw = (uw + WPB - 1) / WPB * WPB;
   launch_t li = make_launch(ctx, uw, true);
   const dim3 grid(li.service_blocks + uw / WPB);
+  pf_args p{};
+  if (B_next) {
+    // the next batch's prefetch rides on this launch's leading waves (as in the forward's
+    // fused launch with many waves: a few prefetch, the rest never stop computing)
+    p.idx = d_next_idx;
+    p.off = d_next_off;
+    p.nbags = B_next * tb->num_tables;
+    p.store_bytes = ctx->store->bytes;
+    p.base_off = tb->base_offset;
+    p.table_bytes = tb->rows * row_bytes;
+    p.row_bytes = (uint32_t)row_bytes;
+    p.T = tb->num_tables;
+    p.waves = std::min<uint32_t>(PF_WAVES, uw);
+    const double little = (double)ctx->cfg.iops_cap * (double)ctx->cfg.latency_ns * 1e-9 * ctx->d.n_dev;
+    const uint64_t slots = (uint64_t)ctx->cfg.num_qp * ctx->cfg.qp_depth;
+    p.backlog = std::min<uint64_t>(slots, std::max<uint64_t>(2048, (uint64_t)(8.0 * little)));
+  }
   if (kind == KIND_BWD1)
-    hipLaunchKernelGGL(k_bwd_sgd<1>, grid, dim3(WG), lds_of(ctx, (const void*)k_bwd_sgd<1>), hs, ctx->d, li, a);
+    hipLaunchKernelGGL(k_bwd_sgd<1>, grid, dim3(WG), lds_of(ctx, (const void*)k_bwd_sgd<1>), hs, ctx->d, li, a, p);
   else if (kind == KIND_BWD2)
-    hipLaunchKernelGGL(k_bwd_sgd<2>, grid, dim3(WG), lds_of(ctx, (const void*)k_bwd_sgd<2>), hs, ctx->d, li, a);
+    hipLaunchKernelGGL(k_bwd_sgd<2>, grid, dim3(WG), lds_of(ctx, (const void*)k_bwd_sgd<2>), hs, ctx->d, li, a, p);
   else
-    hipLaunchKernelGGL(k_bwd_sgd<4>, grid, dim3(WG), lds_of(ctx, (const void*)k_bwd_sgd<4>), hs, ctx->d, li, a);
+    hipLaunchKernelGGL(k_bwd_sgd<4>, grid, dim3(WG), lds_of(ctx, (const void*)k_bwd_sgd<4>), hs, ctx->d, li, a, p);
   HIPCHK(ctx, hipGetLastError());
   return AGILE_OK;
 }

@@ -68,6 +68,51 @@ def test_backward_sgd_flush_equals_oracle(cache_kw):
         buf.free()
 
 
+@pytest.mark.parametrize("cache_kw", [dict(cache_bytes=64 << 20, assoc=16),
+                                      dict(cache_bytes=16 * 4096, assoc=4)])
+def test_training_steps_with_next_batch_prefetch_equal_oracle(cache_kw):
+    """Training steps (forward, then backward with SGD while the next batch is prefetched)
+    give, after the flush, the oracle's image bit for bit, as the plain backward does:
+    the prefetch claims and evicts (writing dirty victims back first) but never changes a
+    value.  With a cache holding the whole store, each step's forward then reads nothing
+    and the losses' outputs equal the oracle's forward on the updated tables."""
+    import torch
+    rows, dim, T, B, lr = 65536, 64, 4, 512, 0.01
+    buf = table_store(rows, dim, [20, 21, 22, 23])
+    ref = buf.array.copy()
+    ctx = agile.Context(line_bytes=4096, num_qp=4, qp_depth=256, timeout_ns=int(10e9),
+                        **cache_kw)
+    try:
+        ctx.open_store(buf)
+        tb = ctx.tables(rows, dim, T)
+        steps = 3
+        host = [_batch(rows, T, B, 40, 1.1, seed=130 + k) for k in range(steps + 1)]
+        dev = [(cuda(o), cuda(i)) for o, i in host]
+        out = torch.empty((B * T, dim), device="cuda")
+        big = cache_kw["cache_bytes"] >= (64 << 20)
+        for k in range(steps):
+            off, idx = host[k]
+            ctx.stats(reset=True)
+            ctx.embbag_forward(tb, dev[k][1], dev[k][0], B, 0, out)
+            ctx.sync()
+            if big and k > 0:
+                assert ctx.stats()["read_cmds"] == 0, k  # prefetched by the last backward
+            exp_f = oracle.embbag_forward(ref, rows, dim, T, idx, off, B, 0)
+            assert np.array_equal(out.cpu().numpy().view(np.uint32), exp_f.view(np.uint32)), k
+            g = gen.normal_f32(131 + k, B * T * dim).reshape(B * T, dim)
+            ctx.embbag_backward_sgd_prefetch(tb, dev[k][1], dev[k][0], B, cuda(g), lr,
+                                             dev[k + 1][1], dev[k + 1][0], B)
+            ctx.sync()
+            oracle.embbag_backward_sgd(ref, rows, dim, T, idx, off, B, g, lr)
+        ctx.flush()
+        check_quiescent_invariants(ctx, cache_kw["assoc"])
+        assert np.array_equal(buf.array.view(np.uint32), ref.view(np.uint32))
+    finally:
+        ctx.close_store()
+        ctx.shutdown()
+        buf.free()
+
+
 def test_finite_differences_on_small_table():
     """Central differences (eps = 1e-3) of L = sum g * pooled, evaluated with GPU
     forwards on a 256 x 8 table, against the gradient the GPU applied."""
