@@ -810,9 +810,11 @@ __global__ __launch_bounds__(64 * HIT_WAVES, 4) void k_embbag_hit(dev_ctx c, emb
 // One launch carries the service wavefronts, a few prefetch wavefronts and the compute
 // loop over the current batch.  The prefetch wavefronts walk the next batch's lookups 64
 // at a time and claim the lines that are neither resident nor in flight without pinning
-// them (a full set drops the request): they never wait for data, only for queue slots,
-// so the store is kept busy by them while every other wavefront computes.  Once their
-// share is submitted they join the compute loop.  The compute loop takes whole bags
+// them (a full set drops the request): they never wait for data, only for queue slots
+// and for the store's backlog to fall below its bound, so the store is kept busy by them
+// while every other wavefront computes.  Once their share is submitted they join the
+// compute loop (in a launch of few wavefronts every wave prefetches and computes in
+// turns; the backward's launch carries the same prefetch role).  The compute loop takes whole bags
 // from work counters and serves each from resident lines as the resident-hit pass does
 // (optimistic reads, checked after loading); where that stops (a line absent or in
 // flight, or a line that changed tenant), the same wavefront goes on with the rest of
