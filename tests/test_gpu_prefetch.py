@@ -214,3 +214,65 @@ def test_prefetch_finds_bags_across_runs_of_empty_bags():
         ctx.close_store()
         ctx.shutdown()
         buf.free()
+
+
+def test_prefetch_entry_points_edge_cases():
+    """Serialized contexts prefetch nothing and still compute the batch exactly; a next
+    batch without offsets is rejected before anything runs; the backward with no lookups
+    only prefetches (its batch is then resident)."""
+    import torch
+    rows, dim, T, B = 4096, 64, 2, 64
+    buf = table_store(rows, dim, [3, 5])
+    try:
+        off, idx = _batch(rows, T, B, 81)
+        off2, idx2 = _batch(rows, T, B, 82)
+        ref = oracle.embbag_forward(buf.array, rows, dim, T, idx, off, B, 0)
+        # serialized: one lane in program order, no prefetch
+        ctx = agile.Context(cache_bytes=4 << 20, line_bytes=4096, assoc=8, num_qp=1, qp_depth=64,
+                            timeout_ns=int(10e9), flags=agile.F_SERIALIZED)
+        try:
+            ctx.open_store(buf)
+            tb = ctx.tables(rows, dim, T)
+            out = torch.empty((B * T, dim), device="cuda")
+            ctx.embbag_forward_prefetch(tb, cuda(idx), cuda(off), B, 0, out, cuda(idx2), cuda(off2), B)
+            ctx.sync()
+            assert np.array_equal(out.cpu().numpy().view(np.uint32), ref.view(np.uint32))
+            st = ctx.stats()
+            assert st["read_cmds"] == _lines(off, idx, T, rows, dim).size  # this batch's only
+        finally:
+            ctx.close_store()
+            ctx.shutdown()
+        ctx = agile.Context(cache_bytes=4 << 20, line_bytes=4096, assoc=8, num_qp=2, qp_depth=128,
+                            timeout_ns=int(10e9))
+        try:
+            ctx.open_store(buf)
+            tb = ctx.tables(rows, dim, T)
+            out = torch.empty((B * T, dim), device="cuda")
+            with pytest.raises(agile.AgileError) as e:
+                ctx.embbag_forward_prefetch(tb, cuda(idx), cuda(off), B, 0, out, cuda(idx2), None, B)
+            assert e.value.status == agile.EINVAL
+            with pytest.raises(agile.AgileError) as e:
+                ctx.embbag_backward_sgd_prefetch(tb, cuda(idx), cuda(off), B,
+                                                 torch.zeros((B * T, dim), device="cuda"), 0.01,
+                                                 cuda(idx2), None, B)
+            assert e.value.status == agile.EINVAL
+            # no lookups to update: the call only prefetches the next batch
+            ctx.stats(reset=True)
+            empty_off = torch.zeros(B * T + 1, dtype=torch.int64, device="cuda")
+            ctx.embbag_backward_sgd_prefetch(tb, torch.empty(0, dtype=torch.int64, device="cuda"),
+                                             empty_off, B, torch.zeros((B * T, dim), device="cuda"),
+                                             0.01, cuda(idx2), cuda(off2), B)
+            ctx.sync()
+            assert ctx.stats()["read_cmds"] == _lines(off2, idx2, T, rows, dim).size
+            ctx.stats(reset=True)
+            ctx.embbag_forward(tb, cuda(idx2), cuda(off2), B, 0, out, mode=agile.MODE_SYNC)
+            ctx.sync()
+            assert ctx.stats()["read_cmds"] == 0
+            ref2 = oracle.embbag_forward(buf.array, rows, dim, T, idx2, off2, B, 0)
+            assert np.array_equal(out.cpu().numpy().view(np.uint32), ref2.view(np.uint32))
+            check_quiescent_invariants(ctx, 8)
+        finally:
+            ctx.close_store()
+            ctx.shutdown()
+    finally:
+        buf.free()
