@@ -199,6 +199,43 @@ def test_autograd_function_matches_direct_calls():
         buf.free()
 
 
+def test_autograd_steps_with_next_batch_prefetch():
+    """Training steps through the autograd module, each backward given the next step's
+    batch: the next forward reads nothing (a cache holding the whole store), every pooled
+    output and the flushed image equal the oracle's."""
+    import torch
+    from paper_2504_19365_amd.autograd import EmbeddingBag
+    rows, dim, T, B, lr = 16384, 64, 2, 128, 0.01
+    buf = table_store(rows, dim, [5, 6])
+    ref = buf.array.copy()
+    ctx = agile.Context(cache_bytes=8 << 20, line_bytes=4096, assoc=16, num_qp=2, qp_depth=128,
+                        timeout_ns=int(5e9))
+    try:
+        ctx.open_store(buf)
+        emb = EmbeddingBag(ctx, rows, dim, T, lr)
+        host = [_batch(rows, T, B, 40, 1.1, seed=17 + k) for k in range(4)]
+        dev = [(cuda(i), cuda(o)) for o, i in host]
+        for k in range(3):
+            off, idx = host[k]
+            ctx.stats(reset=True)
+            pooled = emb(dev[k][0], dev[k][1], B, next_batch=(dev[k + 1][0], dev[k + 1][1], B))
+            ctx.sync()
+            if k:
+                assert ctx.stats()["read_cmds"] == 0, k
+            exp = oracle.embbag_forward(ref, rows, dim, T, idx, off, B, 0)
+            assert np.array_equal(pooled.detach().cpu().numpy(), exp), k
+            g = gen.normal_f32(18 + k, B * T * dim).reshape(B * T, dim)
+            (pooled * cuda(g)).sum().backward()
+            ctx.sync()
+            oracle.embbag_backward_sgd(ref, rows, dim, T, idx, off, B, g, lr)
+        ctx.flush()
+        assert np.array_equal(buf.array.view(np.uint32), ref.view(np.uint32))
+    finally:
+        ctx.close_store()
+        ctx.shutdown()
+        buf.free()
+
+
 def test_backward_rejects_lookup_counts_past_32_bits():
     """The backward pass sorts lookup positions in 32 bits: a count of 2^32 or more is
     rejected with AGILE_EINVAL before anything is launched, and the context stays
