@@ -79,10 +79,11 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--profile-only", nargs="?", const="step", default=None,
-                    choices=("step", "step_async", "hit", "bwd", "randread", "devices", "graph"),
+                    choices=("step", "step_async", "step_sync", "hit", "bwd", "randread",
+                             "devices", "graph"),
                     help="for profilers: 'step' runs the warm-up and timed steps only "
-                         "('step_async': the same in the asynchronous mode without the "
-                         "next-batch prefetch), 'hit' "
+                         "('step_async' / 'step_sync': the same in the asynchronous mode "
+                         "without the next-batch prefetch / the synchronous mode), 'hit' "
                          "the hit-path replay only, 'bwd' / 'randread' / 'devices' / 'graph' that "
                          "measurement only")
     ap.add_argument("--extras", default="sens,serve,randread,devices,bwd,graph",
@@ -757,11 +758,14 @@ def main():
         st["lookups"] = sum(batches[i][2] for i in ids)
         return ms, st
 
-    step_mode = PREFETCH if args.profile_only != "step_async" else agile.MODE_ASYNC
+    step_mode = {"step_async": agile.MODE_ASYNC, "step_sync": agile.MODE_SYNC}.get(args.profile_only,
+                                                                                  PREFETCH)
     ms_step_l, st_step = timed(step_mode)
     out_step = [outs[i].clone() for i in timed_ids[-2:]]
     reads, hits, misses = st_step["read_cmds"], st_step["hits"], st_step["misses"]
-    log(f"async + next-batch prefetch: {np.mean(ms_step_l):.2f} ms/step, reads {reads}, "
+    step_name = {PREFETCH: "async + next-batch prefetch", agile.MODE_ASYNC: "async",
+                 agile.MODE_SYNC: "sync"}[step_mode]
+    log(f"{step_name}: {np.mean(ms_step_l):.2f} ms/step, reads {reads}, "
         f"hits {hits}, demand misses {misses}")
     if args.profile_only:
         print(json.dumps({"profile_only": args.profile_only,
